@@ -1,0 +1,267 @@
+"""Seeded synthetic initial states for the hydro step.
+
+Everything here is input generation only: coordinates, closed-form flow
+profiles and random hotspot / parton placements.  None of the solver's
+arithmetic (fluxes, sources, root solve, EoS lookup) lives here.  Both the CPU
+oracle and the HIP library receive the arrays produced by these functions.
+
+Conventions
+-----------
+Arrays have shape (nx, ny, ne) in C order (x slowest, eta_s fastest).  Cell
+centres sit at x_i = (i - (nx-1)/2) dx, likewise for y and eta_s.  Velocities
+are the tilde components u~ = (u^x, u^y, tau u^eta) of Sec. II; u~^tau follows
+from normalisation.  pi~ components are ordered
+(tautau, taux, tauy, taueta, xx, xy, xeta, yy, yeta, etaeta).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from .eos import C_SB
+
+PI_NAMES = ("tt", "tx", "ty", "te", "xx", "xy", "xe", "yy", "ye", "ee")
+
+
+@dataclass(frozen=True)
+class Grid:
+    nx: int
+    ny: int
+    ne: int
+    dx: float
+    dy: float
+    de: float
+
+    @property
+    def shape(self):
+        return (self.nx, self.ny, self.ne)
+
+    @property
+    def ncell(self) -> int:
+        return self.nx * self.ny * self.ne
+
+    def axes(self):
+        x = (np.arange(self.nx) - (self.nx - 1) / 2.0) * self.dx
+        y = (np.arange(self.ny) - (self.ny - 1) / 2.0) * self.dy
+        e = (np.arange(self.ne) - (self.ne - 1) / 2.0) * self.de
+        return x, y, e
+
+    def mesh(self):
+        x, y, e = self.axes()
+        return np.meshgrid(x, y, e, indexing="ij")
+
+
+def _zeros(g: Grid):
+    return np.zeros(g.shape, dtype=np.float64)
+
+
+def empty_pi(g: Grid) -> np.ndarray:
+    return np.zeros((10,) + g.shape, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# Gubser flow (ideal limit), Sec. V.C: boost invariant, conformal EoS.
+# --------------------------------------------------------------------------
+def gubser_profile(x, y, tau, q=1.0, eps_peak_tau1=None, eps_hat=None):
+    """Ideal Gubser flow at proper time tau (q = 1/L in fm^-1).
+
+    eps = eps_hat (2q)^(8/3) / (tau^(4/3) [1 + 2 q^2 (tau^2 + r^2) + q^4 (tau^2 - r^2)^2]^(4/3)),
+    v_r = 2 q^2 tau r / (1 + q^2 tau^2 + q^2 r^2)   (outward).
+    ``eps_peak_tau1`` fixes eps_hat through eps(tau = 1/q, r = 0) = eps_hat q^(4/3).
+    Returns (eps, u~x, u~y).
+    """
+    if eps_hat is None:
+        eps_hat = eps_peak_tau1 / q ** (4.0 / 3.0)
+    r2 = x * x + y * y
+    den = 1.0 + 2.0 * q * q * (tau * tau + r2) + q ** 4 * (tau * tau - r2) ** 2
+    eps = eps_hat * (2.0 * q) ** (8.0 / 3.0) / (tau ** (4.0 / 3.0) * den ** (4.0 / 3.0))
+    a = 2.0 * q * q * tau / (1.0 + q * q * tau * tau + q * q * r2)  # v_r / r
+    vx, vy = a * x, a * y
+    ut = 1.0 / np.sqrt(1.0 - vx * vx - vy * vy)
+    return eps, ut * vx, ut * vy
+
+
+def gubser_ideal(g: Grid, tau: float, q: float = 1.0, T_peak: float = 0.4):
+    """Gubser IC on grid g at proper time tau; peak T at tau = 1/q, r = 0 (conformal EoS)."""
+    eps_peak = C_SB * T_peak ** 4
+    X, Y, _ = g.mesh()
+    eps, ux, uy = gubser_profile(X, Y, tau, q=q, eps_peak_tau1=eps_peak)
+    return dict(eps=eps, ux=ux, uy=uy, ue=_zeros(g))
+
+
+# --------------------------------------------------------------------------
+# Bjorken flow, Sec. V.B: uniform in (x, y, eta_s), u~ = (1, 0, 0, 0).
+# --------------------------------------------------------------------------
+def bjorken(g: Grid, eps0: float, phi0: float = 0.0):
+    """Uniform state; phi0 = -pi~^{etaeta} = 2 pi~^{xx} = 2 pi~^{yy} (traceless, transverse)."""
+    pi = empty_pi(g)
+    pi[4] = 0.5 * phi0
+    pi[7] = 0.5 * phi0
+    pi[9] = -phi0
+    return dict(eps=np.full(g.shape, eps0), ux=_zeros(g), uy=_zeros(g), ue=_zeros(g), pi=pi)
+
+
+# --------------------------------------------------------------------------
+# Riemann problem, Sec. V.A (Cartesian coordinates, step in one direction).
+# --------------------------------------------------------------------------
+def riemann(nx: int, dx: float, eps0: float):
+    """1D step along x: eps0 where x <= 0, vacuum where x > 0 (grid ny = ne = 1)."""
+    g = Grid(nx, 1, 1, dx, 1.0, 1.0)
+    X, _, _ = g.mesh()
+    eps = np.where(X <= 0.0, eps0, 0.0)
+    return g, dict(eps=eps, ux=_zeros(g), uy=_zeros(g), ue=_zeros(g))
+
+
+# --------------------------------------------------------------------------
+# Static relaxing fluid seen in Milne coordinates (exact solution built here).
+# --------------------------------------------------------------------------
+def static_milne(g: Grid, tau: float, eps0: float, amp):
+    """A fluid at rest in Cartesian coordinates with pi^zz = a, pi^xx = pi^yy = -a/2.
+
+    In Milne coordinates u~ = (cosh eta, 0, 0, -sinh eta) and
+    pi~^tautau = a sinh^2, pi~^taueta = -a sinh cosh, pi~^etaeta = a cosh^2,
+    pi~^xx = pi~^yy = -a/2.  ``amp`` is a(eta) on the grid's eta axis (the
+    caller evaluates a at t = tau cosh eta).
+    """
+    _, _, E = g.mesh()
+    a = np.broadcast_to(np.asarray(amp, dtype=np.float64)[None, None, :], g.shape)
+    sh, ch = np.sinh(E), np.cosh(E)
+    pi = empty_pi(g)
+    pi[0] = a * sh * sh
+    pi[3] = -a * sh * ch
+    pi[9] = a * ch * ch
+    pi[4] = -0.5 * a
+    pi[7] = -0.5 * a
+    return dict(eps=np.full(g.shape, eps0), ux=_zeros(g), uy=_zeros(g), ue=-sh, pi=pi)
+
+
+# --------------------------------------------------------------------------
+# Advected decaying shear mode (Cartesian, exact solution built here).
+# --------------------------------------------------------------------------
+def advected_pi(nx: int, dx: float, eps0: float, vx: float, amp: float, width: float,
+                x0: float = 0.0):
+    """Uniform eps and v_x; pi~^{y eta}(x) = amp exp(-(x-x0)^2/(2 width^2)).
+
+    pi^{y eta} is transverse to u = gamma(1, v, 0, 0) and traceless, and it
+    does not enter T^{tau mu} or the x-flux of T, so the fluid stays uniform.
+    """
+    g = Grid(nx, 1, 1, dx, 1.0, 1.0)
+    X, _, _ = g.mesh()
+    gam = 1.0 / math.sqrt(1.0 - vx * vx)
+    pi = empty_pi(g)
+    pi[8] = amp * np.exp(-(X - x0) ** 2 / (2.0 * width * width))
+    return g, dict(eps=np.full(g.shape, eps0), ux=np.full(g.shape, gam * vx), uy=_zeros(g),
+                   ue=_zeros(g), pi=pi)
+
+
+# --------------------------------------------------------------------------
+# Fluctuating heavy-ion-like initial state: Gaussian hotspots.
+# --------------------------------------------------------------------------
+def _woods_saxon_xy(rng, n, R=6.5, a=0.5):
+    """n points in the plane with density proportional to 1/(1+exp((r-R)/a))."""
+    out = []
+    rmax = R + 10.0 * a
+    while len(out) < n:
+        r = rmax * np.sqrt(rng.random(4 * n))           # uniform in the disk of radius rmax
+        acc = rng.random(4 * n) < 1.0 / (1.0 + np.exp((r - R) / a))
+        phi = 2.0 * math.pi * rng.random(4 * n)
+        for rr, pp in zip(r[acc], phi[acc]):
+            out.append((rr * math.cos(pp), rr * math.sin(pp)))
+            if len(out) == n:
+                break
+    return np.array(out)
+
+
+def eta_envelope(e, eta_flat=2.0, sigma_eta=1.3):
+    """Plateau |eta_s| < eta_flat with Gaussian tails (the form of Table I's H(eta_s))."""
+    d = np.maximum(np.abs(e) - eta_flat, 0.0)
+    return np.exp(-d * d / (2.0 * sigma_eta * sigma_eta))
+
+
+def hotspots(g: Grid, seed: int, n_spots: int = 200, sigma: float = 0.5, R: float = 6.5,
+             a_ws: float = 0.5, eta_flat: float = 2.0, sigma_eta: float = 1.3,
+             eps_max: float = 55.0):
+    """Sum of n_spots Gaussian hotspots (width sigma, Gamma(k=1) weights) placed by a
+    2D Woods-Saxon disk, times an eta_s plateau envelope, scaled to max eps = eps_max.
+    Zero initial flow, zero pi."""
+    rng = np.random.default_rng(seed)
+    xy = _woods_saxon_xy(rng, n_spots, R=R, a=a_ws)
+    w = rng.gamma(1.0, 1.0, n_spots)
+    x, y, e = g.axes()
+    prof = np.zeros((g.nx, g.ny))
+    for (cx, cy), wk in zip(xy, w):
+        gx = np.exp(-(x - cx) ** 2 / (2.0 * sigma * sigma))
+        gy = np.exp(-(y - cy) ** 2 / (2.0 * sigma * sigma))
+        prof += wk * np.outer(gx, gy)
+    H = eta_envelope(e, eta_flat, sigma_eta) if g.ne > 1 else np.ones(1)
+    eps = prof[:, :, None] * H[None, None, :]
+    eps *= eps_max / eps.max()
+    return dict(eps=eps, ux=_zeros(g), uy=_zeros(g), ue=_zeros(g))
+
+
+def minijet_deposit(g: Grid, seed: int, n_jets: int = 400, mean_pt: float = 2.0,
+                    sigma_r: float = 0.5, sigma_eta: float = 0.5, R: float = 6.5,
+                    a_ws: float = 0.5, eta_range: float = 2.0):
+    """Energy-momentum of n_jets massless partons spread over the grid.
+
+    Parton k: p_T ~ Exp(mean_pt), phi ~ U[0, 2pi), (x, y) from the Woods-Saxon
+    disk, eta_k ~ U(-eta_range, eta_range), rapidity y = eta_k.  At a cell with
+    space-time rapidity eta its tilde momentum is
+    p_T (cosh(y - eta), cos phi, sin phi, sinh(y - eta)); it is spread with a
+    Gaussian in (r, eta_s) normalised so that sum_cells dT~ dx dy deta = p~.
+    Returns dT~^{tau mu} with shape (4, nx, ny, ne) in GeV/fm^2.
+    """
+    rng = np.random.default_rng(seed)
+    xy = _woods_saxon_xy(rng, n_jets, R=R, a=a_ws)
+    pt = rng.exponential(mean_pt, n_jets)
+    phi = 2.0 * math.pi * rng.random(n_jets)
+    etak = rng.uniform(-eta_range, eta_range, n_jets) if g.ne > 1 else np.zeros(n_jets)
+    x, y, e = g.axes()
+    out = np.zeros((4,) + g.shape)
+    vol = g.dx * g.dy * g.de
+    for k in range(n_jets):
+        gx = np.exp(-(x - xy[k, 0]) ** 2 / (2.0 * sigma_r ** 2))
+        gy = np.exp(-(y - xy[k, 1]) ** 2 / (2.0 * sigma_r ** 2))
+        ge = np.exp(-(e - etak[k]) ** 2 / (2.0 * sigma_eta ** 2)) if g.ne > 1 else np.ones(1)
+        G = gx[:, None, None] * gy[None, :, None] * ge[None, None, :]
+        norm = G.sum() * vol
+        if norm <= 0.0:
+            continue
+        G /= norm
+        dy_ = etak[k] - e
+        out[0] += pt[k] * G * np.cosh(dy_)[None, None, :]
+        out[1] += pt[k] * math.cos(phi[k]) * G
+        out[2] += pt[k] * math.sin(phi[k]) * G
+        out[3] += pt[k] * G * np.sinh(dy_)[None, None, :]
+    return out
+
+
+def hotspots_with_minijets(g: Grid, tau0: float, seed: int, **kw):
+    """Conserved initial state T~^{tau mu} = tau0 (eps, 0, 0, 0) + parton deposits.
+
+    For a fluid at rest T^{tau tau} = eps and T^{tau i} = 0, so no EoS is needed
+    to build the conserved variables; the root solve recovers (eps, u~).
+    """
+    prim = hotspots(g, seed, **kw)
+    dT = minijet_deposit(g, seed + 7919)
+    T = dT.copy()
+    T[0] += tau0 * prim["eps"]
+    return T
+
+
+# --------------------------------------------------------------------------
+# Random cell states for root-solve tests.
+# --------------------------------------------------------------------------
+def random_states(n: int, seed: int, eps_lo: float = 1e-6, eps_hi: float = 1e3,
+                  vmax: float = 0.9999):
+    """eps log-uniform in [eps_lo, eps_hi]; velocity isotropic with |v| uniform in [0, vmax].
+    Returns (eps, u~[n, 3])."""
+    rng = np.random.default_rng(seed)
+    eps = np.exp(rng.uniform(math.log(eps_lo), math.log(eps_hi), n))
+    v = vmax * rng.random(n)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    gam = 1.0 / np.sqrt(1.0 - v * v)
+    return eps, (gam * v)[:, None] * d

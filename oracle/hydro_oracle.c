@@ -1,0 +1,1123 @@
+/*
+ * hydro_oracle.c -- TEST INFRASTRUCTURE: plain, slow, FP64 CPU oracle for one
+ * RK2 step of the Kurganov-Tadmor scheme for (3+1)D viscous hydrodynamics in
+ * Milne coordinates (CLVisc, arXiv:1802.04449, Secs. II and III).
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  The product path (the HIP library under
+ * paper_1802_04449_amd/) never calls it, and the two share no source.
+ *
+ * Written for readability against the paper: every cell is handled by plain
+ * loops in double precision, with explicit ghost layers, and no blocking or
+ * fusion beyond what the scheme itself prescribes.  Build with
+ * -O2 -ffp-contract=off (no FMA contraction, no fast-math).  OpenMP, when
+ * enabled, only splits independent cells or grid lines; every reduction is
+ * done serially afterwards, so results do not depend on the thread count.
+ *
+ * Notation (Sec. II, tilde variables): u~ = (u^tau, u^x, u^y, tau u^eta),
+ * g~ = diag(1,-1,-1,-1), d~ = (d_tau, d_x, d_y, d_eta / tau).  With
+ *   Tc^{mu nu} = (e + P) u~^mu u~^nu - P g~^{mu nu} + pi~^{mu nu}
+ * the paper's T~^{mu nu} equals tau Tc^{mu nu}.  pi~ components are stored in
+ * the order (tt, tx, ty, te, xx, xy, xe, yy, ye, ee).
+ *
+ * Readings taken where the printed equations are ambiguous (each is pinned by
+ * a closed-form test in tests/):
+ *  - geometric source of T: S_T = (-Tc^{ee}, 0, 0, -Tc^{te}) (from
+ *    nabla_mu T^{mu nu} = 0 with the Christoffel symbols of Sec. II);
+ *  - in S_pi the u~^tau/tau term and the Christoffel term I^{mu nu} enter with
+ *    a minus sign (from writing the IS equation in flux form);
+ *  - reconstruction acts on the primitive fields (e, u~^x, u~^y, u~^eta, pi~)
+ *    with a generalised minmod limiter of parameter theta;
+ *  - the local speed c_{i+1/2} is the largest |eigenvalue| of the ideal flux
+ *    Jacobian along the face normal, over the left and right states;
+ *  - the time derivative of u~ inside S_pi is the difference of the two time
+ *    levels the stage spans, divided by h;
+ *  - the first step estimates u*1 by one ideal forward-Euler step and sets
+ *    u~^{-1} = 2 u~^0 - u*1;
+ *  - cells whose T^{tau tau}-part falls below the cutoff become vacuum
+ *    (e = 0, u~ = 0, and pi~ = 0 at the end of the step).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define HBARC 0.1973269804
+
+/* Planted-mistake switch for the pin tests' own check (0 = the oracle as
+ * written).  A nonzero value deliberately breaks one term, so the tests can
+ * show that some pin notices; it is never set outside that test. */
+static int orc_mutant = 0;
+#define MUT(k) (orc_mutant == (k))
+void orc_set_mutant(int k) { orc_mutant = k; }
+#define NG 2 /* ghost layers per face: the KT stencil reaches i-2 .. i+2 */
+
+/* ------------------------------------------------------------------------ */
+typedef struct orc_params {
+    int nx, ny, ne;
+    double dx, dy, de;
+    double tau0, h, etas;
+    int viscous;   /* 1: evolve the 10 pi~ components (Israel-Stewart) */
+    int cartesian; /* 1: tau == 1 in every metric factor, no Milne sources */
+    double eps_cut, theta, newton_tol;
+    int newton_maxit;
+    double pi_reg; /* cap on sqrt(|pi:pi|)/(e+P); <= 0 disables the regulator */
+} orc_params;
+
+typedef struct orc_diag {
+    double tau;
+    long step;
+    double eps_max;      /* max e over interior cells after the last step     */
+    double sum_Ttt;      /* sum T~^{tau tau} dx dy deta after the last step    */
+    double geo_src;      /* accumulated sum h/2 (S_T1 + S_T2)^tau dx dy deta   */
+    double max_cfl;      /* max over faces and stages of c h / Delta_d         */
+    double newton_mean;  /* mean iterations per root solve (incl. polish)      */
+    long newton_max;
+    long solves, fallbacks, nonconv, nans, vacuum, clamps;
+} orc_diag;
+
+typedef struct orc_eos {
+    int kind; /* 0 conformal (P = e/3), 1 uniform table */
+    double c_sb;
+    double e0, de;
+    int n;
+    double *P, *T, *cs2;
+} orc_eos;
+
+typedef struct orc {
+    orc_params p;
+    orc_eos eos;
+    int NX, NY, NE;       /* padded dims */
+    long ncell, npad;
+    double tau;
+    long step;
+    /* state n (padded) */
+    double *e, *u[3], *pi[10], *T[4], *uprev[3];
+    /* stage-1 prediction, stage results */
+    double *e1, *u1[3], *pi1[10], *T1[4];
+    double *RT1[4], *Rpi1[10], *RT2[4], *Rpi2[10];
+    double *piN[10], *zero;
+    /* per-cell root-solve bookkeeping */
+    int *it_cell, *flag_cell;
+    orc_diag d;
+    long sum_iters;
+} orc;
+
+enum { C2P_FALLBACK = 1, C2P_NONCONV = 2, C2P_NAN = 4, C2P_VAC = 8, C2P_CLAMP = 16 };
+
+/* Index of padded cell (i, j, k) with i in [-NG, nx+NG). */
+static inline long IDX(const orc *S, int i, int j, int k) {
+    return ((long)(i + NG) * S->NY + (j + NG)) * S->NE + (k + NG);
+}
+
+/* pi~ component index of the symmetric pair (mu, nu). */
+static int SYM(int mu, int nu) {
+    static const int t[4][4] = {{0, 1, 2, 3}, {1, 4, 5, 6}, {2, 5, 7, 8}, {3, 6, 8, 9}};
+    return t[mu][nu];
+}
+
+static const double GT[4] = {1.0, -1.0, -1.0, -1.0}; /* g~ = diag(1,-1,-1,-1) */
+
+/* ------------------------------------------------------------------------ */
+/* EoS lookup (Sec. III, EoS options): P, T, cs2 and the segment slope dP/de.
+ * Table: linear interpolation on a uniform e grid; beyond the last node P is
+ * continued with the last segment's slope, cs2 is held, and T follows
+ * T_last ((e+P)/(e_last+P_last))^(1/4).  Negative e is treated as 0. */
+static void eos_eval(const orc_eos *q, double e, double *P, double *T, double *cs2,
+                     double *dPde) {
+    if (!(e > 0.0)) e = 0.0;
+    if (q->kind == 0) {
+        *P = e / 3.0;
+        *cs2 = 1.0 / 3.0;
+        *dPde = 1.0 / 3.0;
+        *T = pow(e / q->c_sb, 0.25);
+        return;
+    }
+    int n = q->n;
+    double x = (e - q->e0) / q->de;
+    if (x < 0.0) x = 0.0;
+    double slope_last = (q->P[n - 1] - q->P[n - 2]) / q->de;
+    if (x >= (double)(n - 1)) {
+        double elast = q->e0 + (n - 1) * q->de;
+        double p = q->P[n - 1] + (e - elast) * slope_last;
+        *P = p;
+        *cs2 = q->cs2[n - 1];
+        *dPde = slope_last;
+        *T = q->T[n - 1] * pow((e + p) / (elast + q->P[n - 1]), 0.25);
+        return;
+    }
+    int i = (int)floor(x);
+    if (i > n - 2) i = n - 2;
+    double f = x - i;
+    *P = q->P[i] + f * (q->P[i + 1] - q->P[i]);
+    *T = MUT(12) ? q->T[i + 1] + f * (q->T[i + 1] - q->T[i]) : q->T[i] + f * (q->T[i + 1] - q->T[i]);
+    *cs2 = q->cs2[i] + f * (q->cs2[i + 1] - q->cs2[i]);
+    *dPde = (q->P[i + 1] - q->P[i]) / q->de;
+}
+
+static double eos_P(const orc_eos *q, double e) {
+    double P, T, c, d;
+    eos_eval(q, e, &P, &T, &c, &d);
+    return P;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Root solve T_ideal -> (e, u~) (Sec. III, RK2 flow chart; App. A.3 notes the
+ * variable iteration count).  K^mu = T~^{tau mu}/tau - pi~^{tau mu} equals
+ * (e+P) u~^tau u~^mu - P g~^{tau mu}; with E = K^tau, M = |K|,
+ * e solves f(e) = e - E + M^2/(E + P(e)) = 0 on [max(0, E - M^2/E), E], where
+ * f is increasing.  Safeguarded Newton (bisection when a step leaves the
+ * bracket), stop at |de| <= tol e, then one extra Newton step so the result
+ * does not depend on the starting guess. */
+static void con2prim(const orc *S, const double Kin[4], double guess, double *e_out,
+                     double u_out[3], int *iters, int *flags) {
+    const orc_eos *q = &S->eos;
+    double E = Kin[0], K1 = Kin[1], K2 = Kin[2], K3 = Kin[3];
+    *iters = 0;
+    *flags = 0;
+    if (isnan(E) || isnan(K1) || isnan(K2) || isnan(K3)) {
+        *flags |= C2P_NAN | C2P_VAC;
+        *e_out = 0.0;
+        u_out[0] = u_out[1] = u_out[2] = 0.0;
+        return;
+    }
+    if (!(E >= S->p.eps_cut)) { /* energy-density cutoff, Sec. V.A */
+        *flags |= C2P_VAC;
+        *e_out = 0.0;
+        u_out[0] = u_out[1] = u_out[2] = 0.0;
+        return;
+    }
+    double M2 = K1 * K1 + K2 * K2 + K3 * K3;
+    double M = sqrt(M2);
+    double Mmax = (1.0 - 1e-10) * E;
+    if (M > Mmax) {
+        double s = Mmax / M;
+        K1 *= s;
+        K2 *= s;
+        K3 *= s;
+        M2 = K1 * K1 + K2 * K2 + K3 * K3;
+        *flags |= C2P_CLAMP;
+    }
+    double lo = E - M2 / E;
+    if (lo < 0.0) lo = 0.0;
+    double hi = E;
+    const double lo0 = lo, hi0 = hi;
+    double x = guess;
+    if (!(x >= lo)) x = lo;
+    if (x > hi) x = hi;
+    int conv = 0, it;
+    for (it = 1; it <= S->p.newton_maxit; ++it) {
+        if (hi < S->p.eps_cut) { /* the root lies below the cutoff: vacuum */
+            *iters = it;
+            *flags |= C2P_VAC;
+            *e_out = 0.0;
+            u_out[0] = u_out[1] = u_out[2] = 0.0;
+            return;
+        }
+        double P, T, c, dP;
+        eos_eval(q, x, &P, &T, &c, &dP);
+        double f = x - E + M2 / (E + P);
+        double df = 1.0 - M2 * dP / ((E + P) * (E + P));
+        if (f == 0.0) {
+            conv = 1;
+            break;
+        }
+        if (f > 0.0)
+            hi = x;
+        else
+            lo = x;
+        double xn = x - f / df;
+        if (!(xn >= lo && xn <= hi)) {
+            xn = 0.5 * (lo + hi);
+            *flags |= C2P_FALLBACK;
+        }
+        double step = fabs(xn - x);
+        x = xn;
+        if (step <= S->p.newton_tol * x) {
+            conv = 1;
+            break;
+        }
+    }
+    if (!conv) {
+        *flags |= C2P_NONCONV;
+        it = S->p.newton_maxit;
+    }
+    {   /* polish */
+        double P, T, c, dP;
+        eos_eval(q, x, &P, &T, &c, &dP);
+        double f = x - E + M2 / (E + P);
+        double df = 1.0 - M2 * dP / ((E + P) * (E + P));
+        double xp = x - f / df;
+        if (xp >= lo0 && xp <= hi0) x = xp;
+    }
+    *iters = it + 1;
+    if (!(x >= S->p.eps_cut)) { /* the cutoff acts on the rest-frame energy density */
+        *flags |= C2P_VAC;
+        *e_out = 0.0;
+        u_out[0] = u_out[1] = u_out[2] = 0.0;
+        return;
+    }
+    double P = eos_P(q, x);
+    /* 1 - v^2 = (e+P)/(E+P), v = K/(E+P) */
+    double ut = sqrt((E + P) / (x + P));
+    double den = MUT(11) ? sqrt(E * (x + P)) : sqrt((E + P) * (x + P));
+    *e_out = x;
+    u_out[0] = K1 / den;
+    u_out[1] = K2 / den;
+    u_out[2] = K3 / den;
+    (void)ut;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Generalised minmod slope (Sec. III, piecewise-linear reconstruction). */
+static double minmod3(double a, double b, double c) {
+    if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+    if (a < 0.0 && b < 0.0 && c < 0.0) return fmax(a, fmax(b, c));
+    return 0.0;
+}
+
+static double limited_slope(double theta, double qm, double q0, double qp) {
+    return minmod3(theta * (q0 - qm), 0.5 * (qp - qm), theta * (qp - q0));
+}
+
+/* Largest |eigenvalue| of the ideal flux Jacobian along axis d (1..3) for a
+ * state with velocity v = u~/u~^tau and sound speed cs:
+ * lambda = [v_d (1-cs2) +- cs sqrt((1-v2)(1 - v2 cs2 - v_d^2 (1-cs2)))]/(1 - v2 cs2). */
+static double local_speed(const double uc[4], int d, double cs2) {
+    double inv = 1.0 / uc[0];
+    double vd = uc[d] * inv;
+    double v2 = (uc[1] * uc[1] + uc[2] * uc[2] + uc[3] * uc[3]) * inv * inv;
+    double omv2 = inv * inv;
+    double disc = omv2 * (1.0 - v2 * cs2 - vd * vd * (1.0 - cs2));
+    if (disc < 0.0) disc = 0.0;
+    double root = MUT(8) ? 0.0 : sqrt(cs2) * sqrt(disc);
+    double den = 1.0 - v2 * cs2;
+    double lp = (vd * (1.0 - cs2) + root) / den;
+    double lm = (vd * (1.0 - cs2) - root) / den;
+    return fmax(fabs(lp), fabs(lm));
+}
+
+/* Conserved densities and fluxes of one side state along axis d.
+ * prim = (e, u~x, u~y, u~e); piT is the pi~ entering T, piP the evolved pi~.
+ * QT = tau Tc^{tau nu}, FT = tau Tc^{d nu}, Qpi = u~^tau pi~, Fpi = u~^d pi~. */
+static void side_flux(const orc *S, const double prim[4], const double piT[10],
+                      const double piP[10], int d, double tauf, int doT, int doPi,
+                      double QT[4], double FT[4], double Qpi[10], double Fpi[10],
+                      double *speed) {
+    double P, T, cs2, dP;
+    eos_eval(&S->eos, prim[0], &P, &T, &cs2, &dP);
+    double uc[4];
+    uc[1] = prim[1];
+    uc[2] = prim[2];
+    uc[3] = prim[3];
+    uc[0] = sqrt(1.0 + uc[1] * uc[1] + uc[2] * uc[2] + uc[3] * uc[3]);
+    double e = prim[0] > 0.0 ? prim[0] : 0.0;
+    double w = e + P;
+    if (doT) {
+        for (int nu = 0; nu < 4; ++nu) {
+            double gtn = (nu == 0) ? 1.0 : 0.0;      /* g~^{tau nu} */
+            double gdn = (nu == d) ? -1.0 : 0.0;     /* g~^{d nu}   */
+            QT[nu] = tauf * (w * uc[0] * uc[nu] - P * gtn + piT[SYM(0, nu)]);
+            FT[nu] = tauf * (w * uc[d] * uc[nu] - P * gdn + piT[SYM(d, nu)]);
+        }
+    }
+    if (doPi) {
+        for (int m = 0; m < 10; ++m) {
+            Qpi[m] = uc[0] * piP[m];
+            Fpi[m] = uc[d] * piP[m];
+        }
+    }
+    *speed = local_speed(uc, d, cs2);
+}
+
+/* ------------------------------------------------------------------------ */
+static void fill_ghosts(const orc *S, double *f) {
+    int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
+    /* eta faces */
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int g = 1; g <= NG; ++g) {
+                f[IDX(S, i, j, -g)] = f[IDX(S, i, j, 0)];
+                f[IDX(S, i, j, ne - 1 + g)] = f[IDX(S, i, j, ne - 1)];
+            }
+    /* y faces (including eta ghosts) */
+    for (int i = 0; i < nx; ++i)
+        for (int k = -NG; k < ne + NG; ++k)
+            for (int g = 1; g <= NG; ++g) {
+                f[IDX(S, i, -g, k)] = f[IDX(S, i, 0, k)];
+                f[IDX(S, i, ny - 1 + g, k)] = f[IDX(S, i, ny - 1, k)];
+            }
+    /* x faces (including y and eta ghosts) */
+    for (int j = -NG; j < ny + NG; ++j)
+        for (int k = -NG; k < ne + NG; ++k)
+            for (int g = 1; g <= NG; ++g) {
+                f[IDX(S, -g, j, k)] = f[IDX(S, 0, j, k)];
+                f[IDX(S, nx - 1 + g, j, k)] = f[IDX(S, nx - 1, j, k)];
+            }
+}
+
+/* KT flux divergence along axis d (1 = x, 2 = y, 3 = eta) (Sec. III, eq. kt
+ * and the face flux H = [F(Q^r) + F(Q^l)]/2 - c (Q^r - Q^l)/2).  Adds -dH/Delta
+ * into RT / Rpi for every interior cell; records max c h / Delta in *cfl. */
+static void kt_axis(const orc *S, int d, double *const e, double *const u[3],
+                    double *const piT[10], double *const piP[10], double tau, int doT,
+                    int doPi, double *RT[4], double *Rpi[10], double *cfl) {
+    const int n[4] = {0, S->p.nx, S->p.ny, S->p.ne};
+    const int nd = n[d];
+    const double tauf = S->p.cartesian ? 1.0 : tau;
+    const double Delta = (d == 1) ? S->p.dx : (d == 2) ? S->p.dy : (MUT(5) ? 1.0 : tauf) * S->p.de;
+    const long stride = (d == 1) ? (long)S->NY * S->NE : (d == 2) ? S->NE : 1;
+    int a1 = (d == 1) ? 2 : 1, a2 = (d == 3) ? 2 : 3; /* the two transverse axes */
+    const int n1 = n[a1], n2 = n[a2];
+    double cmax = 0.0;
+
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(max : cmax)
+#endif
+    for (long line = 0; line < (long)n1 * n2; ++line) {
+        int c1 = (int)(line / n2), c2 = (int)(line % n2);
+        int ijk[4];
+        ijk[a1] = c1;
+        ijk[a2] = c2;
+        ijk[d] = 0;
+        long base = IDX(S, ijk[1], ijk[2], ijk[3]); /* cell 0 of the line */
+        double *H = (double *)malloc(sizeof(double) * 14 * (nd + 1));
+        for (int f = -1; f < nd; ++f) { /* face between cells f and f+1 */
+            double qL[14], qR[14];
+            const double *fld[14];
+            fld[0] = e;
+            fld[1] = u[0];
+            fld[2] = u[1];
+            fld[3] = u[2];
+            for (int m = 0; m < 10; ++m) fld[4 + m] = piP[m];
+            /* reconstruct the primitives; piT is reconstructed separately */
+            double piTL[10], piTR[10];
+            for (int v = 0; v < 14; ++v) {
+                const double *F = fld[v];
+                double qm1 = F[base + (long)(f - 1) * stride], q0 = F[base + (long)f * stride];
+                double q1 = F[base + (long)(f + 1) * stride], q2 = F[base + (long)(f + 2) * stride];
+                double sL = limited_slope(S->p.theta, qm1, q0, q1);
+                double sR = limited_slope(S->p.theta, q0, q1, q2);
+                qL[v] = q0 + 0.5 * sL;
+                qR[v] = MUT(9) ? q1 + 0.5 * sR : q1 - 0.5 * sR;
+            }
+            for (int m = 0; m < 10; ++m) {
+                if (piT == piP) { /* same field: same reconstruction */
+                    piTL[m] = qL[4 + m];
+                    piTR[m] = qR[4 + m];
+                    continue;
+                }
+                const double *F = piT[m];
+                double qm1 = F[base + (long)(f - 1) * stride], q0 = F[base + (long)f * stride];
+                double q1 = F[base + (long)(f + 1) * stride], q2 = F[base + (long)(f + 2) * stride];
+                piTL[m] = q0 + 0.5 * limited_slope(S->p.theta, qm1, q0, q1);
+                piTR[m] = q1 - 0.5 * limited_slope(S->p.theta, q0, q1, q2);
+            }
+            double QTL[4], FTL[4], QpL[10], FpL[10], sl;
+            double QTR[4], FTR[4], QpR[10], FpR[10], sr;
+            side_flux(S, qL, piTL, qL + 4, d, tauf, doT, doPi, QTL, FTL, QpL, FpL, &sl);
+            side_flux(S, qR, piTR, qR + 4, d, tauf, doT, doPi, QTR, FTR, QpR, FpR, &sr);
+            double c = fmax(sl, sr);
+            double ch = c * S->p.h / Delta;
+            if (ch > cmax) cmax = ch;
+            double *Hf = H + 14 * (f + 1);
+            for (int nu = 0; nu < 4; ++nu)
+                Hf[nu] = doT ? 0.5 * (FTL[nu] + FTR[nu]) - 0.5 * c * (QTR[nu] - QTL[nu]) : 0.0;
+            for (int m = 0; m < 10; ++m)
+                Hf[4 + m] = doPi ? 0.5 * (FpL[m] + FpR[m]) - 0.5 * c * (QpR[m] - QpL[m]) : 0.0;
+        }
+        for (int cidx = 0; cidx < nd; ++cidx) {
+            long id = base + (long)cidx * stride;
+            const double *Hm = H + 14 * cidx, *Hp = H + 14 * (cidx + 1);
+            if (doT)
+                for (int nu = 0; nu < 4; ++nu) RT[nu][id] -= (Hp[nu] - Hm[nu]) / Delta;
+            if (doPi)
+                for (int m = 0; m < 10; ++m) Rpi[m][id] -= (Hp[4 + m] - Hm[4 + m]) / Delta;
+        }
+        free(H);
+    }
+    if (cmax > *cfl) *cfl = cmax;
+}
+
+/* Geometric source of T~ (Sec. II, eqn. Ttilde): S_T = (-Tc^{ee}, 0, 0, -Tc^{te}).
+ * Adds it to RT; returns the interior sum of S_T^tau. */
+static double geometric_source(const orc *S, double *const e, double *const u[3],
+                               double *const piT[10], double *RT[4]) {
+    if (S->p.cartesian) return 0.0;
+    int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
+    double *st = (double *)malloc(sizeof(double) * (size_t)nx * ny * ne);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k) {
+                long id = IDX(S, i, j, k);
+                double P, T, cs2, dP;
+                eos_eval(&S->eos, e[id], &P, &T, &cs2, &dP);
+                double ee = e[id] > 0.0 ? e[id] : 0.0;
+                double ux = u[0][id], uy = u[1][id], ue = u[2][id];
+                double ut = sqrt(1.0 + ux * ux + uy * uy + ue * ue);
+                double w = ee + P;
+                double Tee = w * ue * ue + P + piT[9][id]; /* -P g~^{ee} = +P */
+                double Tte = w * ut * ue + piT[3][id];
+                RT[0][id] += MUT(1) ? Tee : -Tee;
+                RT[3][id] += -Tte;
+                st[((long)i * ny + j) * ne + k] = -Tee;
+            }
+    double s = 0.0;
+    for (long c = 0; c < (long)nx * ny * ne; ++c) s += st[c];
+    free(st);
+    return s;
+}
+
+/* Velocity-gradient quantities at padded cell id (Sec. II, definitions of theta,
+ * sigma and D, with the tilde covariant derivatives of eq. dtuz):
+ * G[mu][nu] = nabla~_mu u~^nu (d_tau from the two time levels uE -> uL over h,
+ * spatial parts by central differences), theta = G_mu^mu, a^nu = u~^mu G_mu^nu,
+ * sigma~^{mu nu} = nabla~^mu u~^nu + nabla~^nu u~^mu - u~^mu a^nu - u~^nu a^mu
+ *                  - 2/3 (g~^{mu nu} - u~^mu u~^nu) theta.
+ * Ghosts of u must be filled. */
+static void shear_parts(const orc *S, double *const u[3], double *const uE[3],
+                        double *const uL[3], long id, double tau, double uc[4],
+                        double *theta_out, double a[4], double sig[4][4]) {
+    const int cart = S->p.cartesian;
+    const double tauf = cart ? 1.0 : tau;
+    const long st[4] = {0, (long)S->NY * S->NE, S->NE, 1};
+    const double den[4] = {0, 2.0 * S->p.dx, 2.0 * S->p.dy, 2.0 * tauf * S->p.de};
+    double G[4][4], a4[4], b4[4];
+    for (int m = 0; m < 3; ++m) {
+        uc[m + 1] = u[m][id];
+        a4[m + 1] = uE[m][id];
+        b4[m + 1] = uL[m][id];
+    }
+    uc[0] = sqrt(1.0 + uc[1] * uc[1] + uc[2] * uc[2] + uc[3] * uc[3]);
+    a4[0] = sqrt(1.0 + a4[1] * a4[1] + a4[2] * a4[2] + a4[3] * a4[3]);
+    b4[0] = sqrt(1.0 + b4[1] * b4[1] + b4[2] * b4[2] + b4[3] * b4[3]);
+    for (int nu = 0; nu < 4; ++nu) G[0][nu] = (b4[nu] - a4[nu]) / S->p.h;
+    for (int mu = 1; mu < 4; ++mu) {
+        double up[4], um[4];
+        for (int m = 0; m < 3; ++m) {
+            up[m + 1] = u[m][id + st[mu]];
+            um[m + 1] = u[m][id - st[mu]];
+        }
+        up[0] = sqrt(1.0 + up[1] * up[1] + up[2] * up[2] + up[3] * up[3]);
+        um[0] = sqrt(1.0 + um[1] * um[1] + um[2] * um[2] + um[3] * um[3]);
+        for (int nu = 0; nu < 4; ++nu) G[mu][nu] = (up[nu] - um[nu]) / den[mu];
+    }
+    if (!cart) { /* tilde covariant extras, eq. dtuz */
+        G[3][0] += uc[3] / tau;
+        if (!MUT(4)) G[3][3] += uc[0] / tau;
+    }
+    double theta = G[0][0] + G[1][1] + G[2][2] + G[3][3];
+    for (int nu = 0; nu < 4; ++nu) { /* D~ u~^nu = u~^mu nabla~_mu u~^nu */
+        a[nu] = 0.0;
+        for (int mu = 0; mu < 4; ++mu) a[nu] += uc[mu] * (MUT(10) ? G[nu][mu] : G[mu][nu]);
+    }
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu) {
+            double gmn = (mu == nu) ? GT[mu] : 0.0;
+            sig[mu][nu] = GT[mu] * G[mu][nu] + GT[nu] * G[nu][mu] - uc[mu] * a[nu] -
+                          uc[nu] * a[mu] - (MUT(7) ? 1.0 / 3.0 : 2.0 / 3.0) * (gmn - uc[mu] * uc[nu]) * theta;
+        }
+    *theta_out = theta;
+}
+
+/* Israel-Stewart source S_pi (Sec. II, eqn. pitilde and eqn. Ipi; eqn. pimn with
+ * lambda_i = 0; tau_pi = 5 eta_v/(T s), Sec. II).  uE / uL are the earlier and
+ * later time levels for d_tau u~; u is the stage's velocity field. */
+static void pi_source(const orc *S, double *const e, double *const u[3],
+                      double *const pi[10], double *const uE[3], double *const uL[3],
+                      double tau, double *Rpi[10]) {
+    int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
+    const int cart = S->p.cartesian;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k) {
+                long id = IDX(S, i, j, k);
+                if (!(e[id] >= S->p.eps_cut)) continue; /* vacuum: no viscous source */
+                double uc[4], a[4], sg[4][4], theta;
+                shear_parts(S, u, uE, uL, id, tau, uc, &theta, a, sg);
+                double P, T, cs2, dP;
+                eos_eval(&S->eos, e[id], &P, &T, &cs2, &dP);
+                double etav = S->p.etas * (e[id] + P) * HBARC / T;
+                double taupi = (MUT(15) ? 3.0 : 5.0) * S->p.etas * HBARC / T;
+                double pc[4][4];
+                for (int mu = 0; mu < 4; ++mu)
+                    for (int nu = 0; nu < 4; ++nu) pc[mu][nu] = pi[SYM(mu, nu)][id];
+                double b[4]; /* b^nu = pi~^{nu beta} g~_{beta beta} a^beta */
+                for (int nu = 0; nu < 4; ++nu) {
+                    b[nu] = 0.0;
+                    for (int be = 0; be < 4; ++be) b[nu] += pc[nu][be] * GT[be] * a[be];
+                }
+                double I[4][4];
+                memset(I, 0, sizeof(I));
+                if (!cart) {
+                    double ue = uc[3];
+                    I[0][0] = 2.0 * ue * pc[0][3] / tau;
+                    I[0][1] = I[1][0] = ue * pc[3][1] / tau;
+                    I[0][2] = I[2][0] = ue * pc[3][2] / tau;
+                    I[0][3] = I[3][0] = ue * (pc[0][0] + pc[3][3]) / tau;
+                    I[3][1] = I[1][3] = ue * pc[0][1] / tau;
+                    I[3][2] = I[2][3] = ue * pc[0][2] / tau;
+                    I[3][3] = 2.0 * ue * pc[0][3] / tau;
+                }
+                for (int mu = 0; mu < 4; ++mu)
+                    for (int nu = mu; nu < 4; ++nu) {
+                        double s = -(pc[mu][nu] - etav * sg[mu][nu]) / taupi -
+                                   pc[mu][nu] * theta / 3.0 -
+                                   (MUT(6) ? -1.0 : 1.0) * (uc[mu] * b[nu] + uc[nu] * b[mu]);
+                        if (!cart) s += (MUT(2) ? 1.0 : -1.0) * pc[mu][nu] * uc[0] / tau -
+                                        (MUT(3) ? -1.0 : 1.0) * I[mu][nu];
+                        Rpi[SYM(mu, nu)][id] += s;
+                    }
+            }
+}
+
+/* Shear-stress regulator (the paper states none; see the readings above):
+ * where sqrt(|pi~ : pi~|) exceeds rho_max (e + P), pi~ is scaled down to that
+ * size; in vacuum (e + P = 0) pi~ is set to zero.  pi~ : pi~ =
+ * pi~^{mu nu} pi~^{ab} g~_{mu a} g~_{nu b}, an invariant of the local frame. */
+static void regulate_pi(const orc *S, double e, double pi10[10]) {
+    double P, T, cs2, dP;
+    eos_eval(&S->eos, e, &P, &T, &cs2, &dP);
+    double w = (e > 0.0 ? e : 0.0) + P;
+    if (!(w > 0.0)) {
+        for (int m = 0; m < 10; ++m) pi10[m] = 0.0;
+        return;
+    }
+    double pp = 0.0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu) {
+            double v = pi10[SYM(mu, nu)];
+            pp += GT[mu] * GT[nu] * v * v;
+        }
+    double rho = sqrt(fabs(pp)) / w;
+    if (rho > S->p.pi_reg) {
+        double f = S->p.pi_reg / rho;
+        for (int m = 0; m < 10; ++m) pi10[m] *= f;
+    }
+}
+
+/* Full right-hand side: R_T = S_KT + S_T (if doT), R_pi = S_KT + S_pi (if doPi).
+ * Ghosts of every field read must be filled by the caller. */
+static double rhs(orc *S, double *const e, double *const u[3], double *const piT[10],
+                  double *const piP[10], double *const uE[3], double *const uL[3],
+                  double tau, int doT, int doPi, double *RT[4], double *Rpi[10],
+                  double *cfl) {
+    for (int nu = 0; nu < 4; ++nu)
+        if (doT) memset(RT[nu], 0, sizeof(double) * S->npad);
+    for (int m = 0; m < 10; ++m)
+        if (doPi) memset(Rpi[m], 0, sizeof(double) * S->npad);
+    for (int d = 1; d <= 3; ++d) kt_axis(S, d, e, u, piT, piP, tau, doT, doPi, RT, Rpi, cfl);
+    double st = 0.0;
+    if (doT) st = geometric_source(S, e, u, piT, RT);
+    if (doPi) pi_source(S, e, u, piP, uE, uL, tau, Rpi);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+static double *alloc_field(const orc *S) {
+    return (double *)calloc((size_t)S->npad, sizeof(double));
+}
+
+static int it_cell_zero(int it) { return it == 0; }
+
+static void cells_con2prim(orc *S, double *const T[4], double *const piq[10], double tau,
+                           double *const guess, double *e_out, double *u_out[3]) {
+    int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
+    const double tauf = S->p.cartesian ? 1.0 : tau;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k) {
+                long id = IDX(S, i, j, k);
+                double K[4], uo[3], eo;
+                for (int nu = 0; nu < 4; ++nu)
+                    K[nu] = T[nu][id] / tauf - (piq ? piq[SYM(0, nu)][id] : 0.0);
+                int it, fl;
+                con2prim(S, K, guess ? guess[id] : K[0], &eo, uo, &it, &fl);
+                e_out[id] = eo;
+                for (int m = 0; m < 3; ++m) u_out[m][id] = uo[m];
+                long c = ((long)i * ny + j) * ne + k;
+                S->it_cell[c] = it;
+                S->flag_cell[c] = fl;
+            }
+    /* serial bookkeeping */
+    for (long c = 0; c < S->ncell; ++c) {
+        int fl = S->flag_cell[c];
+        if ((fl & C2P_VAC) && it_cell_zero(S->it_cell[c])) continue; /* no iteration ran */
+        S->d.solves++;
+        S->sum_iters += S->it_cell[c];
+        if (S->it_cell[c] > S->d.newton_max) S->d.newton_max = S->it_cell[c];
+        if (fl & C2P_FALLBACK) S->d.fallbacks++;
+        if (fl & C2P_NONCONV) S->d.nonconv++;
+        if (fl & C2P_NAN) S->d.nans++;
+        if (fl & C2P_CLAMP) S->d.clamps++;
+    }
+}
+
+/* tau~ T^{tau mu} of a primitive state (tau~ = tau, or 1 in Cartesian mode). */
+static void conserved_of(const orc *S, double e, const double u3[3], const double *pic,
+                         double tauf, double Tout[4]) {
+    double P, T, cs2, dP;
+    eos_eval(&S->eos, e, &P, &T, &cs2, &dP);
+    double uc[4] = {0, u3[0], u3[1], u3[2]};
+    uc[0] = sqrt(1.0 + uc[1] * uc[1] + uc[2] * uc[2] + uc[3] * uc[3]);
+    double w = (e > 0.0 ? e : 0.0) + P;
+    for (int nu = 0; nu < 4; ++nu)
+        Tout[nu] = tauf * (w * uc[0] * uc[nu] - P * (nu == 0 ? 1.0 : 0.0) +
+                           (pic ? pic[SYM(0, nu)] : 0.0));
+}
+
+/* ------------------------------------------------------------------------ */
+/* public API                                                               */
+/* ------------------------------------------------------------------------ */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+orc *orc_create(const orc_params *p) {
+    if (p->nx < 1 || p->ny < 1 || p->ne < 1 || !(p->h > 0) || !(p->dx > 0) || !(p->dy > 0) ||
+        !(p->de > 0) || !(p->tau0 > 0))
+        return NULL;
+    if (p->viscous && !(p->etas > 0)) return NULL;
+    orc *S = (orc *)calloc(1, sizeof(orc));
+    S->p = *p;
+    S->NX = p->nx + 2 * NG;
+    S->NY = p->ny + 2 * NG;
+    S->NE = p->ne + 2 * NG;
+    S->ncell = (long)p->nx * p->ny * p->ne;
+    S->npad = (long)S->NX * S->NY * S->NE;
+    S->e = alloc_field(S);
+    S->e1 = alloc_field(S);
+    S->zero = alloc_field(S);
+    for (int m = 0; m < 3; ++m) {
+        S->u[m] = alloc_field(S);
+        S->uprev[m] = alloc_field(S);
+        S->u1[m] = alloc_field(S);
+    }
+    for (int m = 0; m < 10; ++m) {
+        S->pi[m] = alloc_field(S);
+        S->pi1[m] = alloc_field(S);
+        S->piN[m] = alloc_field(S);
+        S->Rpi1[m] = alloc_field(S);
+        S->Rpi2[m] = alloc_field(S);
+    }
+    for (int m = 0; m < 4; ++m) {
+        S->T[m] = alloc_field(S);
+        S->T1[m] = alloc_field(S);
+        S->RT1[m] = alloc_field(S);
+        S->RT2[m] = alloc_field(S);
+    }
+    S->it_cell = (int *)calloc((size_t)S->ncell, sizeof(int));
+    S->flag_cell = (int *)calloc((size_t)S->ncell, sizeof(int));
+    S->eos.kind = 0;
+    S->eos.c_sb = 47.5 * M_PI * M_PI / 30.0 / (HBARC * HBARC * HBARC);
+    S->tau = p->tau0;
+    return S;
+}
+
+void orc_destroy(orc *S) {
+    if (!S) return;
+    free(S->e);
+    free(S->e1);
+    free(S->zero);
+    for (int m = 0; m < 3; ++m) {
+        free(S->u[m]);
+        free(S->uprev[m]);
+        free(S->u1[m]);
+    }
+    for (int m = 0; m < 10; ++m) {
+        free(S->pi[m]);
+        free(S->pi1[m]);
+        free(S->piN[m]);
+        free(S->Rpi1[m]);
+        free(S->Rpi2[m]);
+    }
+    for (int m = 0; m < 4; ++m) {
+        free(S->T[m]);
+        free(S->T1[m]);
+        free(S->RT1[m]);
+        free(S->RT2[m]);
+    }
+    free(S->it_cell);
+    free(S->flag_cell);
+    free(S->eos.P);
+    free(S->eos.T);
+    free(S->eos.cs2);
+    free(S);
+}
+
+int orc_set_eos_conformal(orc *S, double c_sb) {
+    if (!(c_sb > 0)) return -1;
+    S->eos.kind = 0;
+    S->eos.c_sb = c_sb;
+    return 0;
+}
+
+int orc_set_eos_table(orc *S, double e0, double de, int n, const double *P, const double *T,
+                      const double *cs2) {
+    if (n < 2 || !(de > 0)) return -1;
+    free(S->eos.P);
+    free(S->eos.T);
+    free(S->eos.cs2);
+    S->eos.P = (double *)malloc(sizeof(double) * n);
+    S->eos.T = (double *)malloc(sizeof(double) * n);
+    S->eos.cs2 = (double *)malloc(sizeof(double) * n);
+    memcpy(S->eos.P, P, sizeof(double) * n);
+    memcpy(S->eos.T, T, sizeof(double) * n);
+    memcpy(S->eos.cs2, cs2, sizeof(double) * n);
+    S->eos.kind = 1;
+    S->eos.e0 = e0;
+    S->eos.de = de;
+    S->eos.n = n;
+    return 0;
+}
+
+static void copy_in(const orc *S, double *dst, const double *src) {
+    int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k)
+                dst[IDX(S, i, j, k)] = src ? src[((long)i * ny + j) * ne + k] : 0.0;
+}
+
+/* First-step estimate of u*1 by one ideal forward-Euler step (Sec. III: ideal
+ * hydrodynamics estimates u*1 when u^{n-1} is unknown); u~^{-1} = 2 u~^0 - u*1. */
+static void first_step_estimate(orc *S) {
+    double tau0 = S->tau, tau1 = S->tau + S->p.h;
+    const double tf0 = S->p.cartesian ? 1.0 : tau0;
+    fill_ghosts(S, S->e);
+    for (int m = 0; m < 3; ++m) fill_ghosts(S, S->u[m]);
+    double *zp[10];
+    for (int m = 0; m < 10; ++m) zp[m] = S->zero;
+    double cfl = 0.0;
+    rhs(S, S->e, S->u, zp, zp, S->u, S->u, tau0, 1, 0, S->RT1, NULL, &cfl);
+    int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k) {
+                long id = IDX(S, i, j, k);
+                double u3[3] = {S->u[0][id], S->u[1][id], S->u[2][id]}, Tid[4];
+                conserved_of(S, S->e[id], u3, NULL, tf0, Tid);
+                for (int nu = 0; nu < 4; ++nu) S->T1[nu][id] = Tid[nu] + S->p.h * S->RT1[nu][id];
+            }
+    long solves = S->d.solves, it = S->sum_iters; /* do not count these solves */
+    long nmax = S->d.newton_max, fb = S->d.fallbacks, nc = S->d.nonconv, na = S->d.nans,
+         cl = S->d.clamps;
+    cells_con2prim(S, S->T1, NULL, tau1, S->e, S->e1, S->u1);
+    S->d.solves = solves;
+    S->sum_iters = it;
+    S->d.newton_max = nmax;
+    S->d.fallbacks = fb;
+    S->d.nonconv = nc;
+    S->d.nans = na;
+    S->d.clamps = cl;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k) {
+                long id = IDX(S, i, j, k);
+                for (int m = 0; m < 3; ++m)
+                    S->uprev[m][id] = MUT(13) ? S->u[m][id] : 2.0 * S->u[m][id] - S->u1[m][id];
+            }
+}
+
+static void finish_initial(orc *S) {
+    memset(&S->d, 0, sizeof(S->d));
+    S->sum_iters = 0;
+    S->step = 0;
+    first_step_estimate(S);
+    S->d.tau = S->tau;
+}
+
+/* Primitive initial state; pi10 may be NULL (pi~ = 0).  Arrays are C-ordered
+ * (nx, ny, ne); pi10 holds 10 such blocks. */
+int orc_set_initial_primitive(orc *S, const double *e, const double *ux, const double *uy,
+                              const double *ue, const double *pi10) {
+    S->tau = S->p.tau0;
+    copy_in(S, S->e, e);
+    copy_in(S, S->u[0], ux);
+    copy_in(S, S->u[1], uy);
+    copy_in(S, S->u[2], ue);
+    for (int m = 0; m < 10; ++m) copy_in(S, S->pi[m], (pi10 && S->p.viscous) ? pi10 + (long)m * S->ncell : NULL);
+    const double tf = S->p.cartesian ? 1.0 : S->tau;
+    int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k) {
+                long id = IDX(S, i, j, k);
+                if (!(S->e[id] >= S->p.eps_cut)) { /* cutoff */
+                    S->e[id] = 0.0;
+                    for (int m = 0; m < 3; ++m) S->u[m][id] = 0.0;
+                    for (int m = 0; m < 10; ++m) S->pi[m][id] = 0.0;
+                }
+                double u3[3] = {S->u[0][id], S->u[1][id], S->u[2][id]}, pic[10], Tc[4];
+                for (int m = 0; m < 10; ++m) pic[m] = S->pi[m][id];
+                conserved_of(S, S->e[id], u3, pic, tf, Tc);
+                for (int nu = 0; nu < 4; ++nu) S->T[nu][id] = Tc[nu];
+            }
+    finish_initial(S);
+    return 0;
+}
+
+/* Conserved initial state T~^{tau mu} (4 blocks) plus optional pi~; the root
+ * solve (cold guess E) yields (e, u~). */
+int orc_set_initial_conserved(orc *S, const double *T4, const double *pi10) {
+    S->tau = S->p.tau0;
+    for (int nu = 0; nu < 4; ++nu) copy_in(S, S->T[nu], T4 + (long)nu * S->ncell);
+    for (int m = 0; m < 10; ++m) copy_in(S, S->pi[m], (pi10 && S->p.viscous) ? pi10 + (long)m * S->ncell : NULL);
+    cells_con2prim(S, S->T, S->pi, S->tau, NULL, S->e, S->u);
+    int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k) {
+                long id = IDX(S, i, j, k);
+                if (S->e[id] == 0.0)
+                    for (int m = 0; m < 10; ++m) S->pi[m][id] = 0.0;
+            }
+    finish_initial(S);
+    return 0;
+}
+
+/* One RK2 step n -> n+1 (Sec. III, the predictor-corrector flow chart):
+ * stage 1 predicts T', pi' (with u* = 2u^n - u^{n-1}) and solves for (e', u');
+ * stage 2 first updates pi^{n+1} with the averaged sources, then T^{n+1} with
+ * S_T evaluated on pi^{n+1}, then solves for (e^{n+1}, u^{n+1}). */
+static void one_step(orc *S) {
+    const int visc = S->p.viscous;
+    const double h = S->p.h, taun = S->tau, tau1 = S->tau + h;
+    int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
+    double cfl = 0.0;
+    double *zp[10];
+    for (int m = 0; m < 10; ++m) zp[m] = S->zero;
+
+    /* ---- stage 1 at tau_n ---- */
+    fill_ghosts(S, S->e);
+    for (int m = 0; m < 3; ++m) fill_ghosts(S, S->u[m]);
+    if (visc)
+        for (int m = 0; m < 10; ++m) fill_ghosts(S, S->pi[m]);
+    double *const *piN_ = visc ? S->pi : zp;
+    double st1 = rhs(S, S->e, S->u, piN_, piN_, S->uprev, S->u, taun, 1, visc, S->RT1,
+                     S->Rpi1, &cfl);
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k) {
+                long id = IDX(S, i, j, k);
+                for (int nu = 0; nu < 4; ++nu) S->T1[nu][id] = S->T[nu][id] + h * S->RT1[nu][id];
+                if (visc) {
+                    double ux = S->u[0][id], uy = S->u[1][id], ue = S->u[2][id];
+                    double utn = sqrt(1.0 + ux * ux + uy * uy + ue * ue);
+                    double s0 = 2.0 * ux - S->uprev[0][id], s1 = 2.0 * uy - S->uprev[1][id],
+                           s2 = 2.0 * ue - S->uprev[2][id];
+                    if (MUT(16)) { s0 = ux; s1 = uy; s2 = ue; }
+                    double uts = sqrt(1.0 + s0 * s0 + s1 * s1 + s2 * s2);
+                    double p1[10];
+                    for (int m = 0; m < 10; ++m)
+                        p1[m] = (utn * S->pi[m][id] + h * S->Rpi1[m][id]) / uts;
+                    if (S->p.pi_reg > 0.0) regulate_pi(S, S->e[id], p1);
+                    for (int m = 0; m < 10; ++m) S->pi1[m][id] = p1[m];
+                }
+            }
+    cells_con2prim(S, S->T1, visc ? S->pi1 : NULL, tau1, S->e, S->e1, S->u1);
+
+    /* ---- stage 2 at tau_{n+1} ---- */
+    fill_ghosts(S, S->e1);
+    for (int m = 0; m < 3; ++m) fill_ghosts(S, S->u1[m]);
+    if (visc) {
+        for (int m = 0; m < 10; ++m) fill_ghosts(S, S->pi1[m]);
+        rhs(S, S->e1, S->u1, S->pi1, S->pi1, S->u, S->u1, tau1, 0, 1, NULL, S->Rpi2, &cfl);
+        for (int i = 0; i < nx; ++i)
+            for (int j = 0; j < ny; ++j)
+                for (int k = 0; k < ne; ++k) {
+                    long id = IDX(S, i, j, k);
+                    double ux = S->u[0][id], uy = S->u[1][id], ue = S->u[2][id];
+                    double utn = sqrt(1.0 + ux * ux + uy * uy + ue * ue);
+                    double a = S->u1[0][id], b = S->u1[1][id], c = S->u1[2][id];
+                    double ut1 = sqrt(1.0 + a * a + b * b + c * c);
+                    double s0 = 2.0 * ux - S->uprev[0][id], s1 = 2.0 * uy - S->uprev[1][id],
+                           s2 = 2.0 * ue - S->uprev[2][id];
+                    if (MUT(16)) { s0 = ux; s1 = uy; s2 = ue; }
+                    double uts = sqrt(1.0 + s0 * s0 + s1 * s1 + s2 * s2);
+                    /* u'pi^{n+1} = u^n pi^n + h/2 (S1 + S2) with h S1 = u* pi' - u^n pi^n,
+                     * pi' being the (possibly regulated) predictor */
+                    double pn[10];
+                    for (int m = 0; m < 10; ++m)
+                        pn[m] = (0.5 * (utn * S->pi[m][id] + uts * S->pi1[m][id]) +
+                                 0.5 * h * S->Rpi2[m][id]) / ut1;
+                    if (S->p.pi_reg > 0.0) regulate_pi(S, S->e1[id], pn);
+                    for (int m = 0; m < 10; ++m) S->piN[m][id] = pn[m];
+                }
+        for (int m = 0; m < 10; ++m) fill_ghosts(S, S->piN[m]);
+    }
+    double *const *piT2 = visc ? (MUT(14) ? S->pi1 : S->piN) : zp;
+    double st2 = rhs(S, S->e1, S->u1, piT2, piT2, NULL, NULL, tau1, 1, 0, S->RT2, NULL, &cfl);
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k) {
+                long id = IDX(S, i, j, k);
+                for (int nu = 0; nu < 4; ++nu)
+                    S->T[nu][id] = S->T[nu][id] + 0.5 * h * (S->RT1[nu][id] + S->RT2[nu][id]);
+            }
+    /* the new (e, u) go to e1/u1's storage after uprev <- u */
+    for (int m = 0; m < 3; ++m) {
+        double *t = S->uprev[m];
+        S->uprev[m] = S->u[m];
+        S->u[m] = t;
+    }
+    /* solve into S->e (e^n is no longer needed), the stage-1 solution is the guess */
+    cells_con2prim(S, S->T, visc ? S->piN : NULL, tau1, S->e1, S->e, S->u);
+    if (visc)
+        for (int m = 0; m < 10; ++m) {
+            double *t = S->pi[m];
+            S->pi[m] = S->piN[m];
+            S->piN[m] = t;
+        }
+    /* vacuum cells lose their shear stress */
+    double emax = 0.0, sumT = 0.0;
+    long vac = 0;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k) {
+                long id = IDX(S, i, j, k);
+                if (S->e[id] == 0.0) {
+                    vac++;
+                    for (int m = 0; m < 10; ++m) S->pi[m][id] = 0.0;
+                } else if (visc && S->p.pi_reg > 0.0) {
+                    double pn[10];
+                    for (int m = 0; m < 10; ++m) pn[m] = S->pi[m][id];
+                    regulate_pi(S, S->e[id], pn);
+                    for (int m = 0; m < 10; ++m) S->pi[m][id] = pn[m];
+                }
+                if (S->e[id] > emax) emax = S->e[id];
+                sumT += S->T[0][id];
+            }
+    double vol = S->p.dx * S->p.dy * S->p.de;
+    S->tau = tau1;
+    S->step++;
+    S->d.tau = S->tau;
+    S->d.step = S->step;
+    S->d.eps_max = emax;
+    S->d.sum_Ttt = sumT * vol;
+    S->d.geo_src += 0.5 * h * (st1 + st2) * vol;
+    if (cfl > S->d.max_cfl) S->d.max_cfl = cfl;
+    S->d.vacuum = vac;
+    S->d.newton_mean = S->d.solves ? (double)S->sum_iters / (double)S->d.solves : 0.0;
+}
+
+int orc_step(orc *S, int n) {
+    for (int s = 0; s < n; ++s) one_step(S);
+    return 0;
+}
+
+/* Fields: 0 e, 1-3 u~ (x, y, eta), 4-13 pi~, 14-17 T~^{tau mu}, 18-20 u~ at the
+ * previous time level.  dst gets the interior in C order. */
+int orc_read(const orc *S, int field, double *dst) {
+    const double *src;
+    if (field == 0)
+        src = S->e;
+    else if (field >= 1 && field <= 3)
+        src = S->u[field - 1];
+    else if (field >= 4 && field <= 13)
+        src = S->pi[field - 4];
+    else if (field >= 14 && field <= 17)
+        src = S->T[field - 14];
+    else if (field >= 18 && field <= 20)
+        src = S->uprev[field - 18];
+    else
+        return -1;
+    int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ne; ++k)
+                dst[((long)i * ny + j) * ne + k] =
+                    (field >= 4 && field <= 13 && !S->p.viscous) ? 0.0 : src[IDX(S, i, j, k)];
+    return 0;
+}
+
+int orc_diag_get(const orc *S, orc_diag *out) {
+    *out = S->d;
+    return 0;
+}
+
+/* ---- point functions used by the pin tests ---- */
+int orc_eos_eval(const orc *S, int n, const double *e, double *P, double *T, double *cs2,
+                 double *dPde) {
+    for (int i = 0; i < n; ++i) eos_eval(&S->eos, e[i], &P[i], &T[i], &cs2[i], &dPde[i]);
+    return 0;
+}
+
+int orc_con2prim(const orc *S, int n, const double *K4, const double *guess, double *e,
+                 double *u3, int *iters, int *flags) {
+    for (int i = 0; i < n; ++i)
+        con2prim(S, K4 + 4 * (long)i, guess ? guess[i] : K4[4 * (long)i], &e[i], u3 + 3 * (long)i,
+                 &iters[i], &flags[i]);
+    return 0;
+}
+
+/* K^mu = (e+P) u~^tau u~^mu - P g~^{tau mu} of primitive states (for round trips). */
+int orc_prim2K(const orc *S, int n, const double *e, const double *u3, double *K4) {
+    for (int i = 0; i < n; ++i) conserved_of(S, e[i], u3 + 3 * (long)i, NULL, 1.0, K4 + 4 * (long)i);
+    return 0;
+}
+
+int orc_local_speed(int n, const double *u3, int axis, const double *cs2, double *out) {
+    for (int i = 0; i < n; ++i) {
+        double uc[4] = {0, u3[3 * i], u3[3 * i + 1], u3[3 * i + 2]};
+        uc[0] = sqrt(1.0 + uc[1] * uc[1] + uc[2] * uc[2] + uc[3] * uc[3]);
+        out[i] = local_speed(uc, axis, cs2[i]);
+    }
+    return 0;
+}
+
+/* Shear tensor, expansion rate and acceleration at interior cell (i, j, k) of
+ * a velocity field (used by the pin tests to check the gradient assembly of
+ * S_pi against an exact covariant evaluation).  uE / uL: time levels for d_tau
+ * (same convention as the step), u: the current field (C-ordered interior
+ * arrays of 3 blocks).  out: sigma~ (10, pi~ order), theta, a~ (4). */
+int orc_shear_at(orc *S, const double *u3E, const double *u3L, const double *u3, double tau,
+                 int i, int j, int k, double *out15) {
+    double *uE[3], *uL[3], *u[3];
+    for (int m = 0; m < 3; ++m) {
+        uE[m] = alloc_field(S);
+        uL[m] = alloc_field(S);
+        u[m] = alloc_field(S);
+        copy_in(S, uE[m], u3E + (long)m * S->ncell);
+        copy_in(S, uL[m], u3L + (long)m * S->ncell);
+        copy_in(S, u[m], u3 + (long)m * S->ncell);
+        fill_ghosts(S, u[m]);
+    }
+    long id = IDX(S, i, j, k);
+    double uc[4], a[4], sg[4][4], theta;
+    shear_parts(S, u, uE, uL, id, tau, uc, &theta, a, sg);
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = mu; nu < 4; ++nu) out15[SYM(mu, nu)] = sg[mu][nu];
+    out15[10] = theta;
+    for (int nu = 0; nu < 4; ++nu) out15[11 + nu] = a[nu];
+    for (int m = 0; m < 3; ++m) {
+        free(uE[m]);
+        free(uL[m]);
+        free(u[m]);
+    }
+    return 0;
+}

@@ -1,0 +1,168 @@
+"""Closed-form and independently integrated references used to pin the oracle.
+
+Nothing here calls the oracle or the HIP library.  Each reference is derived
+from the paper's physics (Sec. II and Sec. V) by a route that differs from the
+oracle's discretisation: exact solutions, library ODE integrators, and a
+generic covariant evaluation (Christoffel symbols from the metric by automatic
+differentiation) of the shear tensor's projector definition.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.integrate import solve_ivp
+
+from hydro_inputs.eos import C_SB, HBARC
+from hydro_inputs.ics import Grid
+
+# ---------------------------------------------------------------------------
+# Bjorken flow (Sec. V.B)
+# ---------------------------------------------------------------------------
+
+
+def bjorken_ideal_exact(eps0, tau0, tau):
+    """Ideal gas: eps = eps0 (tau0/tau)^(4/3)."""
+    return eps0 * (tau0 / tau) ** (4.0 / 3.0)
+
+
+def is_bjorken_rhs(etas):
+    """0+1D Israel-Stewart Bjorken system, conformal EoS, y = (eps, Phi), Phi = -tau^2 pi^etaeta:
+    d eps/d tau = -(eps + P - Phi)/tau,
+    d Phi/d tau = -(Phi - 4 eta/(3 tau))/tau_pi - 4/3 Phi/tau,
+    with eta = (eta/s)(eps+P) hbarc/T and tau_pi = 5 (eta/s) hbarc/T."""
+
+    def f(tau, y):
+        e, phi = y
+        T = (e / C_SB) ** 0.25
+        P = e / 3.0
+        eta = etas * (e + P) * HBARC / T
+        tpi = 5.0 * etas * HBARC / T
+        return [-(e + P - phi) / tau, -(phi - 4.0 * eta / (3.0 * tau)) / tpi - 4.0 / 3.0 * phi / tau]
+
+    return f
+
+
+def is_bjorken_reference(eps0, phi0, tau0, tau1, etas):
+    sol = solve_ivp(is_bjorken_rhs(etas), (tau0, tau1), [eps0, phi0], method="DOP853",
+                    rtol=1e-13, atol=1e-16)
+    return sol.y[0, -1], sol.y[1, -1]
+
+
+def bjorken_ns_temperature(T0, tau0, tau, etas):
+    """First-order (Navier-Stokes) Bjorken solution for the ideal gas:
+    T/T0 = (tau0/tau)^(1/3) [1 + 2 (eta/s) hbarc/(3 T0 tau0) (1 - (tau0/tau)^(2/3))]."""
+    r = tau0 / tau
+    return T0 * r ** (1.0 / 3.0) * (1.0 + 2.0 * etas * HBARC / (3.0 * T0 * tau0) * (1.0 - r ** (2.0 / 3.0)))
+
+
+# ---------------------------------------------------------------------------
+# Riemann rarefaction (Sec. V.A)
+# ---------------------------------------------------------------------------
+
+
+def riemann_exact(zeta, cs):
+    """Rarefaction into vacuum: eps/eps0 and v as functions of zeta = x/t."""
+    zeta = np.asarray(zeta, dtype=np.float64)
+    ratio = np.ones_like(zeta)
+    fan = zeta >= -cs
+    z = np.clip(zeta[fan], -cs, 1.0 - 1e-15)
+    ratio[fan] = ((1.0 - cs) / (1.0 + cs) * (1.0 - z) / (1.0 + z)) ** ((1.0 + cs * cs) / (2.0 * cs))
+    v = np.tanh(-cs / (1.0 + cs * cs) * np.log(np.maximum(ratio, 1e-300)))
+    return ratio, v
+
+
+# ---------------------------------------------------------------------------
+# A uniformly moving fluid whose shear stress relaxes (exact IS solution).
+# ---------------------------------------------------------------------------
+
+
+def relaxing_fluid_milne(g: Grid, tau, eps0, v, a0, taupi):
+    """Cartesian rest frame: u = gamma(1, v, 0, 0), pi_rest = diag(0, -a/2, -a/2, a) with
+    a = a0 exp(-t'/tau_pi), t' = gamma (t - v x) the fluid's proper time.  This solves the
+    Israel-Stewart equations exactly (sigma = theta = Du = 0 and d_mu pi^{mu nu} = 0).
+    Returned in Milne tilde components on grid g at proper time tau."""
+    X, _, E = g.mesh()
+    gam = 1.0 / math.sqrt(1.0 - v * v)
+    t = tau * np.cosh(E)
+    tp = gam * (t - v * X)
+    a = a0 * np.exp(-tp / taupi)
+    L = np.array([[gam, gam * v, 0, 0], [gam * v, gam, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1.0]])
+    shape = g.shape
+    pic = np.zeros((4, 4) + shape)
+    pr = np.zeros((4, 4) + shape)
+    pr[1, 1] = -0.5 * a
+    pr[2, 2] = -0.5 * a
+    pr[3, 3] = a
+    pic = np.einsum("ma,abxyz,nb->mnxyz", L, pr, L)
+    ch, sh = np.cosh(E), np.sinh(E)
+    # J^mu_alpha = d(tau, x, y, eta)/d(t, x, y, z); tilde scaling multiplies the eta row by tau
+    Jt = np.zeros((4, 4) + shape)
+    Jt[0, 0] = ch
+    Jt[0, 3] = -sh
+    Jt[1, 1] = 1.0
+    Jt[2, 2] = 1.0
+    Jt[3, 0] = -sh  # tau * (-sinh/tau)
+    Jt[3, 3] = ch   # tau * (cosh/tau)
+    pim = np.einsum("maxyz,abxyz,nbxyz->mnxyz", Jt, pic, Jt)
+    order = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]
+    pi = np.stack([pim[m, n] for m, n in order])
+    ux = np.full(shape, gam * v)
+    ue = -gam * sh
+    return dict(eps=np.full(shape, eps0), ux=ux, uy=np.zeros(shape), ue=ue, pi=pi)
+
+
+def conformal_taupi(eps0, etas):
+    T = (eps0 / C_SB) ** 0.25
+    return 5.0 * etas * HBARC / T
+
+
+# ---------------------------------------------------------------------------
+# Shear tensor from its projector definition, generic covariant derivatives.
+# ---------------------------------------------------------------------------
+
+
+def covariant_shear_milne(u_tilde_fn, X):
+    """sigma~^{mu nu}, theta, and a~^nu = (D u)~^nu at Milne point X = (tau, x, y, eta).
+
+    u_tilde_fn(X) -> (u~x, u~y, u~eta) as torch scalars.  The physical contravariant
+    velocity is u = (u~^tau, u~x, u~y, u~eta / tau).  Christoffel symbols come from the
+    metric g = diag(1, -1, -1, -tau^2) by automatic differentiation, and
+    sigma^{mu nu} = 2 Delta^{mu nu alpha beta} nabla_alpha u_beta (Sec. II, eqn. projector).
+    """
+    import torch
+
+    X = torch.tensor(X, dtype=torch.float64)
+
+    def metric(Y):
+        return torch.diag(torch.stack([torch.ones((), dtype=torch.float64),
+                                       -torch.ones((), dtype=torch.float64),
+                                       -torch.ones((), dtype=torch.float64), -Y[0] ** 2]))
+
+    def ucontra(Y):
+        ux, uy, ue = u_tilde_fn(Y)
+        ut = torch.sqrt(1.0 + ux * ux + uy * uy + ue * ue)
+        return torch.stack([ut, ux, uy, ue / Y[0]])
+
+    g = metric(X)
+    ginv = torch.linalg.inv(g)
+    dg = torch.autograd.functional.jacobian(metric, X)  # dg[a, b, c] = d_c g_ab
+    Gam = 0.5 * (torch.einsum("ad,dcb->abc", ginv, dg) + torch.einsum("ad,dbc->abc", ginv, dg)
+                 - torch.einsum("ad,bcd->abc", ginv, dg))  # Gamma^a_{bc}
+    u = ucontra(X)
+    du = torch.autograd.functional.jacobian(ucontra, X)  # du[a, b] = d_b u^a
+    nab = du.T + torch.einsum("abc,c->ba", Gam, u)  # nab[b, a] = nabla_b u^a
+    theta = torch.trace(nab)
+    Du = torch.einsum("b,ba->a", u, nab)
+    Delta = ginv - torch.outer(u, u)
+    nab_low = torch.einsum("ag,bg->ab", nab, g)  # nabla_alpha u_beta
+    P4 = 0.5 * (torch.einsum("ma,nb->mnab", Delta, Delta) + torch.einsum("mb,na->mnab", Delta, Delta)) \
+        - torch.einsum("mn,ab->mnab", Delta, Delta) / 3.0
+    sig = 2.0 * torch.einsum("mnab,ab->mn", P4, nab_low)
+    tau = X[0]
+    scale = torch.tensor([1.0, 1.0, 1.0, float(tau)], dtype=torch.float64)
+    sig_t = sig * scale[:, None] * scale[None, :]
+    a_t = Du * scale
+    order = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]
+    return (np.array([float(sig_t[m, n]) for m, n in order]), float(theta),
+            a_t.detach().numpy().copy())

@@ -1,0 +1,45 @@
+"""Self-check of the pins: plant one plausible mistake at a time in the oracle
+(on the CPU) and require that at least one pin fails.
+
+Mutants (see MUT(k) in oracle/hydro_oracle.c):
+ 1 S_T^tau sign, 2 sign of the pi u~^tau/tau term, 3 sign of I^{mu nu},
+ 4 missing u~^tau/tau extra in nabla~_eta u~^eta, 5 Delta_eta = deta (no tau),
+ 6 sign of the u b term, 7 wrong trace coefficient in sigma, 8 local speed
+ without the sound speed, 9 sign of the right-state reconstruction,
+ 10 transposed gradient in D~u~, 11 wrong velocity normalisation in the root
+ solve, 12 EoS T interpolation off by one node, 13 no ideal first-step
+ estimate, 14 stage-2 T flux with pi' instead of pi^{n+1}, 15 tau_pi = 3 eta/(sT).
+Mutant 16 (u* = u^n instead of 2u^n - u^{n-1}) alters only the predicted pi'
+at O(h) and the step at O(h^2), the scheme's own order, so no pin is expected
+to separate it; the GPU-oracle parity tests cover that code path.
+"""
+import warnings
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+from . import pins
+
+CAUGHT = list(range(1, 16))
+
+
+@pytest.mark.parametrize("k", CAUGHT)
+def test_planted_mistake_is_caught(k):
+    failed = []
+    O.set_mutant(k)
+    try:
+        with warnings.catch_warnings(), np.errstate(all="ignore"):
+            warnings.simplefilter("ignore")
+            for name, fn in pins.ALL_PINS.items():
+                try:
+                    ok, _ = fn()
+                except Exception:
+                    ok = False
+                if not ok:
+                    failed.append(name)
+                    break
+    finally:
+        O.set_mutant(0)
+    assert failed, f"planted mistake {k} passed every pin"
