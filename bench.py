@@ -1,0 +1,139 @@
+"""Benchmark: cell-updates/s of the viscous KT + RK2 step on one MI355X.
+
+Workload (default): viscous hydro, eta/s = 0.08, 201 x 201 x 105 cells
+(dx = dy = 0.16 fm, deta = 0.3), tau0 = 0.6 fm, h = 0.01 fm, 200 seeded Gaussian
+hotspots, 1555-row synthetic EoS, FP64.  A step is one full RK2 step (all three
+stencil passes, both root solves, the diagnostics reduction) over the grid.
+
+Prints one JSON line.  `roofline` is measured live for the dominant kernel with
+HIP events recorded on the library's stream around every launch in the timed
+region; `cpu_baseline` times the CPU oracle on a bounded sample of the same
+workload (rank 0, N = 1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+# Algorithmic HBM bytes per cell for each kernel of the FP64 viscous step: every
+# field a kernel reads or writes, counted once per cell (stencil reuse assumed
+# perfect).  stage1: reads e, u~(3), u~prev(3), pi~(10), T(4); writes e', u~'(3),
+# pi~'(10), T'(4).  stage2_pi: reads e', u~'(3), pi~'(10), e, u~(3), u~prev(3),
+# pi~(10); writes pi~(10).  stage2_T: reads e', u~'(3), pi~(10), T(4), T'(4);
+# writes T(4), e(1), u~(3).
+BYTES_PER_CELL = {"stage1": (21 + 18) * 8, "stage2_pi": (31 + 10) * 8, "stage2_T": (22 + 8) * 8,
+                  "first_estimate": (4 + 3) * 8, "init": 0, "reduce": 0}
+BYTES_PER_CELL_IDEAL = {"stage1": (8 + 5) * 8, "stage2_T": (8 + 4) * 8}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1802_04449_amd as K
+    from hydro_inputs import workloads as W
+
+    wl = W.hotspots_viscous(steps=args.steps)
+    p = wl.params
+    g = K.Hydro(**p)
+    g.set_eos(wl.eos)
+    g.set_initial(wl.ic)
+    g.step(args.warmup)
+    torch.cuda.synchronize()
+
+    K.ktmi_set_timing(g.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    names = K.ktmi_kernel_names()
+    per_kernel = {}
+    for k, n in enumerate(names):
+        tot, cnt = K.ktmi_timing(g.h, k)
+        if cnt:
+            per_kernel[n] = dict(total_ms=tot, launches=cnt, avg_ms=tot / cnt)
+    K.ktmi_set_timing(g.h, False)
+    diag = g.diag()
+
+    dt = t1 - t0
+    ncell = wl.ncell
+    value = ncell * args.steps / dt
+    dom = max(per_kernel, key=lambda n: per_kernel[n]["total_ms"])
+    bpc = BYTES_PER_CELL if p["viscous"] else BYTES_PER_CELL_IDEAL
+    bytes_launch = bpc[dom] * ncell
+    achieved = bytes_launch / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
+    step_bytes = sum(bpc.get(n, 0) * ncell * per_kernel[n]["launches"] for n in per_kernel)
+    out = {
+        "metric": "cell-updates/s of viscous KT+RK2 step, plain FP64 vs batched/learned/FP32 @1e-6",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "nx": p["nx"], "ny": p["ny"], "ne": p["ne"],
+                   "dx": p["dx"], "deta": p["de"], "tau0": p["tau0"], "h": p["h"],
+                   "eta_over_s": p["etas"], "ic": "200 Gaussian hotspots, seed 1",
+                   "eos": "1555-row synthetic crossover table", "path": "plain FP64"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_cell": bpc[dom]},
+        "kernels": {n: round(v["avg_ms"], 4) for n, v in per_kernel.items()},
+        "step_hbm_GBs_algorithmic": step_bytes / dt / 1e9,
+        "diag": {k: diag[k] for k in ("tau", "eps_max", "newton_mean", "newton_max", "clamps",
+                                      "nonconv", "nans", "vacuum")},
+        "context": {"paper_table_II_viscous_gpu_cell_updates_per_s": 1.69e7,
+                    "paper_hardware": "AMD FirePro S9150, 385x385x115 cells"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, steps):
+    """The CPU oracle as it stands, on the same grid and initial state, all host
+    threads, `steps` steps (the set-up and first-step estimate are not timed)."""
+    import oracle as O
+    from tests import gpu_common as G
+
+    threads = min(16, os.cpu_count() or 1)
+    O.set_threads(threads)
+    o = O.Oracle(G.oracle_params(wl.params), eos=wl.eos)
+    o.set_initial(wl.ic)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": wl.ncell * steps / dt, "unit": "cell-updates/s", "cores": O.max_threads(),
+            "kind": "oracle",
+            "sample": f"full {wl.params['nx']}x{wl.params['ny']}x{wl.params['ne']} grid, first "
+                      f"{steps} steps from the same initial state ({dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

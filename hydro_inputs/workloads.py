@@ -1,0 +1,72 @@
+"""Named synthetic workloads (grid, physics parameters, seeded initial state).
+
+These stand in for the paper's event-by-event inputs (Trento/AMPT initial
+states and lattice EoS tables are not available): sizes, spacings and value
+distributions follow the benchmark configurations of the hot path.  Nothing
+here computes any part of the step.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+from . import eos as E
+from . import ics
+
+
+@dataclass
+class Workload:
+    name: str
+    params: dict                 # nx, ny, ne, dx, dy, de, tau0, h, etas, viscous, cartesian
+    eos: object                  # "conformal" or an EosTable
+    steps: int
+    ic: dict = None              # primitive initial state, or
+    T4: object = None            # conserved initial state (4, nx, ny, ne)
+    note: str = ""
+
+    @property
+    def ncell(self):
+        p = self.params
+        return p["nx"] * p["ny"] * p["ne"]
+
+    @property
+    def grid(self):
+        p = self.params
+        return ics.Grid(p["nx"], p["ny"], p["ne"], p["dx"], p["dy"], p["de"])
+
+
+def _params(nx, ny, ne, dx, dy, de, tau0, h, etas=0.0, viscous=False, cartesian=False):
+    return dict(nx=nx, ny=ny, ne=ne, dx=dx, dy=dy, de=de, tau0=tau0, h=h, etas=etas,
+                viscous=int(viscous), cartesian=int(cartesian))
+
+
+def gubser_ideal_33(steps: int = 50) -> Workload:
+    """Ideal conformal hydro on 33x33x17 (dx = dy = deta = 0.3), tau0 = 1 fm,
+    h = 0.02 fm, initial state = ideal Gubser flow (q = 1/fm, peak T = 0.4 GeV)."""
+    p = _params(33, 33, 17, 0.3, 0.3, 0.3, 1.0, 0.02)
+    g = ics.Grid(33, 33, 17, 0.3, 0.3, 0.3)
+    return Workload("gubser_ideal_33x33x17", p, "conformal", steps, ic=ics.gubser_ideal(g, 1.0))
+
+
+def hotspots_viscous(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps=200, seed=1,
+                     etas=0.08) -> Workload:
+    """Viscous hydro, eta/s = 0.08, tau0 = 0.6 fm, h = 0.01 fm, 200 Gaussian hotspots
+    (sigma 0.5 fm, Gamma(1) weights) in a 6.5 fm Woods-Saxon disk times an eta_s
+    plateau (|eta_s| < 2, Gaussian tails sigma 1.3), peak e = 55 GeV/fm^3, zero
+    initial flow and shear stress, 1555-row synthetic crossover EoS."""
+    p = _params(nx, ny, ne, dx, dy, de, 0.6, 0.01, etas=etas, viscous=True)
+    g = ics.Grid(nx, ny, ne, dx, dy, de)
+    return Workload(f"hotspots_viscous_{nx}x{ny}x{ne}", p, E.cached_synthetic_table(), steps,
+                    ic=ics.hotspots(g, seed=seed))
+
+
+def hotspots_minijets(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps=200, seed=2,
+                      etas=0.08) -> Workload:
+    """As hotspots_viscous plus 400 mini-jet partons (p_T ~ Exp(2 GeV)) deposited into
+    T~^{tau mu}; the initial flow follows from the root solve."""
+    p = _params(nx, ny, ne, dx, dy, de, 0.6, 0.01, etas=etas, viscous=True)
+    g = ics.Grid(nx, ny, ne, dx, dy, de)
+    return Workload(f"hotspots_minijets_{nx}x{ny}x{ne}", p, E.cached_synthetic_table(), steps,
+                    T4=ics.hotspots_with_minijets(g, 0.6, seed))
+
+
+C1_FULL = dict(nx=201, ny=201, ne=105)

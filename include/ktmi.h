@@ -1,0 +1,162 @@
+/*
+ * ktmi.h -- C ABI of libktmi, an MI355X (gfx950) library for the hot path of
+ * CLVisc (arXiv:1802.04449): one RK2 step of the Kurganov-Tadmor central scheme
+ * for (3+1)D second-order viscous hydrodynamics in Milne coordinates
+ * (tau, x, y, eta_s).
+ *
+ * What one step computes (Sec. II eqns. Ttilde, pitilde, Ipi; Sec. III eqns.
+ * common_form, kt, flux_out and the RK2 predictor-corrector flow chart):
+ *   - KT flux divergence of T~^{tau mu} = tau T^{tau mu} and u~^tau pi~^{mu nu}
+ *     from a minmod piecewise-linear reconstruction of the primitive fields,
+ *   - the geometric source S_T and the Israel-Stewart source S_pi,
+ *   - predictor (T', pi' with u* = 2u^n - u^{n-1}), then corrector (pi^{n+1}
+ *     first, then T^{n+1} with S_T evaluated on pi^{n+1}),
+ *   - after each stage the per-cell root solve T_ideal = T - pi -> (e, u~)
+ *     with a tabulated or ideal-gas EoS (Sec. III, EoS options),
+ *   - the energy-density cutoff (Sec. V.A), diagnostics reductions (App. A.2).
+ * Tilde variables as in Sec. II: u~ = (u^tau, u^x, u^y, tau u^eta),
+ * pi~ components ordered (tt, tx, ty, te, xx, xy, xe, yy, ye, ee).
+ * Units: e, P in GeV/fm^3; T in GeV; lengths and tau in fm.
+ *
+ * Conventions for every call:
+ *   - Return value 0 on success; a negative KTMI_E* code on error, with a
+ *     message available from ktmi_last_error(h).  No exception crosses the ABI.
+ *   - Field arrays are device pointers to FP64 data of nx*ny*ne elements in C
+ *     order (x slowest, eta fastest) unless a call says "host".
+ *   - The library never allocates device memory: the caller supplies one
+ *     workspace of ktmi_workspace_bytes() bytes (ktmi_bind) and owns it; the
+ *     library owns its layout.  All work is enqueued on the bound HIP stream;
+ *     calls marked "synchronizes" wait for that stream.
+ *   - A handle is not thread safe; distinct handles are independent.
+ */
+#ifndef KTMI_H
+#define KTMI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    KTMI_OK = 0,
+    KTMI_EINVAL = -22, /* bad argument or descriptor */
+    KTMI_ESTATE = -5,  /* call out of order (e.g. step before bind / initial state) */
+    KTMI_EHIP = -71    /* a HIP runtime call failed; see ktmi_last_error */
+};
+
+enum { KTMI_FP64 = 0, KTMI_MIXED = 1 };                               /* precision */
+enum { KTMI_GUESS_PREV = 0, KTMI_GUESS_COLD = 1 };                    /* root-solve start */
+
+/* Field ids for ktmi_read. */
+enum {
+    KTMI_F_EPS = 0,   /* e */
+    KTMI_F_UX = 1,    /* u~^x, u~^y, u~^eta: 1..3 */
+    KTMI_F_PI = 4,    /* pi~ components: 4..13 in the order above */
+    KTMI_F_T = 14,    /* T~^{tau mu}: 14..17 */
+    KTMI_F_UPREV = 18 /* u~ at the previous time level: 18..20 */
+};
+
+typedef struct ktmi_desc {
+    int nx, ny, ne;      /* cells per axis, each >= 1 */
+    double dx, dy, de;   /* spacings in fm, fm, and units of eta_s */
+    double tau0, h;      /* initial proper time and time step (fm) */
+    double etas;         /* eta_v / s; must be > 0 when viscous */
+    int viscous;         /* 1: evolve the 10 pi~ components; 0: ideal (pi~ = 0) */
+    int cartesian;       /* 1: tau == 1 in every metric factor, no Milne sources */
+    double eps_cut;      /* energy-density cutoff, 1e-7 GeV/fm^3 in the paper */
+    double theta;        /* generalised minmod parameter in [1, 2] */
+    double newton_tol;   /* relative tolerance of the root solve */
+    int newton_maxit;    /* iteration cap of the root solve */
+    double pi_reg;       /* cap on sqrt(|pi~:pi~|)/(e+P); <= 0 disables */
+    int precision;       /* KTMI_FP64 */
+    int guess;           /* KTMI_GUESS_* */
+} ktmi_desc;
+
+typedef struct ktmi_diagnostics {
+    double tau;          /* proper time after the last step */
+    long step;           /* steps taken since the initial state */
+    double eps_max;      /* max e after the last step (App. A.2 stop criterion) */
+    double sum_Ttt;      /* sum of T~^{tau tau} dx dy deta after the last step */
+    double geo_src;      /* accumulated sum of h/2 (S_T1 + S_T2)^tau dx dy deta */
+    double max_cfl;      /* max over faces and stages of c h / Delta */
+    double newton_mean;  /* mean iterations per root solve (incl. the polish step) */
+    long newton_max;     /* max iterations of one root solve */
+    long solves, fallbacks, nonconv, nans, vacuum, clamps; /* counters */
+} ktmi_diagnostics;
+
+typedef struct ktmi_handle ktmi_handle;
+
+/* Fills d with the defaults: cutoff 1e-7, theta 1.8, tolerance 1e-12, 100
+ * iterations, regulator 1.0, FP64, previous-stage guess.  Sizes are zero. */
+void ktmi_desc_default(ktmi_desc *d);
+
+/* Validates d and creates a handle (host memory only).  KTMI_EINVAL if a size
+ * is < 1, a spacing, tau0 or h is not > 0, or viscous with etas <= 0. */
+int ktmi_create(const ktmi_desc *d, ktmi_handle **out);
+
+/* Bytes of device workspace the handle needs (0 if d is invalid). */
+size_t ktmi_workspace_bytes(const ktmi_desc *d);
+
+/* Binds caller-owned device memory (>= ktmi_workspace_bytes, 256-byte aligned)
+ * and a hipStream_t (passed as void*; NULL = default stream).  May be called
+ * again to move the handle to another stream; the workspace must not change
+ * after an initial state is set. */
+int ktmi_bind(ktmi_handle *h, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/* Ideal-gas EoS P = e/3 (EOSI), T = (e/c_sb)^(1/4).  Sec. III, EoS options. */
+int ktmi_set_eos_conformal(ktmi_handle *h, double c_sb);
+
+/* Uniform-e table: row i holds (e0 + i de, P[i], T[i], cs2[i]); host arrays of
+ * n >= 2 rows, copied to the workspace.  Linear interpolation between rows; past
+ * the last row P continues with the last slope, cs2 is held and
+ * T = T_last ((e+P)/(e_last+P_last))^(1/4).  KTMI_EINVAL if n < 2 or de <= 0. */
+int ktmi_set_eos_table(ktmi_handle *h, double e0, double de, int n, const double *P,
+                       const double *T, const double *cs2);
+
+/* Initial primitive state (device arrays): e, u~x, u~y, u~eta and optionally 10
+ * pi~ blocks (pi10 may be NULL for pi~ = 0; ignored in ideal mode).  Applies the
+ * cutoff, forms T~^{tau mu}, and estimates u~^{-1} by one ideal forward-Euler
+ * step (Sec. III: ideal hydrodynamics estimates u*1 on the first step).
+ * Resets the diagnostics. */
+int ktmi_set_initial_primitive(ktmi_handle *h, const double *e, const double *ux,
+                               const double *uy, const double *ue, const double *pi10);
+
+/* Initial conserved state: 4 device blocks of T~^{tau mu} and optional pi~;
+ * the root solve (starting from E) yields (e, u~).  Then as above. */
+int ktmi_set_initial_conserved(ktmi_handle *h, const double *T4, const double *pi10);
+
+/* Enqueues n RK2 steps on the bound stream (asynchronous).  Device-side
+ * failures (NaN, non-converged solves) are counted in the diagnostics, not
+ * returned here. */
+int ktmi_step(ktmi_handle *h, int n);
+
+/* Copies one field (ids above) to device array dst (stream-ordered, async). */
+int ktmi_read(ktmi_handle *h, int field, double *dst);
+
+/* Diagnostics accumulated since the initial state.  Synchronizes. */
+int ktmi_diag(ktmi_handle *h, ktmi_diagnostics *out);
+
+/* Per-kernel timing with HIP events recorded on the bound stream around every
+ * launch (on = 1) or off (0; the default).  Turning it on clears the totals. */
+int ktmi_set_timing(ktmi_handle *h, int on);
+
+/* Kernel names of the step, in the order used by ktmi_timing. */
+int ktmi_kernel_count(void);
+const char *ktmi_kernel_name(int k);
+
+/* Total milliseconds and launch count of kernel k since timing was turned on.
+ * Synchronizes. */
+int ktmi_timing(ktmi_handle *h, int k, double *total_ms, long *launches);
+
+/* Message of the last error on h (or of the last failed ktmi_create if h is
+ * NULL).  Valid until the next call on h. */
+const char *ktmi_last_error(const ktmi_handle *h);
+
+/* Releases host resources; the caller frees the workspace afterwards. */
+void ktmi_destroy(ktmi_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KTMI_H */

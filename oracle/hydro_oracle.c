@@ -138,7 +138,7 @@ static void eos_eval(const orc_eos *q, double e, double *P, double *T, double *c
     }
     int n = q->n;
     double x = (e - q->e0) / q->de;
-    if (x < 0.0) x = 0.0;
+    if (!(x >= 0.0)) x = 0.0; /* also maps NaN to the first row */
     double slope_last = (q->P[n - 1] - q->P[n - 2]) / q->de;
     if (x >= (double)(n - 1)) {
         double elast = q->e0 + (n - 1) * q->de;
@@ -654,13 +654,13 @@ static void cells_con2prim(orc *S, double *const T[4], double *const piq[10], do
     /* serial bookkeeping */
     for (long c = 0; c < S->ncell; ++c) {
         int fl = S->flag_cell[c];
-        if ((fl & C2P_VAC) && it_cell_zero(S->it_cell[c])) continue; /* no iteration ran */
+        if (fl & C2P_NAN) S->d.nans++;
+        if (it_cell_zero(S->it_cell[c])) continue; /* decided before iterating */
         S->d.solves++;
         S->sum_iters += S->it_cell[c];
         if (S->it_cell[c] > S->d.newton_max) S->d.newton_max = S->it_cell[c];
         if (fl & C2P_FALLBACK) S->d.fallbacks++;
         if (fl & C2P_NONCONV) S->d.nonconv++;
-        if (fl & C2P_NAN) S->d.nans++;
         if (fl & C2P_CLAMP) S->d.clamps++;
     }
 }
@@ -1003,11 +1003,6 @@ static void one_step(orc *S) {
                 if (S->e[id] == 0.0) {
                     vac++;
                     for (int m = 0; m < 10; ++m) S->pi[m][id] = 0.0;
-                } else if (visc && S->p.pi_reg > 0.0) {
-                    double pn[10];
-                    for (int m = 0; m < 10; ++m) pn[m] = S->pi[m][id];
-                    regulate_pi(S, S->e[id], pn);
-                    for (int m = 0; m < 10; ++m) S->pi[m][id] = pn[m];
                 }
                 if (S->e[id] > emax) emax = S->e[id];
                 sumT += S->T[0][id];

@@ -1,0 +1,250 @@
+"""Python binding of libktmi (include/ktmi.h): one RK2 step of the Kurganov-Tadmor
+scheme for (3+1)D viscous hydrodynamics in Milne coordinates on MI355X.
+
+The functions ktmi_* mirror the C ABI one to one and only marshal arguments.
+PyTorch supplies device memory (the workspace and field tensors) and the HIP
+stream.  Every step of the method runs in the HIP kernels of libktmi.so; there is
+no CPU fallback: if the library is missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libktmi.so")
+
+KTMI_OK, KTMI_EINVAL, KTMI_ESTATE, KTMI_EHIP = 0, -22, -5, -71
+KTMI_FP64, KTMI_MIXED = 0, 1
+KTMI_GUESS_PREV, KTMI_GUESS_COLD = 0, 1
+KTMI_F_EPS, KTMI_F_UX, KTMI_F_PI, KTMI_F_T, KTMI_F_UPREV = 0, 1, 4, 14, 18
+
+FIELDS = {"eps": 0, "ux": 1, "uy": 2, "ue": 3}
+FIELDS.update({f"pi{m}": 4 + m for m in range(10)})
+FIELDS.update({f"T{m}": 14 + m for m in range(4)})
+FIELDS.update({"uprev_x": 18, "uprev_y": 19, "uprev_e": 20})
+
+
+class ktmi_desc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("ne", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("de", C.c_double),
+                ("tau0", C.c_double), ("h", C.c_double), ("etas", C.c_double),
+                ("viscous", C.c_int), ("cartesian", C.c_int),
+                ("eps_cut", C.c_double), ("theta", C.c_double), ("newton_tol", C.c_double),
+                ("newton_maxit", C.c_int), ("pi_reg", C.c_double), ("precision", C.c_int),
+                ("guess", C.c_int)]
+
+
+class ktmi_diagnostics(C.Structure):
+    _fields_ = [("tau", C.c_double), ("step", C.c_long), ("eps_max", C.c_double),
+                ("sum_Ttt", C.c_double), ("geo_src", C.c_double), ("max_cfl", C.c_double),
+                ("newton_mean", C.c_double), ("newton_max", C.c_long), ("solves", C.c_long),
+                ("fallbacks", C.c_long), ("nonconv", C.c_long), ("nans", C.c_long),
+                ("vacuum", C.c_long), ("clamps", C.c_long)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -c "
+                          "'import __graft_entry__ as g; g.build()' (no CPU fallback exists)")
+    lib = C.CDLL(LIB_PATH)
+    vp, dp, sz = C.c_void_p, C.POINTER(C.c_double), C.c_size_t
+    sig = {
+        "ktmi_desc_default": (None, [C.POINTER(ktmi_desc)]),
+        "ktmi_create": (C.c_int, [C.POINTER(ktmi_desc), C.POINTER(vp)]),
+        "ktmi_workspace_bytes": (sz, [C.POINTER(ktmi_desc)]),
+        "ktmi_bind": (C.c_int, [vp, vp, sz, vp]),
+        "ktmi_set_eos_conformal": (C.c_int, [vp, C.c_double]),
+        "ktmi_set_eos_table": (C.c_int, [vp, C.c_double, C.c_double, C.c_int, dp, dp, dp]),
+        "ktmi_set_initial_primitive": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "ktmi_set_initial_conserved": (C.c_int, [vp, vp, vp]),
+        "ktmi_step": (C.c_int, [vp, C.c_int]),
+        "ktmi_read": (C.c_int, [vp, C.c_int, vp]),
+        "ktmi_diag": (C.c_int, [vp, C.POINTER(ktmi_diagnostics)]),
+        "ktmi_set_timing": (C.c_int, [vp, C.c_int]),
+        "ktmi_kernel_count": (C.c_int, []),
+        "ktmi_kernel_name": (C.c_char_p, [C.c_int]),
+        "ktmi_timing": (C.c_int, [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_long)]),
+        "ktmi_last_error": (C.c_char_p, [vp]),
+        "ktmi_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class KtmiError(RuntimeError):
+    pass
+
+
+def _check(rc, h=None):
+    if rc != KTMI_OK:
+        msg = lib.ktmi_last_error(h)
+        raise KtmiError(f"ktmi error {rc}: {msg.decode() if msg else ''}")
+
+
+# ---- one-to-one wrappers of the C ABI ------------------------------------
+def ktmi_desc_default() -> ktmi_desc:
+    d = ktmi_desc()
+    lib.ktmi_desc_default(C.byref(d))
+    return d
+
+
+def ktmi_create(desc: ktmi_desc):
+    h = C.c_void_p()
+    _check(lib.ktmi_create(C.byref(desc), C.byref(h)))
+    return h
+
+
+def ktmi_workspace_bytes(desc: ktmi_desc) -> int:
+    return int(lib.ktmi_workspace_bytes(C.byref(desc)))
+
+
+def ktmi_bind(h, dev_ptr: int, nbytes: int, stream_ptr: int):
+    _check(lib.ktmi_bind(h, C.c_void_p(dev_ptr), nbytes, C.c_void_p(stream_ptr)), h)
+
+
+def ktmi_set_eos_conformal(h, c_sb: float):
+    _check(lib.ktmi_set_eos_conformal(h, float(c_sb)), h)
+
+
+def ktmi_set_eos_table(h, e0, de, P, T, cs2):
+    """P, T, cs2: contiguous float64 host numpy arrays of equal length."""
+    import numpy as np
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (P, T, cs2)]
+    ptrs = [a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs]
+    _check(lib.ktmi_set_eos_table(h, float(e0), float(de), int(arrs[0].size), *ptrs), h)
+
+
+def ktmi_set_initial_primitive(h, e_ptr, ux_ptr, uy_ptr, ue_ptr, pi_ptr=None):
+    _check(lib.ktmi_set_initial_primitive(h, C.c_void_p(e_ptr), C.c_void_p(ux_ptr),
+                                          C.c_void_p(uy_ptr), C.c_void_p(ue_ptr),
+                                          C.c_void_p(pi_ptr) if pi_ptr else None), h)
+
+
+def ktmi_set_initial_conserved(h, T_ptr, pi_ptr=None):
+    _check(lib.ktmi_set_initial_conserved(h, C.c_void_p(T_ptr),
+                                          C.c_void_p(pi_ptr) if pi_ptr else None), h)
+
+
+def ktmi_step(h, n: int):
+    _check(lib.ktmi_step(h, int(n)), h)
+
+
+def ktmi_read(h, field: int, dst_ptr: int):
+    _check(lib.ktmi_read(h, int(field), C.c_void_p(dst_ptr)), h)
+
+
+def ktmi_diag(h) -> dict:
+    d = ktmi_diagnostics()
+    _check(lib.ktmi_diag(h, C.byref(d)), h)
+    return {k: getattr(d, k) for k, _ in ktmi_diagnostics._fields_}
+
+
+def ktmi_set_timing(h, on: bool):
+    _check(lib.ktmi_set_timing(h, int(bool(on))), h)
+
+
+def ktmi_kernel_names():
+    return [lib.ktmi_kernel_name(k).decode() for k in range(lib.ktmi_kernel_count())]
+
+
+def ktmi_timing(h, k: int):
+    t = C.c_double()
+    n = C.c_long()
+    _check(lib.ktmi_timing(h, int(k), C.byref(t), C.byref(n)), h)
+    return t.value, n.value
+
+
+def ktmi_destroy(h):
+    lib.ktmi_destroy(h)
+
+
+# ---- convenience object: torch-owned memory around one handle -------------
+class Hydro:
+    """One grid on the GPU.  Owns a torch workspace tensor and a handle."""
+
+    def __init__(self, device="cuda", stream=None, **desc_kw):
+        import torch
+        self.torch = torch
+        d = ktmi_desc_default()
+        for k, v in desc_kw.items():
+            if not hasattr(d, k):
+                raise KeyError(k)
+            setattr(d, k, v)
+        self.desc = d
+        self.shape = (d.nx, d.ny, d.ne)
+        self.ncell = d.nx * d.ny * d.ne
+        self.h = ktmi_create(d)
+        nbytes = ktmi_workspace_bytes(d)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=self.device)
+        ptr = self.ws.data_ptr()
+        aligned = (ptr + 255) // 256 * 256
+        ktmi_bind(self.h, aligned, nbytes, self.stream.cuda_stream)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            try:
+                self.torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            ktmi_destroy(h)
+            self.h = None
+
+    def set_eos(self, eos):
+        if eos is None or (isinstance(eos, str) and eos == "conformal"):
+            from hydro_inputs.eos import C_SB
+            ktmi_set_eos_conformal(self.h, C_SB)
+        else:
+            ktmi_set_eos_table(self.h, eos.eps0, eos.deps, eos.P, eos.T, eos.cs2)
+
+    def _dev(self, a):
+        t = self.torch.as_tensor(a, dtype=self.torch.float64)
+        return t.to(self.device).contiguous()
+
+    def set_initial(self, ic: dict):
+        with self.torch.cuda.stream(self.stream):
+            keep = [self._dev(ic[k]).reshape(-1) for k in ("eps", "ux", "uy", "ue")]
+            pi = ic.get("pi")
+            pit = None if pi is None else self._dev(pi).reshape(10, -1)
+            ktmi_set_initial_primitive(self.h, *[t.data_ptr() for t in keep],
+                                       pit.data_ptr() if pit is not None else None)
+            self.stream.synchronize()
+
+    def set_initial_conserved(self, T4, pi=None):
+        with self.torch.cuda.stream(self.stream):
+            Tt = self._dev(T4).reshape(4, -1)
+            pit = None if pi is None else self._dev(pi).reshape(10, -1)
+            ktmi_set_initial_conserved(self.h, Tt.data_ptr(),
+                                       pit.data_ptr() if pit is not None else None)
+            self.stream.synchronize()
+
+    def step(self, n=1):
+        ktmi_step(self.h, n)
+
+    def read(self, name, out=None):
+        """Field as a device tensor of shape (nx, ny, ne) (stream-ordered)."""
+        if out is None:
+            out = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
+        fid = FIELDS[name] if isinstance(name, str) else int(name)
+        ktmi_read(self.h, fid, out.data_ptr())
+        return out
+
+    def read_numpy(self, name):
+        t = self.read(name)
+        self.stream.synchronize()
+        return t.cpu().numpy()
+
+    def fields(self):
+        return {k: self.read_numpy(k) for k in FIELDS}
+
+    def diag(self):
+        return ktmi_diag(self.h)

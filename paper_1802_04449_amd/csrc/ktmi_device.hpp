@@ -1,0 +1,266 @@
+// ktmi_device.hpp -- per-cell device math of the KT + RK2 viscous hydro step
+// (arXiv:1802.04449, Secs. II-III) for gfx950: EoS lookup, root solve,
+// limiter, local speed, side fluxes, velocity gradients and the IS source.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ktmi {
+
+constexpr double kHbarc = 0.1973269804;  // GeV fm
+
+// Parameters copied by value into every launch (kernel argument segment).
+struct StepParams {
+  int nx, ny, ne, ncell;
+  double dx, dy, de;
+  double h;
+  double etas;
+  double eps_cut, theta, newton_tol, pi_reg;
+  int newton_maxit;
+  int guess_cold;
+};
+
+struct EosDev {
+  int kind;  // 0 ideal gas, 1 uniform table
+  int n;
+  double c_sb, e0, de;
+  const double* P;
+  const double* T;
+  const double* cs2;
+};
+
+// Root-solve outcome flags (counted in the diagnostics).
+enum : int { kFallback = 1, kNonconv = 2, kNan = 4, kVac = 8, kClamp = 16 };
+
+// ---------------------------------------------------------------------------
+// EoS lookup (Sec. III, EoS options).  The table is uniform in e; values are
+// linear between rows; past the last row P keeps the last slope, cs2 is held
+// and T scales as ((e+P)/(e_last+P_last))^(1/4).  e < 0 is read as 0.
+// ---------------------------------------------------------------------------
+struct EosSeg {
+  int i;       // row index of the segment (or n-1 past the end)
+  double f;    // position inside the segment
+  bool beyond;
+};
+
+__device__ __forceinline__ EosSeg eos_seg(const EosDev& q, double e) {
+  EosSeg s;
+  double x = (e - q.e0) / q.de;
+  x = x >= 0.0 ? x : 0.0;  // also maps NaN to the first row
+  s.beyond = x >= (double)(q.n - 1);
+  const double xc = s.beyond ? (double)(q.n - 2) : x;  // keeps the index in [0, n-2]
+  int i = (int)floor(xc);
+  i = i > q.n - 2 ? q.n - 2 : (i < 0 ? 0 : i);
+  s.i = i;
+  s.f = xc - (double)i;
+  return s;
+}
+
+// P and cs2 (flux side states).
+__device__ __forceinline__ void eos_p_cs2(const EosDev& q, double e, double& P, double& cs2) {
+  e = e > 0.0 ? e : 0.0;
+  if (q.kind == 0) {
+    P = e * (1.0 / 3.0);
+    cs2 = 1.0 / 3.0;
+    return;
+  }
+  EosSeg s = eos_seg(q, e);
+  const int n = q.n;
+  if (s.beyond) {
+    const double slope = (q.P[n - 1] - q.P[n - 2]) / q.de;
+    const double elast = q.e0 + (double)(n - 1) * q.de;
+    P = q.P[n - 1] + (e - elast) * slope;
+    cs2 = q.cs2[n - 1];
+    return;
+  }
+  const double p0 = q.P[s.i], p1 = q.P[s.i + 1];
+  const double c0 = q.cs2[s.i], c1 = q.cs2[s.i + 1];
+  P = p0 + s.f * (p1 - p0);
+  cs2 = c0 + s.f * (c1 - c0);
+}
+
+// P and the segment slope dP/de (root solve).
+__device__ __forceinline__ void eos_p_dp(const EosDev& q, double e, double& P, double& dP) {
+  e = e > 0.0 ? e : 0.0;
+  if (q.kind == 0) {
+    P = e * (1.0 / 3.0);
+    dP = 1.0 / 3.0;
+    return;
+  }
+  EosSeg s = eos_seg(q, e);
+  const int n = q.n;
+  if (s.beyond) {
+    dP = (q.P[n - 1] - q.P[n - 2]) / q.de;
+    const double elast = q.e0 + (double)(n - 1) * q.de;
+    P = q.P[n - 1] + (e - elast) * dP;
+    return;
+  }
+  const double p0 = q.P[s.i], p1 = q.P[s.i + 1];
+  P = p0 + s.f * (p1 - p0);
+  dP = (p1 - p0) / q.de;
+}
+
+// P and T (viscous source).
+__device__ __forceinline__ void eos_p_t(const EosDev& q, double e, double& P, double& T) {
+  e = e > 0.0 ? e : 0.0;
+  if (q.kind == 0) {
+    P = e * (1.0 / 3.0);
+    T = sqrt(sqrt(e / q.c_sb));
+    return;
+  }
+  EosSeg s = eos_seg(q, e);
+  const int n = q.n;
+  if (s.beyond) {
+    const double slope = (q.P[n - 1] - q.P[n - 2]) / q.de;
+    const double elast = q.e0 + (double)(n - 1) * q.de;
+    P = q.P[n - 1] + (e - elast) * slope;
+    T = q.T[n - 1] * sqrt(sqrt((e + P) / (elast + q.P[n - 1])));
+    return;
+  }
+  const double p0 = q.P[s.i], p1 = q.P[s.i + 1];
+  const double t0 = q.T[s.i], t1 = q.T[s.i + 1];
+  P = p0 + s.f * (p1 - p0);
+  T = t0 + s.f * (t1 - t0);
+}
+
+__device__ __forceinline__ double eos_p(const EosDev& q, double e) {
+  double P, c;
+  eos_p_cs2(q, e, P, c);
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// Root solve (Sec. III flow chart: T_ideal = T - pi -> e, u).  With
+// K = T~^{tau .}/tau - pi~^{tau .}, E = K^tau, M = |K|, the rest-frame energy
+// density is the unique root of f(e) = e - E + M^2/(E + P(e)) on
+// [max(0, E - M^2/E), E].  Safeguarded Newton (bisection when a step leaves the
+// bracket) to |de| <= tol e, then one more Newton step; the cutoff applies to
+// the root.  Velocity: u~^i = K^i / sqrt((E+P)(e+P)).
+// ---------------------------------------------------------------------------
+struct Prim {
+  double e, u1, u2, u3;
+};
+
+__device__ __forceinline__ Prim vacuum() { return Prim{0.0, 0.0, 0.0, 0.0}; }
+
+__device__ inline Prim con2prim(const EosDev& q, const StepParams& p, double E, double K1,
+                                double K2, double K3, double guess, int& iters, int& flags) {
+  iters = 0;
+  flags = 0;
+  if (isnan(E) || isnan(K1) || isnan(K2) || isnan(K3)) {
+    flags = kNan | kVac;
+    return vacuum();
+  }
+  if (!(E >= p.eps_cut)) {
+    flags = kVac;
+    return vacuum();
+  }
+  double M2 = K1 * K1 + K2 * K2 + K3 * K3;
+  const double Mmax = (1.0 - 1e-10) * E;
+  if (M2 > Mmax * Mmax) {
+    const double s = Mmax / sqrt(M2);
+    K1 *= s;
+    K2 *= s;
+    K3 *= s;
+    M2 = K1 * K1 + K2 * K2 + K3 * K3;
+    flags |= kClamp;
+  }
+  double lo = E - M2 / E;
+  lo = lo < 0.0 ? 0.0 : lo;
+  double hi = E;
+  const double lo0 = lo, hi0 = hi;
+  double x = guess;
+  if (!(x >= lo)) x = lo;
+  if (x > hi) x = hi;
+  bool conv = false;
+  int it;
+  for (it = 1; it <= p.newton_maxit; ++it) {
+    if (hi < p.eps_cut) {
+      iters = it;
+      flags |= kVac;
+      return vacuum();
+    }
+    double P, dP;
+    eos_p_dp(q, x, P, dP);
+    const double w = E + P;
+    const double f = x - E + M2 / w;
+    const double df = 1.0 - M2 * dP / (w * w);
+    if (f == 0.0) {
+      conv = true;
+      break;
+    }
+    if (f > 0.0)
+      hi = x;
+    else
+      lo = x;
+    double xn = x - f / df;
+    if (!(xn >= lo && xn <= hi)) {
+      xn = 0.5 * (lo + hi);
+      flags |= kFallback;
+    }
+    const double step = fabs(xn - x);
+    x = xn;
+    if (step <= p.newton_tol * x) {
+      conv = true;
+      break;
+    }
+  }
+  if (!conv) {
+    flags |= kNonconv;
+    it = p.newton_maxit;
+  }
+  {
+    double P, dP;
+    eos_p_dp(q, x, P, dP);
+    const double w = E + P;
+    const double f = x - E + M2 / w;
+    const double df = 1.0 - M2 * dP / (w * w);
+    const double xp = x - f / df;
+    if (xp >= lo0 && xp <= hi0) x = xp;
+  }
+  iters = it + 1;
+  if (!(x >= p.eps_cut)) {
+    flags |= kVac;
+    return vacuum();
+  }
+  const double P = eos_p(q, x);
+  const double inv = 1.0 / sqrt((E + P) * (x + P));
+  return Prim{x, K1 * inv, K2 * inv, K3 * inv};
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction and the KT local speed (Sec. III, eqs. kt and flux_out).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double minmod3(double a, double b, double c) {
+  if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+  if (a < 0.0 && b < 0.0 && c < 0.0) return fmax(a, fmax(b, c));
+  return 0.0;
+}
+
+__device__ __forceinline__ double mm_slope(double th, double qm, double q0, double qp) {
+  return minmod3(th * (q0 - qm), 0.5 * (qp - qm), th * (qp - q0));
+}
+
+// Largest |eigenvalue| of the ideal flux Jacobian along the face normal for a
+// state with u~ = (ut, ux, uy, ue) and sound speed squared cs2:
+// lambda = [v_d (1-cs2) +- cs sqrt((1-v^2)(1 - v^2 cs2 - v_d^2 (1-cs2)))]/(1 - v^2 cs2).
+__device__ __forceinline__ double local_speed(double ut, double ux, double uy, double ue,
+                                              double ud, double cs2) {
+  const double inv = 1.0 / ut;
+  const double vd = ud * inv;
+  const double v2 = (ux * ux + uy * uy + ue * ue) * inv * inv;
+  double disc = inv * inv * (1.0 - v2 * cs2 - vd * vd * (1.0 - cs2));
+  disc = disc < 0.0 ? 0.0 : disc;
+  const double root = sqrt(cs2) * sqrt(disc);
+  const double den = 1.0 - v2 * cs2;
+  const double a = vd * (1.0 - cs2);
+  return fmax(fabs((a + root) / den), fabs((a - root) / den));
+}
+
+// pi~ component index of the symmetric pair (mu, nu).
+__host__ __device__ constexpr int sym(int mu, int nu) {
+  return mu > nu ? sym(nu, mu)
+                 : (mu == 0 ? nu : (mu == 1 ? 3 + nu : (mu == 2 ? 5 + nu : 9)));
+}
+
+}  // namespace ktmi

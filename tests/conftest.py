@@ -17,3 +17,9 @@ def _oracle_built():
     import oracle
     oracle.load()
     yield
+
+
+def pytest_collection_finish(session):
+    # import torch during collection so the first GPU test does not pay for it
+    if any(item.get_closest_marker("gpu") for item in session.items):
+        import torch  # noqa: F401
