@@ -41,7 +41,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB five times (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "decomposition is a design, not part of this build.", file=sys.stderr)
@@ -114,6 +119,19 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 2^30 bytes, five times: rocprofv3's FETCH_SIZE and
+    WRITE_SIZE per dispatch for it calibrate the counters against known traffic."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n * 8, "repeats": 5}), flush=True)
 
 
 def cpu_baseline(wl, steps):
