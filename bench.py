@@ -41,6 +41,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--workload", default="hotspots", choices=["hotspots", "gubser_dense"],
+                    help="hotspots: the benchmark configuration; gubser_dense: the same grid and "
+                         "physics with a smooth Gubser profile that leaves no vacuum cells")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every tile shape first (on a discarded run) and use the fastest")
+    ap.add_argument("--tile", type=int, default=-1, help="tile shape index (-1: library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (counter calibration)")
     args = ap.parse_args()
@@ -58,10 +64,17 @@ def main():
     import paper_1802_04449_amd as K
     from hydro_inputs import workloads as W
 
-    wl = W.hotspots_viscous(steps=args.steps)
+    wl = (W.hotspots_viscous(steps=args.steps) if args.workload == "hotspots"
+          else W.gubser_dense_viscous(steps=args.steps))
     p = wl.params
-    g = K.Hydro(**p)
+    g = K.Hydro(tile=args.tile, **p)
     g.set_eos(wl.eos)
+    tile_times = None
+    if args.autotune:
+        # tune on a throwaway copy of the state, then start the measured run afresh
+        from paper_1802_04449_amd import autotune
+        g.set_initial(wl.ic)
+        tile, tile_times = autotune.tune(g, steps=3, use_cache=False)
     g.set_initial(wl.ic)
     g.step(args.warmup)
     torch.cuda.synchronize()
@@ -104,12 +117,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "nx": p["nx"], "ny": p["ny"], "ne": p["ne"],
                    "dx": p["dx"], "deta": p["de"], "tau0": p["tau0"], "h": p["h"],
-                   "eta_over_s": p["etas"], "ic": "200 Gaussian hotspots, seed 1",
+                   "eta_over_s": p["etas"], "ic": wl.note or "200 Gaussian hotspots, seed 1",
                    "eos": "1555-row synthetic crossover table", "path": "plain FP64"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_cell": bpc[dom]},
         "kernels": {n: round(v["avg_ms"], 4) for n, v in per_kernel.items()},
+        "tile": list(K.ktmi_tile_shape(K.ktmi_get_tile(g.h))),
+        "tile_ms_per_step": ({str(K.ktmi_tile_shape(t)): round(v, 3) for t, v in tile_times.items()}
+                             if tile_times else None),
         "step_hbm_GBs_algorithmic": step_bytes / dt / 1e9,
         "diag": {k: diag[k] for k in ("tau", "eps_max", "newton_mean", "newton_max", "clamps",
                                       "nonconv", "nans", "vacuum")},

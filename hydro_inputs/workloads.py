@@ -69,4 +69,14 @@ def hotspots_minijets(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps=20
                     T4=ics.hotspots_with_minijets(g, 0.6, seed))
 
 
+def gubser_dense_viscous(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps=200,
+                         etas=0.08) -> Workload:
+    """The benchmark grid and physics with a smooth ideal-Gubser profile (q = 1/fm,
+    evaluated at tau = 0.6 fm) instead of hotspots: no cell is vacuum."""
+    p = _params(nx, ny, ne, dx, dy, de, 0.6, 0.01, etas=etas, viscous=True)
+    g = ics.Grid(nx, ny, ne, dx, dy, de)
+    return Workload(f"gubser_dense_viscous_{nx}x{ny}x{ne}", p, E.cached_synthetic_table(), steps,
+                    ic=ics.gubser_ideal(g, 0.6), note="ideal Gubser profile at tau0, no vacuum")
+
+
 C1_FULL = dict(nx=201, ny=201, ne=105)

@@ -71,6 +71,7 @@ typedef struct ktmi_desc {
     double pi_reg;       /* cap on sqrt(|pi~:pi~|)/(e+P); <= 0 disables */
     int precision;       /* KTMI_FP64 */
     int guess;           /* KTMI_GUESS_* */
+    int tile;            /* workgroup tile shape index (ktmi_tile_shape); -1 = automatic */
 } ktmi_desc;
 
 typedef struct ktmi_diagnostics {
@@ -88,7 +89,8 @@ typedef struct ktmi_diagnostics {
 typedef struct ktmi_handle ktmi_handle;
 
 /* Fills d with the defaults: cutoff 1e-7, theta 1.8, tolerance 1e-12, 100
- * iterations, regulator 1.0, FP64, previous-stage guess.  Sizes are zero. */
+ * iterations, regulator 1.0, FP64, previous-stage guess, automatic tile.  Sizes
+ * are zero. */
 void ktmi_desc_default(ktmi_desc *d);
 
 /* Validates d and creates a handle (host memory only).  KTMI_EINVAL if a size
@@ -148,6 +150,17 @@ const char *ktmi_kernel_name(int k);
 /* Total milliseconds and launch count of kernel k since timing was turned on.
  * Synchronizes. */
 int ktmi_timing(ktmi_handle *h, int k, double *total_ms, long *launches);
+
+/* Workgroup tile shapes of the stencil kernels: each workgroup of 256 threads
+ * owns tx*ty*tz cells (x, y, eta).  Any shape gives the same results up to
+ * rounding of the diagnostics sums; the speed differs with the grid. */
+int ktmi_tile_count(void);
+int ktmi_tile_shape(int t, int *tx, int *ty, int *tz);
+
+/* Selects the tile shape used by later launches (-1 = automatic: fewest padded
+ * thread slots).  The workspace is sized for every shape. */
+int ktmi_set_tile(ktmi_handle *h, int t);
+int ktmi_get_tile(const ktmi_handle *h);
 
 /* Message of the last error on h (or of the last failed ktmi_create if h is
  * NULL).  Valid until the next call on h. */

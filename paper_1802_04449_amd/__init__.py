@@ -32,7 +32,7 @@ class ktmi_desc(C.Structure):
                 ("viscous", C.c_int), ("cartesian", C.c_int),
                 ("eps_cut", C.c_double), ("theta", C.c_double), ("newton_tol", C.c_double),
                 ("newton_maxit", C.c_int), ("pi_reg", C.c_double), ("precision", C.c_int),
-                ("guess", C.c_int)]
+                ("guess", C.c_int), ("tile", C.c_int)]
 
 
 class ktmi_diagnostics(C.Structure):
@@ -65,6 +65,11 @@ def _load():
         "ktmi_kernel_count": (C.c_int, []),
         "ktmi_kernel_name": (C.c_char_p, [C.c_int]),
         "ktmi_timing": (C.c_int, [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_long)]),
+        "ktmi_tile_count": (C.c_int, []),
+        "ktmi_tile_shape": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]),
+        "ktmi_set_tile": (C.c_int, [vp, C.c_int]),
+        "ktmi_get_tile": (C.c_int, [vp]),
         "ktmi_last_error": (C.c_char_p, [vp]),
         "ktmi_destroy": (None, [vp]),
     }
@@ -159,6 +164,24 @@ def ktmi_timing(h, k: int):
     n = C.c_long()
     _check(lib.ktmi_timing(h, int(k), C.byref(t), C.byref(n)), h)
     return t.value, n.value
+
+
+def ktmi_tile_count() -> int:
+    return int(lib.ktmi_tile_count())
+
+
+def ktmi_tile_shape(t: int):
+    a, b, c = C.c_int(), C.c_int(), C.c_int()
+    _check(lib.ktmi_tile_shape(int(t), C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def ktmi_set_tile(h, t: int):
+    _check(lib.ktmi_set_tile(h, int(t)), h)
+
+
+def ktmi_get_tile(h) -> int:
+    return int(lib.ktmi_get_tile(h))
 
 
 def ktmi_destroy(h):

@@ -2,15 +2,20 @@
 // scheme for (3+1)D viscous hydrodynamics in Milne coordinates
 // (arXiv:1802.04449; equations of Sec. II, algorithm of Sec. III).
 //
-// One step is three stencil passes over the grid (one thread per cell, fields
-// stored structure-of-arrays in FP64, eta fastest):
+// One step is three stencil passes over the grid, FP64 structure-of-arrays
+// fields with eta fastest:
 //   stage1   : R_T and R_pi at tau_n from (e, u~, pi~)^n; predictor T', pi'
 //              (u* = 2u^n - u^{n-1}); root solve -> (e', u~').
 //   stage2pi : R_pi at tau_{n+1} from (e', u~', pi'); corrector pi^{n+1}.
 //   stage2T  : R_T at tau_{n+1} from (e', u~') and pi^{n+1} (the paper's order:
 //              pi first, then T); corrector T^{n+1}; root solve -> (e, u~)^{n+1}.
-// Each pass writes per-workgroup diagnostic partials; a one-workgroup reduce
-// folds them in a fixed order, so results are bitwise reproducible.
+// Each workgroup owns a TX x TY x TZ tile of cells (one thread per cell).  For
+// every axis the workgroup evaluates each face flux of its tile exactly once
+// (one thread per face, results staged in LDS), then every cell takes the
+// difference of its two faces.  Workgroups are mapped to tiles so that each of
+// the 8 XCDs sweeps a contiguous slab of tiles (halo cells stay in that XCD's
+// L2).  Each pass writes per-workgroup diagnostic partials; a one-workgroup
+// reduce folds them in a fixed order, so results are bitwise reproducible.
 // The caller provides all device memory; nothing here allocates.
 #include <hip/hip_runtime.h>
 
@@ -18,6 +23,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -27,7 +33,7 @@
 namespace ktmi {
 
 constexpr int kBlock = 256;
-constexpr int kNP = 12;           // diagnostic partials per workgroup
+constexpr int kNP = 12;            // diagnostic partials per workgroup
 constexpr int kEosMaxRows = 8192;  // table capacity reserved in the workspace
 
 // Partial slots.  Sums: 0, 2, 3, 5-8, 10, 11.  Maxima: 1, 4, 9.
@@ -49,7 +55,7 @@ struct Fields {
   double* u1[3];
   double* pi1[10];
   double* T1[4];
-  double* partial;  // [2][nblk][kNP]
+  double* partial;  // [2][kNP][nblk]: stage1 then stage2T, slot-major
   double* acc;      // [16] accumulated diagnostics
 };
 
@@ -59,9 +65,52 @@ struct Geo {
   int cart;
 };
 
+// Tile grid of one launch.
+struct TileGrid {
+  int ntx, nty, ntz, ntiles;
+};
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// pi~ at a cell, zero where e == 0 (vacuum cells carry no shear stress).
+// Workgroups are dispatched to the 8 XCDs round robin (block b -> XCD b % 8).
+// Give XCD x a contiguous range of tile ids so neighbouring tiles share its L2.
+__device__ __forceinline__ int tile_of_block(int nb) {
+  const int b = blockIdx.x, x = b & 7, k = b >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+// Position of this thread's cell.
+struct Pos {
+  int i, j, k;     // global cell coordinates
+  int lx, ly, lz;  // coordinates inside the tile
+  int i0, j0, k0;  // tile origin
+  int c;           // flat index (valid only if active)
+  bool active;
+};
+
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ Pos cell_pos(const StepParams& p, const TileGrid& tg) {
+  Pos q;
+  const int t = tile_of_block(tg.ntiles);
+  const int tk = t % tg.ntz, r = t / tg.ntz;
+  const int tj = r % tg.nty, ti = r / tg.nty;
+  q.i0 = ti * TX;
+  q.j0 = tj * TY;
+  q.k0 = tk * TZ;
+  const int tid = threadIdx.x;
+  q.lz = tid % TZ;
+  q.ly = (tid / TZ) % TY;
+  q.lx = tid / (TZ * TY);
+  q.i = q.i0 + q.lx;
+  q.j = q.j0 + q.ly;
+  q.k = q.k0 + q.lz;
+  q.active = tid < TX * TY * TZ && q.i < p.nx && q.j < p.ny && q.k < p.ne;
+  q.c = (q.i * p.ny + q.j) * p.ne + q.k;
+  return q;
+}
+
+// pi~ at a cell: PI_SRC 0 -> 0, 1 -> zero where e == 0 (vacuum), 2 -> as stored.
 template <int PI_SRC>
 __device__ __forceinline__ double ld_pi(const double* const* pi, int m, int idx, double e) {
   if (PI_SRC == 0) return 0.0;
@@ -72,42 +121,47 @@ __device__ __forceinline__ double ld_pi(const double* const* pi, int m, int idx,
 
 // KT face flux H = [F(Q^r) + F(Q^l)]/2 - c (Q^r - Q^l)/2 (Sec. III, eq. flux_out)
 // at the face between cells a and a+1 along `axis` (1 = x, 2 = y, 3 = eta).
-// `c0` is the flat index of the current cell, `ic` its coordinate along the axis.
+// `base` is the flat index of the row's cell with coordinate 0 along the axis.
 // Components 0..3: T~^{d nu} part (if DO_T); 4..13: u~^d pi~ part (if DO_PI).
-// PI_SRC: 0 pi = 0, 1 pi masked by e == 0, 2 pi as stored.
+// Returns the face's local speed c.  A face whose four stencil cells are exact
+// vacuum (all primitives zero) has H = 0 and c = c_vac, so it skips the arithmetic.
 template <bool DO_T, bool DO_PI, int PI_SRC>
-__device__ __forceinline__ void face_flux(const double* __restrict__ e, const double* const* u,
-                                          const double* const* pi, int c0, int ic, int a, int n,
-                                          int stride, int axis, double tauf, double theta,
-                                          const EosDev& eos, double H[14], double& cmax) {
+__device__ __forceinline__ double face_flux(const double* __restrict__ e, const double* const* u,
+                                            const double* const* pi, int base, int a, int n,
+                                            int stride, int axis, double tauf,
+                                            const StepParams& p, const EosDev& eos,
+                                            double H[14]) {
   int idx[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) idx[t] = c0 + (clampi(a - 1 + t, 0, n - 1) - ic) * stride;
-  double qL[14], qR[14];
-  double ev[4];
+  for (int t = 0; t < 4; ++t) idx[t] = base + clampi(a - 1 + t, 0, n - 1) * stride;
+  double q4[14][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) ev[t] = e[idx[t]];
-  qL[0] = ev[1] + 0.5 * mm_slope(theta, ev[0], ev[1], ev[2]);
-  qR[0] = ev[2] - 0.5 * mm_slope(theta, ev[1], ev[2], ev[3]);
+  for (int t = 0; t < 4; ++t) q4[0][t] = e[idx[t]];
 #pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    const double q0 = u[m][idx[0]], q1 = u[m][idx[1]], q2 = u[m][idx[2]], q3 = u[m][idx[3]];
-    qL[1 + m] = q1 + 0.5 * mm_slope(theta, q0, q1, q2);
-    qR[1 + m] = q2 - 0.5 * mm_slope(theta, q1, q2, q3);
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) q4[1 + m][t] = u[m][idx[t]];
+#pragma unroll
+  for (int m = 0; m < 10; ++m)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) q4[4 + m][t] = ld_pi<PI_SRC>(pi, m, idx[t], q4[0][t]);
+  bool vac = true;
+  const int nchk = (PI_SRC == 2) ? 14 : 4;  // with PI_SRC 0/1, e == 0 implies pi~ = 0
+#pragma unroll
+  for (int v = 0; v < 14; ++v)
+    if (v < nchk)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) vac = vac && (q4[v][t] == 0.0);
+  if (vac) {
+#pragma unroll
+    for (int k = 0; k < 14; ++k) H[k] = 0.0;
+    return p.c_vac;
   }
+  double qL[14], qR[14];
 #pragma unroll
-  for (int m = 0; m < 10; ++m) {
-    if (PI_SRC == 0) {
-      qL[4 + m] = 0.0;
-      qR[4 + m] = 0.0;
-    } else {
-      const double q0 = ld_pi<PI_SRC>(pi, m, idx[0], ev[0]);
-      const double q1 = ld_pi<PI_SRC>(pi, m, idx[1], ev[1]);
-      const double q2 = ld_pi<PI_SRC>(pi, m, idx[2], ev[2]);
-      const double q3 = ld_pi<PI_SRC>(pi, m, idx[3], ev[3]);
-      qL[4 + m] = q1 + 0.5 * mm_slope(theta, q0, q1, q2);
-      qR[4 + m] = q2 - 0.5 * mm_slope(theta, q1, q2, q3);
-    }
+  for (int v = 0; v < 14; ++v) {
+    qL[v] = q4[v][1] + 0.5 * mm_slope(p.theta, q4[v][0], q4[v][1], q4[v][2]);
+    qR[v] = q4[v][2] - 0.5 * mm_slope(p.theta, q4[v][1], q4[v][2], q4[v][3]);
   }
   double QL[14], FL[14], QR[14], FR[14], sL, sR;
 #pragma unroll
@@ -143,42 +197,101 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ e, const do
       sL = s;
   }
   const double c = fmax(sL, sR);
-  cmax = fmax(cmax, c);
 #pragma unroll
   for (int k = 0; k < 14; ++k) {
     const bool on = k < 4 ? DO_T : DO_PI;
     H[k] = on ? 0.5 * (FL[k] + FR[k]) - 0.5 * c * (QR[k] - QL[k]) : 0.0;
   }
+  return c;
 }
 
-// Flux divergence of all three axes (Sec. III, eq. kt) into R (zeroed here).
-// Returns max over faces of c / Delta.
-template <bool DO_T, bool DO_PI, int PI_SRC>
-__device__ __forceinline__ double kt_divergence(const double* __restrict__ e,
-                                                const double* const* u, const double* const* pi,
-                                                const StepParams& p, const EosDev& eos,
-                                                double tauf, int c0, int i, int j, int k,
-                                                double R[14]) {
+// KT flux divergence of the thread's cell over all three axes (Sec. III, eq. kt):
+// R[q] = -sum_d (H_{+1/2} - H_{-1/2}) / Delta_d.  Every face of the tile is
+// computed once by one thread and staged in LDS (component-major).  Returns
+// max over the computed faces of c / Delta (for the CFL diagnostic).
+template <int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC>
+__device__ __forceinline__ double tile_divergence(const double* __restrict__ e,
+                                                  const double* const* u, const double* const* pi,
+                                                  const StepParams& p, const EosDev& eos,
+                                                  double tauf, const Pos& q, double R[14],
+                                                  double* lds) {
+  constexpr int N = TX * TY * TZ;
 #pragma unroll
-  for (int q = 0; q < 14; ++q) R[q] = 0.0;
+  for (int k = 0; k < 14; ++k) R[k] = 0.0;
   double cfl = 0.0;
-  const int n3[3] = {p.nx, p.ny, p.ne};
-  const int co[3] = {i, j, k};
-  const int st[3] = {p.ny * p.ne, p.ne, 1};
-  const double del[3] = {p.dx, p.dy, tauf * p.de};
-#pragma unroll 1
-  for (int d = 0; d < 3; ++d) {
-    if (n3[d] == 1) continue;  // both faces see identical states: zero divergence
-    double Hm[14], Hp[14], c = 0.0;
-    face_flux<DO_T, DO_PI, PI_SRC>(e, u, pi, c0, co[d], co[d] - 1, n3[d], st[d], d + 1, tauf,
-                                   p.theta, eos, Hm, c);
-    face_flux<DO_T, DO_PI, PI_SRC>(e, u, pi, c0, co[d], co[d], n3[d], st[d], d + 1, tauf,
-                                   p.theta, eos, Hp, c);
+  const int tid = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 14; ++q) R[q] -= (Hp[q] - Hm[q]) / del[d];
-    cfl = fmax(cfl, c / del[d]);
+  for (int d = 0; d < 3; ++d) {
+    const int nd = d == 0 ? p.nx : (d == 1 ? p.ny : p.ne);
+    if (nd == 1) continue;  // both faces see identical states: zero divergence
+    constexpr int dummy = 0;
+    (void)dummy;
+    const int Td = d == 0 ? TX : (d == 1 ? TY : TZ);
+    const int F = (Td + 1) * (N / Td);
+    const double inv_del = d == 0 ? p.inv_dx : (d == 1 ? p.inv_dy : p.inv_de / tauf);
+    const int stride = d == 0 ? p.ny * p.ne : (d == 1 ? p.ne : 1);
+    for (int f = tid; f < F; f += kBlock) {
+      // face f -> (a: position along the axis in [0, Td], lx/ly/lz of the other axes);
+      // the ordering keeps eta fastest among consecutive threads where possible
+      int a, fx, fy, fz;
+      if (d == 0) {
+        a = f / (TY * TZ);
+        const int o = f % (TY * TZ);
+        fx = 0; fy = o / TZ; fz = o % TZ;
+      } else if (d == 1) {
+        fx = f / ((TY + 1) * TZ);
+        const int o = f % ((TY + 1) * TZ);
+        a = o / TZ; fy = 0; fz = o % TZ;
+      } else {
+        const int o = f / (TZ + 1);
+        a = f % (TZ + 1);
+        fx = o / TY; fy = o % TY; fz = 0;
+      }
+      const int gi = q.i0 + fx, gj = q.j0 + fy, gk = q.k0 + fz;
+      const int ga = (d == 0 ? q.i0 : (d == 1 ? q.j0 : q.k0)) + a;  // right cell of the face
+      const bool inrow = (d == 0 || gi < p.nx) && (d == 1 || gj < p.ny) && (d == 2 || gk < p.ne);
+      double H[14];
+      if (inrow && ga <= nd) {
+        const int base = d == 0 ? (gj * p.ne + gk)
+                                : (d == 1 ? (gi * p.ny) * p.ne + gk : (gi * p.ny + gj) * p.ne);
+        const double c = face_flux<DO_T, DO_PI, PI_SRC>(e, u, pi, base, ga - 1, nd, stride, d + 1,
+                                                        tauf, p, eos, H);
+        cfl = fmax(cfl, c * inv_del);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 14; ++k) H[k] = 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 14; ++k) lds[k * F + f] = H[k];
+    }
+    __syncthreads();
+    if (q.active) {
+      int fm, fp;
+      if (d == 0) {
+        fm = q.lx * (TY * TZ) + q.ly * TZ + q.lz;
+        fp = fm + TY * TZ;
+      } else if (d == 1) {
+        fm = q.lx * ((TY + 1) * TZ) + q.ly * TZ + q.lz;
+        fp = fm + TZ;
+      } else {
+        fm = (q.lx * TY + q.ly) * (TZ + 1) + q.lz;
+        fp = fm + 1;
+      }
+#pragma unroll
+      for (int k = 0; k < 14; ++k) R[k] -= (lds[k * F + fp] - lds[k * F + fm]) * inv_del;
+    }
+    __syncthreads();
   }
+  (void)N;
   return cfl;
+}
+
+template <int TX, int TY, int TZ>
+constexpr int lds_doubles() {
+  constexpr int N = TX * TY * TZ;
+  constexpr int fx = (TX + 1) * (N / TX), fy = (TY + 1) * (N / TY), fz = (TZ + 1) * (N / TZ);
+  constexpr int m = fx > fy ? (fx > fz ? fx : fz) : (fy > fz ? fy : fz);
+  return 14 * m;
 }
 
 // u~^tau of spatial components.
@@ -190,14 +303,16 @@ __device__ __forceinline__ double utau(double a, double b, double c) {
 // tau_pi = 5 eta_v/(T s)):
 // S = -(pi - eta sigma)/tau_pi - pi theta/3 - (u b + b u) - pi u~^tau/tau - I,
 // sigma~, theta, D~u~ from nabla~_mu u~^nu (eq. dtuz), b^nu = pi^{nu beta} g_{beta beta} a^beta.
-// uE/uL: time levels for d_tau u~.
+// uE/uL: time levels for d_tau u~.  With eta = (eta/s)(e+P) hbarc/T and
+// tau_pi = 5 (eta/s) hbarc/T, eta/tau_pi = (e+P)/5.
 __device__ __forceinline__ void pi_source(const double* const* u, const double* const* uE,
                                           const double* const* uL, const StepParams& p,
-                                          const EosDev& eos, const Geo& g, int c0, int i, int j,
-                                          int k, double ec, const double pc[10], double S[10]) {
+                                          const EosDev& eos, const Geo& g, const Pos& q,
+                                          double ec, const double pc[10], double S[10]) {
+  const int c0 = q.c;
   const int cart = g.cart;
   const double tau = g.tau;
-  const double tauf = cart ? 1.0 : tau;
+  const double inv_tau = 1.0 / tau;
   const double uc[4] = {utau(u[0][c0], u[1][c0], u[2][c0]), u[0][c0], u[1][c0], u[2][c0]};
   double G[4][4];
   {
@@ -206,12 +321,12 @@ __device__ __forceinline__ void pi_source(const double* const* u, const double* 
     const double ea[4] = {utau(a1, a2, a3), a1, a2, a3};
     const double eb[4] = {utau(b1, b2, b3), b1, b2, b3};
 #pragma unroll
-    for (int nu = 0; nu < 4; ++nu) G[0][nu] = (eb[nu] - ea[nu]) / p.h;
+    for (int nu = 0; nu < 4; ++nu) G[0][nu] = (eb[nu] - ea[nu]) * p.inv_h;
   }
   const int n3[3] = {p.nx, p.ny, p.ne};
-  const int co[3] = {i, j, k};
+  const int co[3] = {q.i, q.j, q.k};
   const int st[3] = {p.ny * p.ne, p.ne, 1};
-  const double den[3] = {2.0 * p.dx, 2.0 * p.dy, 2.0 * tauf * p.de};
+  const double ihalf[3] = {0.5 * p.inv_dx, 0.5 * p.inv_dy, 0.5 * p.inv_de * (cart ? 1.0 : inv_tau)};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int ip = c0 + (clampi(co[d] + 1, 0, n3[d] - 1) - co[d]) * st[d];
@@ -221,11 +336,11 @@ __device__ __forceinline__ void pi_source(const double* const* u, const double* 
     const double up4[4] = {utau(p1, p2, p3), p1, p2, p3};
     const double um4[4] = {utau(m1, m2, m3), m1, m2, m3};
 #pragma unroll
-    for (int nu = 0; nu < 4; ++nu) G[d + 1][nu] = (up4[nu] - um4[nu]) / den[d];
+    for (int nu = 0; nu < 4; ++nu) G[d + 1][nu] = (up4[nu] - um4[nu]) * ihalf[d];
   }
   if (!cart) {
-    G[3][0] += uc[3] / tau;
-    G[3][3] += uc[0] / tau;
+    G[3][0] += uc[3] * inv_tau;
+    G[3][3] += uc[0] * inv_tau;
   }
   const double theta = G[0][0] + G[1][1] + G[2][2] + G[3][3];
   double a[4];
@@ -240,9 +355,10 @@ __device__ __forceinline__ void pi_source(const double* const* u, const double* 
             pc[sym(nu, 3)] * a[3];
   double P, T;
   eos_p_t(eos, ec, P, T);
-  const double etav = p.etas * (ec + P) * kHbarc / T;
-  const double taupi = 5.0 * p.etas * kHbarc / T;
+  const double inv_taupi = T * p.inv_taupi_coef;
+  const double eta_over_taupi = 0.2 * (ec + P);
   const double ue = uc[3];
+  const double third = 1.0 / 3.0;
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
 #pragma unroll
@@ -250,18 +366,18 @@ __device__ __forceinline__ void pi_source(const double* const* u, const double* 
       const int m = sym(mu, nu);
       const double gmn = (mu == nu) ? gt[mu] : 0.0;
       const double sig = gt[mu] * G[mu][nu] + gt[nu] * G[nu][mu] - uc[mu] * a[nu] -
-                         uc[nu] * a[mu] - 2.0 / 3.0 * (gmn - uc[mu] * uc[nu]) * theta;
-      double s = -(pc[m] - etav * sig) / taupi - pc[m] * theta / 3.0 -
+                         uc[nu] * a[mu] - 2.0 * third * (gmn - uc[mu] * uc[nu]) * theta;
+      double s = -pc[m] * inv_taupi + eta_over_taupi * sig - pc[m] * theta * third -
                  (uc[mu] * b[nu] + uc[nu] * b[mu]);
       if (!cart) {
         double I = 0.0;  // Christoffel terms I^{mu nu}
-        if (m == 0 || m == 9) I = 2.0 * ue * pc[3] / tau;
-        else if (m == 1) I = ue * pc[6] / tau;
-        else if (m == 2) I = ue * pc[8] / tau;
-        else if (m == 3) I = ue * (pc[0] + pc[9]) / tau;
-        else if (m == 6) I = ue * pc[1] / tau;
-        else if (m == 8) I = ue * pc[2] / tau;
-        s += -pc[m] * uc[0] / tau - I;
+        if (m == 0 || m == 9) I = 2.0 * ue * pc[3];
+        else if (m == 1) I = ue * pc[6];
+        else if (m == 2) I = ue * pc[8];
+        else if (m == 3) I = ue * (pc[0] + pc[9]);
+        else if (m == 6) I = ue * pc[1];
+        else if (m == 8) I = ue * pc[2];
+        s += -(pc[m] * uc[0] + I) * inv_tau;
       }
       S[m] = s;
     }
@@ -313,7 +429,7 @@ __device__ __forceinline__ void block_partials(double v[kNP], double* out) {
     const int s = threadIdx.x;
     double x = red[0][s];
     for (int w = 1; w < kBlock / 64; ++w) x = is_max_slot(s) ? fmax(x, red[w][s]) : x + red[w][s];
-    out[(size_t)blockIdx.x * kNP + s] = x;
+    out[(size_t)s * gridDim.x + blockIdx.x] = x;  // slot-major: the reduce reads coalesced
   }
 }
 
@@ -326,13 +442,6 @@ __device__ __forceinline__ void count_solve(double v[kNP], int it, int fl) {
   if (fl & kFallback) v[P_FALLBACK] += 1.0;
   if (fl & kNonconv) v[P_NONCONV] += 1.0;
   if (fl & kClamp) v[P_CLAMP] += 1.0;
-}
-
-__device__ __forceinline__ void decompose(const StepParams& p, int c, int& i, int& j, int& k) {
-  k = c % p.ne;
-  const int r = c / p.ne;
-  j = r % p.ny;
-  i = r / p.ny;
 }
 
 // ---------------------------------------------------------------------------
@@ -388,24 +497,22 @@ __global__ __launch_bounds__(kBlock) void k_init_conserved(Fields f, StepParams 
   f.u[0][c] = s.u1;
   f.u[1][c] = s.u2;
   f.u[2][c] = s.u3;
-  if (s.e == 0.0)
-#pragma unroll
-    for (int m = 0; m < 10; ++m) f.pi[m][c] = 0.0;
-  else if (!visc)
+  if (s.e == 0.0 || !visc)
 #pragma unroll
     for (int m = 0; m < 10; ++m) f.pi[m][c] = 0.0;
 }
 
 // First step: u*1 from one ideal forward-Euler step; u~^{-1} = 2 u~^0 - u*1.
+template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(kBlock) void k_first_estimate(Fields f, StepParams p, EosDev eos,
-                                                            Geo g) {
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= p.ncell) return;
-  int i, j, k;
-  decompose(p, c, i, j, k);
+                                                            Geo g, TileGrid tg) {
+  __shared__ double lds[lds_doubles<TX, TY, TZ>()];
+  const Pos q = cell_pos<TX, TY, TZ>(p, tg);
   const double tf = g.cart ? 1.0 : g.tau;
   double R[14];
-  kt_divergence<true, false, 0>(f.e, f.u, f.pi, p, eos, tf, c, i, j, k, R);
+  tile_divergence<TX, TY, TZ, true, false, 0>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
+  if (!q.active) return;
+  const int c = q.c;
   const double e = f.e[c], u1 = f.u[0][c], u2 = f.u[1][c], u3 = f.u[2][c];
   const double ut = utau(u1, u2, u3);
   double P, cs2;
@@ -417,10 +524,10 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(Fields f, StepParams 
   }
   const double u4[4] = {ut, u1, u2, u3};
   double K[4];
-  const double tf1 = g.cart ? 1.0 : g.tau1;
+  const double inv_tf1 = 1.0 / (g.cart ? 1.0 : g.tau1);
 #pragma unroll
   for (int nu = 0; nu < 4; ++nu)
-    K[nu] = (tf * (w * ut * u4[nu] - (nu == 0 ? P : 0.0)) + p.h * R[nu]) / tf1;
+    K[nu] = (tf * (w * ut * u4[nu] - (nu == 0 ? P : 0.0)) + p.h * R[nu]) * inv_tf1;
   int it, fl;
   const Prim s = con2prim(eos, p, K[0], K[1], K[2], K[3], e, it, fl);
   f.up[0][c] = 2.0 * u1 - s.u1;
@@ -429,20 +536,21 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(Fields f, StepParams 
 }
 
 // Stage 1 at tau_n (predictor) for the ideal (VISC = false) or viscous path.
-template <bool VISC>
-__global__ __launch_bounds__(kBlock) void k_stage1(Fields f, StepParams p, EosDev eos, Geo g) {
-  const int c = blockIdx.x * kBlock + threadIdx.x;
+template <int TX, int TY, int TZ, bool VISC>
+__global__ __launch_bounds__(kBlock) void k_stage1(Fields f, StepParams p, EosDev eos, Geo g,
+                                                    TileGrid tg) {
+  __shared__ double lds[lds_doubles<TX, TY, TZ>()];
+  const Pos q = cell_pos<TX, TY, TZ>(p, tg);
   double v[kNP];
 #pragma unroll
   for (int s = 0; s < kNP; ++s) v[s] = 0.0;
-  if (c < p.ncell) {
-    int i, j, k;
-    decompose(p, c, i, j, k);
-    const double tf = g.cart ? 1.0 : g.tau;
-    double R[14];
-    const double cfl = kt_divergence<true, VISC, VISC ? 1 : 0>(f.e, f.u, f.pi, p, eos, tf, c, i,
-                                                                 j, k, R);
-    v[P_CFL] = cfl * p.h;
+  const double tf = g.cart ? 1.0 : g.tau;
+  double R[14];
+  const double cfl =
+      tile_divergence<TX, TY, TZ, true, VISC, VISC ? 1 : 0>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
+  v[P_CFL] = cfl * p.h;
+  if (q.active) {
+    const int c = q.c;
     const double e = f.e[c], u1 = f.u[0][c], u2 = f.u[1][c], u3 = f.u[2][c];
     const double ut = utau(u1, u2, u3);
     double pc[10];
@@ -461,15 +569,15 @@ __global__ __launch_bounds__(kBlock) void k_stage1(Fields f, StepParams p, EosDe
     if (VISC) {
       if (e >= p.eps_cut) {
         double S[10];
-        pi_source(f.u, f.up, f.u, p, eos, g, c, i, j, k, e, pc, S);
+        pi_source(f.u, f.up, f.u, p, eos, g, q, e, pc, S);
 #pragma unroll
         for (int m = 0; m < 10; ++m) R[4 + m] += S[m];
       }
       const double s1 = 2.0 * u1 - f.up[0][c], s2 = 2.0 * u2 - f.up[1][c],
                    s3 = 2.0 * u3 - f.up[2][c];
-      const double uts = utau(s1, s2, s3);
+      const double inv_uts = 1.0 / utau(s1, s2, s3);
 #pragma unroll
-      for (int m = 0; m < 10; ++m) p1[m] = (ut * pc[m] + p.h * R[4 + m]) / uts;
+      for (int m = 0; m < 10; ++m) p1[m] = (ut * pc[m] + p.h * R[4 + m]) * inv_uts;
       regulate(eos, p, e, p1);
 #pragma unroll
       for (int m = 0; m < 10; ++m) f.pi1[m][c] = p1[m];
@@ -483,11 +591,11 @@ __global__ __launch_bounds__(kBlock) void k_stage1(Fields f, StepParams p, EosDe
       T1[nu] = f.T[nu][c] + p.h * R[nu];
       f.T1[nu][c] = T1[nu];
     }
-    const double tf1 = g.cart ? 1.0 : g.tau1;
+    const double inv_tf1 = 1.0 / (g.cart ? 1.0 : g.tau1);
+    const double K0 = T1[0] * inv_tf1 - p1[0];
     int it, fl;
-    const Prim s = con2prim(eos, p, T1[0] / tf1 - p1[0], T1[1] / tf1 - p1[1],
-                            T1[2] / tf1 - p1[2], T1[3] / tf1 - p1[3],
-                            p.guess_cold ? T1[0] / tf1 - p1[0] : e, it, fl);
+    const Prim s = con2prim(eos, p, K0, T1[1] * inv_tf1 - p1[1], T1[2] * inv_tf1 - p1[2],
+                            T1[3] * inv_tf1 - p1[3], p.guess_cold ? K0 : e, it, fl);
     count_solve(v, it, fl);
     f.e1[c] = s.e;
     f.u1[0][c] = s.u1;
@@ -498,21 +606,23 @@ __global__ __launch_bounds__(kBlock) void k_stage1(Fields f, StepParams p, EosDe
 }
 
 // Stage 2, part 1 (tau_{n+1}): pi^{n+1} = [ (u^n pi^n + u* pi')/2 + h/2 R_pi(e', u', pi') ] / u'^tau.
-__global__ __launch_bounds__(kBlock) void k_stage2_pi(Fields f, StepParams p, EosDev eos, Geo g) {
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= p.ncell) return;
-  int i, j, k;
-  decompose(p, c, i, j, k);
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_stage2_pi(Fields f, StepParams p, EosDev eos, Geo g,
+                                                      TileGrid tg) {
+  __shared__ double lds[lds_doubles<TX, TY, TZ>()];
+  const Pos q = cell_pos<TX, TY, TZ>(p, tg);
   const double tf = g.cart ? 1.0 : g.tau;
   double R[14];
-  kt_divergence<false, true, 2>(f.e1, f.u1, f.pi1, p, eos, tf, c, i, j, k, R);
+  tile_divergence<TX, TY, TZ, false, true, 2>(f.e1, f.u1, f.pi1, p, eos, tf, q, R, lds);
+  if (!q.active) return;
+  const int c = q.c;
   const double e1 = f.e1[c];
   double pc[10];
 #pragma unroll
   for (int m = 0; m < 10; ++m) pc[m] = f.pi1[m][c];
   if (e1 >= p.eps_cut) {
     double S[10];
-    pi_source(f.u1, f.u, f.u1, p, eos, g, c, i, j, k, e1, pc, S);
+    pi_source(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
 #pragma unroll
     for (int m = 0; m < 10; ++m) R[4 + m] += S[m];
   }
@@ -520,12 +630,12 @@ __global__ __launch_bounds__(kBlock) void k_stage2_pi(Fields f, StepParams p, Eo
   const double a1 = f.u[0][c], a2 = f.u[1][c], a3 = f.u[2][c];
   const double utn = utau(a1, a2, a3);
   const double uts = utau(2.0 * a1 - f.up[0][c], 2.0 * a2 - f.up[1][c], 2.0 * a3 - f.up[2][c]);
-  const double ut1 = utau(f.u1[0][c], f.u1[1][c], f.u1[2][c]);
+  const double inv_ut1 = 1.0 / utau(f.u1[0][c], f.u1[1][c], f.u1[2][c]);
   double pn[10];
 #pragma unroll
   for (int m = 0; m < 10; ++m) {
     const double pin = en == 0.0 ? 0.0 : f.pi[m][c];
-    pn[m] = (0.5 * (utn * pin + uts * pc[m]) + 0.5 * p.h * R[4 + m]) / ut1;
+    pn[m] = (0.5 * (utn * pin + uts * pc[m]) + 0.5 * p.h * R[4 + m]) * inv_ut1;
   }
   regulate(eos, p, e1, pn);
 #pragma unroll
@@ -534,20 +644,21 @@ __global__ __launch_bounds__(kBlock) void k_stage2_pi(Fields f, StepParams p, Eo
 
 // Stage 2, part 2 (tau_{n+1}): T^{n+1} = T^n + [(T' - T^n) + h R_T(e', u', pi^{n+1})]/2,
 // root solve -> (e, u~)^{n+1} (written over e^n and u~^{n-1}), diagnostics.
-template <bool VISC>
-__global__ __launch_bounds__(kBlock) void k_stage2_T(Fields f, StepParams p, EosDev eos, Geo g) {
-  const int c = blockIdx.x * kBlock + threadIdx.x;
+template <int TX, int TY, int TZ, bool VISC>
+__global__ __launch_bounds__(kBlock) void k_stage2_T(Fields f, StepParams p, EosDev eos, Geo g,
+                                                     TileGrid tg) {
+  __shared__ double lds[lds_doubles<TX, TY, TZ>()];
+  const Pos q = cell_pos<TX, TY, TZ>(p, tg);
   double v[kNP];
 #pragma unroll
   for (int s = 0; s < kNP; ++s) v[s] = 0.0;
-  if (c < p.ncell) {
-    int i, j, k;
-    decompose(p, c, i, j, k);
-    const double tf = g.cart ? 1.0 : g.tau;
-    double R[14];
-    const double cfl = kt_divergence<true, false, VISC ? 2 : 0>(f.e1, f.u1, f.pi, p, eos, tf, c,
-                                                                  i, j, k, R);
-    v[P_CFL] = cfl * p.h;
+  const double tf = g.cart ? 1.0 : g.tau;
+  double R[14];
+  const double cfl = tile_divergence<TX, TY, TZ, true, false, VISC ? 2 : 0>(f.e1, f.u1, f.pi, p,
+                                                                          eos, tf, q, R, lds);
+  v[P_CFL] = cfl * p.h;
+  if (q.active) {
+    const int c = q.c;
     const double e1 = f.e1[c], u1 = f.u1[0][c], u2 = f.u1[1][c], u3 = f.u1[2][c];
     double pc[10];
 #pragma unroll
@@ -569,11 +680,11 @@ __global__ __launch_bounds__(kBlock) void k_stage2_T(Fields f, StepParams p, Eos
       Tn[nu] = t0 + 0.5 * ((f.T1[nu][c] - t0) + p.h * R[nu]);
       f.T[nu][c] = Tn[nu];
     }
-    const double tf1 = g.cart ? 1.0 : g.tau1;
-    const double K0 = Tn[0] / tf1 - pc[0];
+    const double inv_tf1 = 1.0 / (g.cart ? 1.0 : g.tau1);
+    const double K0 = Tn[0] * inv_tf1 - pc[0];
     int it, fl;
-    const Prim s = con2prim(eos, p, K0, Tn[1] / tf1 - pc[1], Tn[2] / tf1 - pc[2],
-                            Tn[3] / tf1 - pc[3], p.guess_cold ? K0 : e1, it, fl);
+    const Prim s = con2prim(eos, p, K0, Tn[1] * inv_tf1 - pc[1], Tn[2] * inv_tf1 - pc[2],
+                            Tn[3] * inv_tf1 - pc[3], p.guess_cold ? K0 : e1, it, fl);
     count_solve(v, it, fl);
     f.e[c] = s.e;
     f.up[0][c] = s.u1;  // becomes u~^{n+1} after the host swaps u and up
@@ -587,49 +698,49 @@ __global__ __launch_bounds__(kBlock) void k_stage2_T(Fields f, StepParams p, Eos
 }
 
 // Folds the partials of stage1 and stage2T into the accumulated diagnostics.
+// One workgroup per slot; each folds the slot's partials in a fixed order.
 // acc: 0 geo_src, 1 max_cfl, 2 solves, 3 iter_sum, 4 iter_max, 5 fallbacks,
 //      6 nonconv, 7 nans, 8 clamps, 9 eps_max, 10 sum_Ttt, 11 vacuum.
 __global__ __launch_bounds__(kBlock) void k_reduce(Fields f, int nblk, double half_h_vol,
                                                    double vol) {
-  __shared__ double sh[kBlock];
-  for (int s = 0; s < kNP; ++s) {
-    const bool mx = is_max_slot(s);
-    double x = 0.0, y = 0.0;  // stage1, stage2T
-    for (int b = threadIdx.x; b < nblk; b += kBlock) {
-      const double a = f.partial[(size_t)b * kNP + s];
-      const double c = f.partial[((size_t)nblk + b) * kNP + s];
-      x = mx ? fmax(x, a) : x + a;
-      y = mx ? fmax(y, c) : y + c;
-    }
-    for (int pass = 0; pass < 2; ++pass) {
-      sh[threadIdx.x] = pass ? y : x;
-      __syncthreads();
-      for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-          sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + w])
-                               : sh[threadIdx.x] + sh[threadIdx.x + w];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) {
-        if (pass)
-          y = sh[0];
-        else
-          x = sh[0];
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      double* acc = f.acc;
-      switch (s) {
-        case P_GEO: acc[0] += half_h_vol * (x + y); break;
-        case P_CFL: acc[1] = fmax(acc[1], fmax(x, y)); break;
-        case P_EMAX: acc[9] = y; break;
-        case P_TSUM: acc[10] = y * vol; break;
-        case P_VAC: acc[11] = y; break;
-        case P_ITMAX: acc[4] = fmax(acc[4], fmax(x, y)); break;
-        default: acc[s] += x + y; break;
-      }
-    }
+  __shared__ double sh[2][kBlock / 64];
+  const int s = blockIdx.x;
+  const bool mx = is_max_slot(s);
+  double x = 0.0, y = 0.0;  // stage1, stage2T
+  for (int b = threadIdx.x; b < nblk; b += kBlock) {
+    const double a = f.partial[(size_t)s * nblk + b];
+    const double c = f.partial[(size_t)(kNP + s) * nblk + b];
+    x = mx ? fmax(x, a) : x + a;
+    y = mx ? fmax(y, c) : y + c;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double xo = __shfl_xor(x, off, 64), yo = __shfl_xor(y, off, 64);
+    x = mx ? fmax(x, xo) : x + xo;
+    y = mx ? fmax(y, yo) : y + yo;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[0][wave] = x;
+    sh[1][wave] = y;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  x = sh[0][0];
+  y = sh[1][0];
+  for (int w = 1; w < kBlock / 64; ++w) {
+    x = mx ? fmax(x, sh[0][w]) : x + sh[0][w];
+    y = mx ? fmax(y, sh[1][w]) : y + sh[1][w];
+  }
+  double* acc = f.acc;
+  switch (s) {
+    case P_GEO: acc[0] += half_h_vol * (x + y); break;
+    case P_CFL: acc[1] = fmax(acc[1], fmax(x, y)); break;
+    case P_EMAX: acc[9] = y; break;
+    case P_TSUM: acc[10] = y * vol; break;
+    case P_VAC: acc[11] = y; break;
+    case P_ITMAX: acc[4] = fmax(acc[4], fmax(x, y)); break;
+    default: acc[s] += x + y; break;
   }
 }
 
@@ -645,6 +756,15 @@ __global__ void k_zero(double* p, int n) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c < n) p[c] = 0.0;
 }
+
+// ---------------------------------------------------------------------------
+// Tile shapes available to the launcher (the autotuner picks among them).
+// ---------------------------------------------------------------------------
+struct TileShape {
+  int tx, ty, tz;
+};
+constexpr TileShape kTiles[] = {{4, 4, 16}, {2, 8, 16}, {4, 8, 8}, {1, 8, 32}, {16, 16, 1}, {256, 1, 1}};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 }  // namespace ktmi
 
@@ -667,9 +787,12 @@ struct ktmi_handle {
   EosDev eos{};
   Fields f{};
   double* eos_store = nullptr;
+  double cs2_vac = 1.0 / 3.0;  // cs2 of the EoS at e = 0
   double tau = 0.0;
   long step = 0;
-  int nblk = 0;
+  int nblk = 0;      // blocks of the flat (per-cell) kernels
+  int tile = 0;      // index into kTiles
+  TileGrid tg{};     // tile grid of the stencil kernels
   size_t fstride = 0;
   bool timing = false;
   struct Rec {
@@ -737,7 +860,44 @@ static bool desc_ok(const ktmi_desc* d, std::string* why) {
     *why = "unknown guess mode";
     return false;
   }
+  if (d->tile < -1 || d->tile >= kNumTiles) {
+    *why = "tile index out of range";
+    return false;
+  }
   return true;
+}
+
+static TileGrid tile_grid(const ktmi_desc* d, int t) {
+  TileGrid g;
+  g.ntx = (d->nx + kTiles[t].tx - 1) / kTiles[t].tx;
+  g.nty = (d->ny + kTiles[t].ty - 1) / kTiles[t].ty;
+  g.ntz = (d->ne + kTiles[t].tz - 1) / kTiles[t].tz;
+  g.ntiles = g.ntx * g.nty * g.ntz;
+  return g;
+}
+
+// Default tile: fewest padded thread slots, counting double for shapes whose eta
+// extent is shorter than min(ne, 16) (their lanes stride across eta rows, so
+// loads stop coalescing).  Ties keep list order.  The autotuner can override.
+static int auto_tile(const ktmi_desc* d) {
+  int best = 0;
+  double best_score = 1e300;
+  const int want_z = d->ne < 16 ? d->ne : 16;
+  for (int t = 0; t < kNumTiles; ++t) {
+    const double slots = (double)tile_grid(d, t).ntiles * kBlock;
+    const double score = slots * (kTiles[t].tz >= want_z ? 1.0 : 2.0);
+    if (score < best_score) {
+      best_score = score;
+      best = t;
+    }
+  }
+  return best;
+}
+
+static int max_tiles(const ktmi_desc* d) {
+  int m = 0;
+  for (int t = 0; t < kNumTiles; ++t) m = std::max(m, tile_grid(d, t).ntiles);
+  return m;
 }
 
 static const int kNumFields = 39;  // e, u(3), up(3), pi(10), T(4), e1, u1(3), pi1(10), T1(4)
@@ -761,8 +921,14 @@ static StepParams step_params(const ktmi_handle* h) {
   p.dx = h->d.dx;
   p.dy = h->d.dy;
   p.de = h->d.de;
+  p.inv_dx = 1.0 / h->d.dx;
+  p.inv_dy = 1.0 / h->d.dy;
+  p.inv_de = 1.0 / h->d.de;
   p.h = h->d.h;
+  p.inv_h = 1.0 / h->d.h;
   p.etas = h->d.etas;
+  p.inv_taupi_coef = h->d.etas > 0 ? 1.0 / (5.0 * h->d.etas * kHbarc) : 0.0;
+  p.c_vac = sqrt(h->cs2_vac);
   p.eps_cut = h->d.eps_cut;
   p.theta = h->d.theta;
   p.newton_tol = h->d.newton_tol;
@@ -808,13 +974,73 @@ static Geo geo(const ktmi_handle* h, double tau, double tau1) {
   return g;
 }
 
+// Launches one stencil kernel family member for the handle's tile shape.
+template <template <int, int, int> class K, typename... Args>
+static void launch_tiled(const ktmi_handle* h, Args... args) {
+  const dim3 grid(h->tg.ntiles), block(kBlock);
+  switch (h->tile) {
+#define KTMI_TILE_CASE(id, X, Y, Z) \
+  case id: K<X, Y, Z>::launch(grid, block, h->stream, args...); break;
+    KTMI_TILE_CASE(0, 4, 4, 16)
+    KTMI_TILE_CASE(1, 2, 8, 16)
+    KTMI_TILE_CASE(2, 4, 8, 8)
+    KTMI_TILE_CASE(3, 1, 8, 32)
+    KTMI_TILE_CASE(4, 16, 16, 1)
+    KTMI_TILE_CASE(5, 256, 1, 1)
+#undef KTMI_TILE_CASE
+    default: break;
+  }
+}
+
+template <int X, int Y, int Z>
+struct LFirst {
+  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
+                     TileGrid tg) {
+    hipLaunchKernelGGL((k_first_estimate<X, Y, Z>), g, b, 0, s, f, p, e, geo, tg);
+  }
+};
+template <int X, int Y, int Z>
+struct LStage1V {
+  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
+                     TileGrid tg) {
+    hipLaunchKernelGGL((k_stage1<X, Y, Z, true>), g, b, 0, s, f, p, e, geo, tg);
+  }
+};
+template <int X, int Y, int Z>
+struct LStage1I {
+  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
+                     TileGrid tg) {
+    hipLaunchKernelGGL((k_stage1<X, Y, Z, false>), g, b, 0, s, f, p, e, geo, tg);
+  }
+};
+template <int X, int Y, int Z>
+struct LStage2Pi {
+  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
+                     TileGrid tg) {
+    hipLaunchKernelGGL((k_stage2_pi<X, Y, Z>), g, b, 0, s, f, p, e, geo, tg);
+  }
+};
+template <int X, int Y, int Z>
+struct LStage2TV {
+  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
+                     TileGrid tg) {
+    hipLaunchKernelGGL((k_stage2_T<X, Y, Z, true>), g, b, 0, s, f, p, e, geo, tg);
+  }
+};
+template <int X, int Y, int Z>
+struct LStage2TI {
+  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
+                     TileGrid tg) {
+    hipLaunchKernelGGL((k_stage2_T<X, Y, Z, false>), g, b, 0, s, f, p, e, geo, tg);
+  }
+};
+
 static int finish_initial(ktmi_handle* h) {
   const StepParams p = step_params(h);
   const int nb = h->nblk;
   const Geo g = geo(h, h->tau, h->tau + h->d.h);
-  int rc = launch(h, K_FIRST, [&] {
-    hipLaunchKernelGGL(k_first_estimate, dim3(nb), dim3(kBlock), 0, h->stream, h->f, p, h->eos, g);
-  });
+  (void)nb;
+  int rc = launch(h, K_FIRST, [&] { launch_tiled<LFirst>(h, h->f, p, h->eos, g, h->tg); });
   if (rc) return rc;
   rc = launch(h, K_INIT, [&] {
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, h->stream, h->f.acc, 32);
@@ -843,13 +1069,14 @@ void ktmi_desc_default(ktmi_desc* d) {
   d->pi_reg = 1.0;
   d->precision = KTMI_FP64;
   d->guess = KTMI_GUESS_PREV;
+  d->tile = -1;
 }
 
 size_t ktmi_workspace_bytes(const ktmi_desc* d) {
   std::string why;
   if (!desc_ok(d, &why)) return 0;
   const size_t fs = field_stride(d);
-  const size_t nb = (size_t)num_blocks(d);
+  const size_t nb = (size_t)max_tiles(d);
   size_t bytes = (size_t)kNumFields * fs * sizeof(double);
   bytes += ((2 * nb * kNP + 31) / 32 * 32) * sizeof(double);  // partials
   bytes += 32 * sizeof(double);                               // accumulators
@@ -866,9 +1093,12 @@ int ktmi_create(const ktmi_desc* d, ktmi_handle** out) {
   h->d = *d;
   h->tau = d->tau0;
   h->nblk = num_blocks(d);
+  h->tile = d->tile < 0 ? auto_tile(d) : d->tile;
+  h->tg = tile_grid(d, h->tile);
   h->fstride = field_stride(d);
   h->eos.kind = 0;
   h->eos.c_sb = 47.5 * M_PI * M_PI / 30.0 / (kHbarc * kHbarc * kHbarc);
+  h->eos.inv_csb = 1.0 / h->eos.c_sb;
   h->eos_set = true;  // ideal gas until a table is set
   *out = h;
   return KTMI_OK;
@@ -901,7 +1131,7 @@ int ktmi_bind(ktmi_handle* h, void* ws, size_t bytes, void* stream) {
   for (int m = 0; m < 4; ++m) f.T1[m] = base + fs * q++;
   double* rest = base + fs * q;
   f.partial = rest;
-  rest += (2 * (size_t)h->nblk * kNP + 31) / 32 * 32;
+  rest += (2 * (size_t)max_tiles(&h->d) * kNP + 31) / 32 * 32;
   f.acc = rest;
   rest += 32;
   h->eos_store = rest;
@@ -914,6 +1144,8 @@ int ktmi_set_eos_conformal(ktmi_handle* h, double c_sb) {
   if (!(c_sb > 0)) return fail(h, KTMI_EINVAL, "c_sb must be > 0");
   h->eos.kind = 0;
   h->eos.c_sb = c_sb;
+  h->eos.inv_csb = 1.0 / c_sb;
+  h->cs2_vac = 1.0 / 3.0;
   h->eos_set = true;
   return KTMI_OK;
 }
@@ -936,6 +1168,8 @@ int ktmi_set_eos_table(ktmi_handle* h, double e0, double de, int n, const double
   h->eos.n = n;
   h->eos.e0 = e0;
   h->eos.de = de;
+  h->eos.inv_de = 1.0 / de;
+  h->cs2_vac = (e0 >= 0.0) ? cs2[0] : cs2[0];  // lookups clamp e = 0 to the first row
   h->eos.P = dP;
   h->eos.T = dT;
   h->eos.cs2 = dC;
@@ -1001,37 +1235,29 @@ int ktmi_step(ktmi_handle* h, int nsteps) {
   if (!h->ready) return fail(h, KTMI_ESTATE, "set an initial state first");
   if (nsteps < 0) return fail(h, KTMI_EINVAL, "negative step count");
   const StepParams p = step_params(h);
-  const int nb = h->nblk;
   hipStream_t s = h->stream;
   const double vol = h->d.dx * h->d.dy * h->d.de;
   for (int it = 0; it < nsteps; ++it) {
     const double t0 = h->tau, t1 = h->tau + h->d.h;
     const Geo g0 = geo(h, t0, t1), g1 = geo(h, t1, t1);
+    const TileGrid tg = h->tg;
     int rc;
     if (h->d.viscous) {
-      rc = launch(h, K_STAGE1, [&] {
-        hipLaunchKernelGGL(k_stage1<true>, dim3(nb), dim3(kBlock), 0, s, h->f, p, h->eos, g0);
-      });
+      rc = launch(h, K_STAGE1, [&] { launch_tiled<LStage1V>(h, h->f, p, h->eos, g0, tg); });
       if (rc) return rc;
-      rc = launch(h, K_STAGE2PI, [&] {
-        hipLaunchKernelGGL(k_stage2_pi, dim3(nb), dim3(kBlock), 0, s, h->f, p, h->eos, g1);
-      });
+      rc = launch(h, K_STAGE2PI, [&] { launch_tiled<LStage2Pi>(h, h->f, p, h->eos, g1, tg); });
       if (rc) return rc;
-      rc = launch(h, K_STAGE2T, [&] {
-        hipLaunchKernelGGL(k_stage2_T<true>, dim3(nb), dim3(kBlock), 0, s, h->f, p, h->eos, g1);
-      });
+      rc = launch(h, K_STAGE2T, [&] { launch_tiled<LStage2TV>(h, h->f, p, h->eos, g1, tg); });
     } else {
-      rc = launch(h, K_STAGE1, [&] {
-        hipLaunchKernelGGL(k_stage1<false>, dim3(nb), dim3(kBlock), 0, s, h->f, p, h->eos, g0);
-      });
+      rc = launch(h, K_STAGE1, [&] { launch_tiled<LStage1I>(h, h->f, p, h->eos, g0, tg); });
       if (rc) return rc;
-      rc = launch(h, K_STAGE2T, [&] {
-        hipLaunchKernelGGL(k_stage2_T<false>, dim3(nb), dim3(kBlock), 0, s, h->f, p, h->eos, g1);
-      });
+      rc = launch(h, K_STAGE2T, [&] { launch_tiled<LStage2TI>(h, h->f, p, h->eos, g1, tg); });
     }
     if (rc) return rc;
+    const int nt = tg.ntiles;
     rc = launch(h, K_REDUCE, [&] {
-      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, h->f, nb, 0.5 * h->d.h * vol, vol);
+      hipLaunchKernelGGL(k_reduce, dim3(kNP), dim3(kBlock), 0, s, h->f, nt, 0.5 * h->d.h * vol,
+                         vol);
     });
     if (rc) return rc;
     for (int m = 0; m < 3; ++m) std::swap(h->f.u[m], h->f.up[m]);
@@ -1121,6 +1347,26 @@ int ktmi_timing(ktmi_handle* h, int k, double* total_ms, long* launches) {
   }
   *total_ms = t;
   *launches = cnt;
+  return KTMI_OK;
+}
+
+int ktmi_tile_count(void) { return kNumTiles; }
+
+int ktmi_tile_shape(int t, int* tx, int* ty, int* tz) {
+  if (t < 0 || t >= kNumTiles || !tx || !ty || !tz) return KTMI_EINVAL;
+  *tx = kTiles[t].tx;
+  *ty = kTiles[t].ty;
+  *tz = kTiles[t].tz;
+  return KTMI_OK;
+}
+
+int ktmi_get_tile(const ktmi_handle* h) { return h ? h->tile : KTMI_EINVAL; }
+
+int ktmi_set_tile(ktmi_handle* h, int t) {
+  if (!h) return KTMI_EINVAL;
+  if (t < -1 || t >= kNumTiles) return fail(h, KTMI_EINVAL, "tile index out of range");
+  h->tile = t < 0 ? auto_tile(&h->d) : t;
+  h->tg = tile_grid(&h->d, h->tile);
   return KTMI_OK;
 }
 

@@ -13,9 +13,12 @@ constexpr double kHbarc = 0.1973269804;  // GeV fm
 struct StepParams {
   int nx, ny, ne, ncell;
   double dx, dy, de;
-  double h;
+  double inv_dx, inv_dy, inv_de;  // reciprocals of the spacings
+  double h, inv_h;
   double etas;
+  double inv_taupi_coef;  // 1 / (5 eta/s hbarc): 1/tau_pi = T * inv_taupi_coef
   double eps_cut, theta, newton_tol, pi_reg;
+  double c_vac;  // local speed of a vacuum state, sqrt(cs2(0))
   int newton_maxit;
   int guess_cold;
 };
@@ -23,7 +26,7 @@ struct StepParams {
 struct EosDev {
   int kind;  // 0 ideal gas, 1 uniform table
   int n;
-  double c_sb, e0, de;
+  double c_sb, inv_csb, e0, de, inv_de;
   const double* P;
   const double* T;
   const double* cs2;
@@ -45,7 +48,7 @@ struct EosSeg {
 
 __device__ __forceinline__ EosSeg eos_seg(const EosDev& q, double e) {
   EosSeg s;
-  double x = (e - q.e0) / q.de;
+  double x = (e - q.e0) * q.inv_de;
   x = x >= 0.0 ? x : 0.0;  // also maps NaN to the first row
   s.beyond = x >= (double)(q.n - 1);
   const double xc = s.beyond ? (double)(q.n - 2) : x;  // keeps the index in [0, n-2]
@@ -67,7 +70,7 @@ __device__ __forceinline__ void eos_p_cs2(const EosDev& q, double e, double& P, 
   EosSeg s = eos_seg(q, e);
   const int n = q.n;
   if (s.beyond) {
-    const double slope = (q.P[n - 1] - q.P[n - 2]) / q.de;
+    const double slope = (q.P[n - 1] - q.P[n - 2]) * q.inv_de;
     const double elast = q.e0 + (double)(n - 1) * q.de;
     P = q.P[n - 1] + (e - elast) * slope;
     cs2 = q.cs2[n - 1];
@@ -90,14 +93,14 @@ __device__ __forceinline__ void eos_p_dp(const EosDev& q, double e, double& P, d
   EosSeg s = eos_seg(q, e);
   const int n = q.n;
   if (s.beyond) {
-    dP = (q.P[n - 1] - q.P[n - 2]) / q.de;
+    dP = (q.P[n - 1] - q.P[n - 2]) * q.inv_de;
     const double elast = q.e0 + (double)(n - 1) * q.de;
     P = q.P[n - 1] + (e - elast) * dP;
     return;
   }
   const double p0 = q.P[s.i], p1 = q.P[s.i + 1];
   P = p0 + s.f * (p1 - p0);
-  dP = (p1 - p0) / q.de;
+  dP = (p1 - p0) * q.inv_de;
 }
 
 // P and T (viscous source).
@@ -105,13 +108,13 @@ __device__ __forceinline__ void eos_p_t(const EosDev& q, double e, double& P, do
   e = e > 0.0 ? e : 0.0;
   if (q.kind == 0) {
     P = e * (1.0 / 3.0);
-    T = sqrt(sqrt(e / q.c_sb));
+    T = sqrt(sqrt(e * q.inv_csb));
     return;
   }
   EosSeg s = eos_seg(q, e);
   const int n = q.n;
   if (s.beyond) {
-    const double slope = (q.P[n - 1] - q.P[n - 2]) / q.de;
+    const double slope = (q.P[n - 1] - q.P[n - 2]) * q.inv_de;
     const double elast = q.e0 + (double)(n - 1) * q.de;
     P = q.P[n - 1] + (e - elast) * slope;
     T = q.T[n - 1] * sqrt(sqrt((e + P) / (elast + q.P[n - 1])));
@@ -251,10 +254,10 @@ __device__ __forceinline__ double local_speed(double ut, double ux, double uy, d
   const double v2 = (ux * ux + uy * uy + ue * ue) * inv * inv;
   double disc = inv * inv * (1.0 - v2 * cs2 - vd * vd * (1.0 - cs2));
   disc = disc < 0.0 ? 0.0 : disc;
-  const double root = sqrt(cs2) * sqrt(disc);
-  const double den = 1.0 - v2 * cs2;
+  const double root = sqrt(cs2 * disc);
+  const double inv_den = 1.0 / (1.0 - v2 * cs2);
   const double a = vd * (1.0 - cs2);
-  return fmax(fabs((a + root) / den), fabs((a - root) / den));
+  return (fabs(a) + root) * inv_den;  // = max(|a + root|, |a - root|) / den, root >= 0
 }
 
 // pi~ component index of the symmetric pair (mu, nu).

@@ -77,3 +77,25 @@ def test_workspace_size_and_state_errors():
             K.ktmi_bind(h, 256, n - 8, 0)
     finally:
         K.ktmi_destroy(h)
+
+
+def test_tile_shapes_cover_256_threads():
+    import paper_1802_04449_amd as K
+    n = K.ktmi_tile_count()
+    assert n >= 4
+    for t in range(n):
+        tx, ty, tz = K.ktmi_tile_shape(t)
+        assert tx * ty * tz == 256
+    with pytest.raises(K.KtmiError):
+        K.ktmi_tile_shape(n)
+    d = _desc(nx=50, ny=40, ne=1)
+    h = K.ktmi_create(d)
+    try:
+        tx, ty, tz = K.ktmi_tile_shape(K.ktmi_get_tile(h))
+        assert tz == 1  # a boost-invariant grid gets a flat tile automatically
+        K.ktmi_set_tile(h, 0)
+        assert K.ktmi_get_tile(h) == 0
+        with pytest.raises(K.KtmiError):
+            K.ktmi_set_tile(h, n)
+    finally:
+        K.ktmi_destroy(h)

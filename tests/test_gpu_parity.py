@@ -169,3 +169,21 @@ def test_hotspots_viscous_full_size_201x201x105():
     wl = W.hotspots_viscous(steps=2)
     threads = min(16, os.cpu_count() or 1)
     _both(wl, 2, threads=threads)
+
+
+def test_tile_shapes_bitwise_identical():
+    """Every workgroup tile shape computes each face once with the same arithmetic,
+    so the fields are bitwise identical whichever shape the launcher uses."""
+    import paper_1802_04449_amd as K
+    wl = W.hotspots_viscous(nx=27, ny=23, ne=19, dx=0.45, dy=0.45, de=0.4, steps=4, seed=9)
+    _say("tile shapes")
+    ref = None
+    for t in range(K.ktmi_tile_count()):
+        f = G.run_gpu(wl, 4, tile=t).fields()
+        if ref is None:
+            ref = f
+            of = G.run_oracle(wl, 4).fields()
+            G.assert_parity(f, of, TOL, "tile 0")
+            continue
+        for k in f:
+            assert np.array_equal(f[k], ref[k]), (t, k)
