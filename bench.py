@@ -41,12 +41,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--workload", default="hotspots", choices=["hotspots", "gubser_dense"],
+    ap.add_argument("--workload", default="hotspots",
+                    choices=["hotspots", "gubser_dense", "large", "batch64"],
                     help="hotspots: the benchmark configuration; gubser_dense: the same grid and "
-                         "physics with a smooth Gubser profile that leaves no vacuum cells")
+                         "physics with a smooth Gubser profile that leaves no vacuum cells; large: "
+                         "385x385x129 single event; batch64: 64 uneven events in grouped launches")
+    ap.add_argument("--graph", action="store_true", help="replay each step as a HIP graph")
     ap.add_argument("--autotune", action="store_true",
                     help="time every tile shape first (on a discarded run) and use the fastest")
     ap.add_argument("--tile", type=int, default=-1, help="tile shape index (-1: library default)")
+    ap.add_argument("--precision", type=int, default=0,
+                    help="0: plain FP64; 1: mixed (FP32 flux/relaxation, FP64 root solve and sources)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (counter calibration)")
     args = ap.parse_args()
@@ -64,18 +69,31 @@ def main():
     import paper_1802_04449_amd as K
     from hydro_inputs import workloads as W
 
-    wl = (W.hotspots_viscous(steps=args.steps) if args.workload == "hotspots"
-          else W.gubser_dense_viscous(steps=args.steps))
+    if args.workload == "batch64":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
+    wl = {"hotspots": W.hotspots_viscous, "gubser_dense": W.gubser_dense_viscous,
+          "large": W.large_event}[args.workload](steps=args.steps)
     p = wl.params
-    g = K.Hydro(tile=args.tile, **p)
+    stream = torch.cuda.Stream() if args.graph else None
+    g = K.Hydro(tile=args.tile, precision=args.precision, stream=stream, **p)
     g.set_eos(wl.eos)
+
+    def initial():
+        if wl.T4 is not None:
+            g.set_initial_conserved(wl.T4)
+        else:
+            g.set_initial(wl.ic)
+
     tile_times = None
     if args.autotune:
         # tune on a throwaway copy of the state, then start the measured run afresh
         from paper_1802_04449_amd import autotune
-        g.set_initial(wl.ic)
+        initial()
         tile, tile_times = autotune.tune(g, steps=3, use_cache=False)
-    g.set_initial(wl.ic)
+    initial()
+    if args.graph:
+        g.set_graph(True)
     g.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -113,12 +131,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == 0 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "nx": p["nx"], "ny": p["ny"], "ne": p["ne"],
                    "dx": p["dx"], "deta": p["de"], "tau0": p["tau0"], "h": p["h"],
                    "eta_over_s": p["etas"], "ic": wl.note or "200 Gaussian hotspots, seed 1",
-                   "eos": "1555-row synthetic crossover table", "path": "plain FP64"},
+                   "eos": "1555-row synthetic crossover table",
+                   "path": "plain FP64" if args.precision == 0 else "mixed FP32/FP64"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_cell": bpc[dom]},
@@ -132,9 +151,45 @@ def main():
         "context": {"paper_table_II_viscous_gpu_cell_updates_per_s": 1.69e7,
                     "paper_hardware": "AMD FirePro S9150, 385x385x115 cells"},
     }
+    out["graph"] = bool(args.graph)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """64 uneven events (grids 101^2..301^2 x {1, 33, 65, 105}, eta/s in {0, 0.08, 0.16})
+    stepped together: per stage one launch per (mode, tile, precision) class."""
+    import torch
+
+    import paper_1802_04449_amd as K
+    from hydro_inputs import workloads as W
+
+    evs = W.event_batch(nev=64, steps=args.steps)
+    st = torch.cuda.Stream()
+    hs = []
+    for wl in evs:
+        h = K.Hydro(stream=st, precision=args.precision, **wl.params)
+        h.set_eos(wl.eos)
+        h.set_initial(wl.ic)
+        hs.append(h)
+    grp = K.Group(hs)
+    if args.graph:
+        grp.set_graph(True)
+    grp.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grp.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cells = sum(wl.ncell for wl in evs)
+    return {"metric": "cell-updates/s of viscous KT+RK2 step, plain FP64 vs batched/learned/FP32 @1e-6",
+            "value": cells * args.steps / dt, "unit": "cell-updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if args.precision == 0 else "f32+f64", "data": "synthetic",
+            "config": {"workload": "batch of 64 uneven events", "cells": cells,
+                       "classes": grp.classes, "graph": bool(args.graph)}}
 
 
 def copy_calibration():

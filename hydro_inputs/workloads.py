@@ -79,4 +79,39 @@ def gubser_dense_viscous(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps
                     ic=ics.gubser_ideal(g, 0.6), note="ideal Gubser profile at tau0, no vacuum")
 
 
+def large_event(nx=385, ny=385, ne=129, dx=0.08, dy=0.08, de=0.15, steps=1000, seed=2,
+                etas=0.08, h=0.005) -> Workload:
+    """Large single event: 385x385x129 cells, dx = dy = 0.08 fm, deta = 0.15, h = 0.005 fm
+    (the step of the 201^3-class grid scaled with the spacing, keeping the CFL number),
+    tau0 = 0.6 fm, eta/s = 0.08, hotspots + mini-jets initial state (seed 2)."""
+    p = _params(nx, ny, ne, dx, dy, de, 0.6, h, etas=etas, viscous=True)
+    g = ics.Grid(nx, ny, ne, dx, dy, de)
+    return Workload(f"large_event_{nx}x{ny}x{ne}", p, E.cached_synthetic_table(), steps,
+                    T4=ics.hotspots_with_minijets(g, 0.6, seed), note="hotspots + 400 mini-jets")
+
+
+def event_batch(nev=64, seed0=1000, steps=200, sizes=None):
+    """A batch of uneven viscous events: nx = ny drawn uniformly from the odd
+    numbers 101..301, n_eta from {1 (boost invariant), 33, 65, 105}, eta/s from
+    {0 (ideal), 0.08, 0.16}; hotspot initial state with seed seed0 + e; spacings,
+    tau0 and h as in the 201x201x105 benchmark grid.  `sizes` optionally overrides
+    the drawn (n, n_eta, eta/s) triples (for small test batches)."""
+    import numpy as np
+    rng = np.random.default_rng(seed0)
+    out = []
+    for e in range(nev):
+        if sizes is not None:
+            n, ne, etas = sizes[e]
+        else:
+            n = int(rng.choice(np.arange(101, 302, 2)))
+            ne = int(rng.choice([1, 33, 65, 105]))
+            etas = float(rng.choice([0.0, 0.08, 0.16]))
+        wl = hotspots_viscous(nx=n, ny=n, ne=ne, steps=steps, seed=seed0 + e, etas=etas)
+        if etas == 0.0:
+            wl.params["viscous"] = 0
+        wl.name = f"event{e}_{n}x{n}x{ne}_etas{etas}"
+        out.append(wl)
+    return out
+
+
 C1_FULL = dict(nx=201, ny=201, ne=105)

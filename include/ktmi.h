@@ -69,7 +69,9 @@ typedef struct ktmi_desc {
     double newton_tol;   /* relative tolerance of the root solve */
     int newton_maxit;    /* iteration cap of the root solve */
     double pi_reg;       /* cap on sqrt(|pi~:pi~|)/(e+P); <= 0 disables */
-    int precision;       /* KTMI_FP64 */
+    int precision;       /* KTMI_FP64, or KTMI_MIXED: FP32 reconstruction, fluxes, local
+                            speed and shear relaxation source; FP64 root solve, geometric
+                            source, state and accumulators */
     int guess;           /* KTMI_GUESS_* */
     int tile;            /* workgroup tile shape index (ktmi_tile_shape); -1 = automatic */
 } ktmi_desc;
@@ -161,6 +163,32 @@ int ktmi_tile_shape(int t, int *tx, int *ty, int *tz);
  * thread slots).  The workspace is sized for every shape. */
 int ktmi_set_tile(ktmi_handle *h, int t);
 int ktmi_get_tile(const ktmi_handle *h);
+
+/* Replays one captured step as a HIP graph on every later ktmi_step (on = 1).
+ * Every step issues identical launches (time and buffer parity live in device
+ * memory), so the graph of one step is valid for all steps.  Needs a
+ * non-default stream; ignored while timing is on.  KTMI_EINVAL on the default
+ * stream. */
+int ktmi_set_graph(ktmi_handle *h, int on);
+
+/* Groups: step many events (possibly of different grids and modes) together.
+ * Events are sorted into classes of equal (viscous, precision, tile); per class
+ * and stage a single launch covers the tiles of all its events (at most 128 per
+ * class), and one reduce launch serves them all.  The handles keep their own
+ * workspaces and states; the group only needs a device table of
+ * ktmi_group_workspace_bytes(nev) bytes (256-byte aligned, caller-owned).  All
+ * handles must share one stream and have an initial state; rebuild the group
+ * after changing a handle's tile or EoS.  ktmi_read / ktmi_diag on a member
+ * handle see the grouped steps. */
+typedef struct ktmi_group ktmi_group;
+size_t ktmi_group_workspace_bytes(int nev);
+int ktmi_group_create(ktmi_handle *const *hs, int nev, void *dev_ws, size_t bytes,
+                      ktmi_group **out);
+int ktmi_group_step(ktmi_group *g, int n);
+int ktmi_group_set_graph(ktmi_group *g, int on);
+int ktmi_group_class_count(const ktmi_group *g);
+const char *ktmi_group_last_error(const ktmi_group *g);
+void ktmi_group_destroy(ktmi_group *g);
 
 /* Message of the last error on h (or of the last failed ktmi_create if h is
  * NULL).  Valid until the next call on h. */

@@ -67,6 +67,11 @@ def load():
     lib.orc_local_speed.argtypes = [C.c_int, P, C.c_int, P, P]
     lib.orc_shear_at.argtypes = [C.c_void_p, P, P, P, C.c_double, C.c_int, C.c_int, C.c_int, P]
     lib.orc_set_mutant.argtypes = [C.c_int]
+    lib.orc_mlp_nparam.restype = C.c_int
+    lib.orc_mlp_forward.argtypes = [P, C.c_int, P, P, P]
+    lib.orc_mlp_loss_grad.argtypes = [P, C.c_int, P, P, P, P, P]
+    lib.orc_mlp_adam.argtypes = [P, P, P, P, C.c_int, C.c_double, C.c_double, C.c_double,
+                                 C.c_double]
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_max_threads.restype = C.c_int
     _lib = lib
@@ -225,3 +230,28 @@ def local_speed(u3, axis, cs2):
 
 
 C2P_FALLBACK, C2P_NONCONV, C2P_NAN, C2P_VAC, C2P_CLAMP = 1, 2, 4, 8, 16
+
+
+# ---- learned root-solve guess (FP64 reference) ----
+def mlp_nparam() -> int:
+    return int(load().orc_mlp_nparam())
+
+
+def mlp_forward(params, E, M):
+    p, E, M = _c(params), _c(E).reshape(-1), _c(M).reshape(-1)
+    out = np.empty(E.size)
+    load().orc_mlp_forward(_p(p), E.size, _p(E), _p(M), _p(out))
+    return out
+
+
+def mlp_loss_grad(params, E, M, eps):
+    p, E, M, e = _c(params), _c(E).reshape(-1), _c(M).reshape(-1), _c(eps).reshape(-1)
+    loss = np.zeros(1)
+    g = np.empty(p.size)
+    load().orc_mlp_loss_grad(_p(p), E.size, _p(E), _p(M), _p(e), _p(loss), _p(g))
+    return float(loss[0]), g
+
+
+def mlp_adam(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, epsilon=1e-8):
+    """In-place Adam step on float64 arrays params, m, v."""
+    load().orc_mlp_adam(_p(params), _p(_c(grad)), _p(m), _p(v), int(t), lr, b1, b2, epsilon)

@@ -44,6 +44,9 @@ class ktmi_diagnostics(C.Structure):
 
 
 def _load():
+    # torch first: libktmi.so then binds to the HIP runtime torch already loaded, so
+    # device memory from torch and the library's launches share one runtime
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with python -c "
                           "'import __graft_entry__ as g; g.build()' (no CPU fallback exists)")
@@ -70,6 +73,14 @@ def _load():
                                       C.POINTER(C.c_int)]),
         "ktmi_set_tile": (C.c_int, [vp, C.c_int]),
         "ktmi_get_tile": (C.c_int, [vp]),
+        "ktmi_set_graph": (C.c_int, [vp, C.c_int]),
+        "ktmi_group_workspace_bytes": (sz, [C.c_int]),
+        "ktmi_group_create": (C.c_int, [C.POINTER(vp), C.c_int, vp, sz, C.POINTER(vp)]),
+        "ktmi_group_step": (C.c_int, [vp, C.c_int]),
+        "ktmi_group_set_graph": (C.c_int, [vp, C.c_int]),
+        "ktmi_group_class_count": (C.c_int, [vp]),
+        "ktmi_group_last_error": (C.c_char_p, [vp]),
+        "ktmi_group_destroy": (None, [vp]),
         "ktmi_last_error": (C.c_char_p, [vp]),
         "ktmi_destroy": (None, [vp]),
     }
@@ -184,6 +195,43 @@ def ktmi_get_tile(h) -> int:
     return int(lib.ktmi_get_tile(h))
 
 
+def ktmi_set_graph(h, on: bool):
+    _check(lib.ktmi_set_graph(h, int(bool(on))), h)
+
+
+def ktmi_group_workspace_bytes(nev: int) -> int:
+    return int(lib.ktmi_group_workspace_bytes(int(nev)))
+
+
+def _gcheck(rc, g):
+    if rc != KTMI_OK:
+        msg = lib.ktmi_group_last_error(g)
+        raise KtmiError(f"ktmi group error {rc}: {msg.decode() if msg else ''}")
+
+
+def ktmi_group_create(handles, dev_ptr: int, nbytes: int):
+    arr = (C.c_void_p * len(handles))(*[h.value for h in handles])
+    g = C.c_void_p()
+    _check(lib.ktmi_group_create(arr, len(handles), C.c_void_p(dev_ptr), nbytes, C.byref(g)))
+    return g
+
+
+def ktmi_group_step(g, n: int):
+    _gcheck(lib.ktmi_group_step(g, int(n)), g)
+
+
+def ktmi_group_set_graph(g, on: bool):
+    _gcheck(lib.ktmi_group_set_graph(g, int(bool(on))), g)
+
+
+def ktmi_group_class_count(g) -> int:
+    return int(lib.ktmi_group_class_count(g))
+
+
+def ktmi_group_destroy(g):
+    lib.ktmi_group_destroy(g)
+
+
 def ktmi_destroy(h):
     lib.ktmi_destroy(h)
 
@@ -271,3 +319,41 @@ class Hydro:
 
     def diag(self):
         return ktmi_diag(self.h)
+
+    def set_graph(self, on=True):
+        ktmi_set_graph(self.h, on)
+
+
+class Group:
+    """Several Hydro objects stepped together (one launch per class and stage).
+    All members must use the same (non-default, for graphs) torch stream."""
+
+    def __init__(self, members):
+        import torch
+        self.torch = torch
+        self.members = list(members)
+        nb = ktmi_group_workspace_bytes(len(self.members))
+        dev = self.members[0].device
+        self.ws = torch.empty(nb // 8 + 32, dtype=torch.float64, device=dev)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.g = ktmi_group_create([m.h for m in self.members], ptr, nb)
+
+    def __del__(self):
+        g = getattr(self, "g", None)
+        if g:
+            try:
+                self.torch.cuda.synchronize()
+            except Exception:
+                pass
+            ktmi_group_destroy(g)
+            self.g = None
+
+    def step(self, n=1):
+        ktmi_group_step(self.g, n)
+
+    def set_graph(self, on=True):
+        ktmi_group_set_graph(self.g, on)
+
+    @property
+    def classes(self):
+        return ktmi_group_class_count(self.g)

@@ -65,9 +65,41 @@ struct Geo {
   int cart;
 };
 
-// Tile grid of one launch.
+// Tile grid of one event.
 struct TileGrid {
   int ntx, nty, ntz, ntiles;
+};
+
+// Everything a stencil kernel needs about one event, kept in device memory so
+// that every step issues identical launches (graph replay) and one launch can
+// cover the tiles of many events.  The clock (tau, step count, parity of the
+// u~ / u~prev buffers) lives in the event's workspace and is advanced on the
+// device by the reduce kernel at the end of every step.
+struct EventDesc {
+  Fields f;  // u and up as for parity 0
+  StepParams p;
+  EosDev eos;
+  TileGrid tg;
+  int cart;
+  int viscous;
+  double* clock;  // [0] tau, [1] steps taken, [2] parity
+};
+
+constexpr int kMaxGroup = 128;  // events per grouped launch
+struct GroupTable {
+  int nev;
+  int start[kMaxGroup + 1];  // first tile of each event in the launch
+};
+
+// Per-block view of its event.  stage2 = 0: tau = tau_n, tau1 = tau_n + h;
+// stage2 = 1: tau = tau1 = tau_n + h.
+struct Ctx {
+  Fields f;
+  StepParams p;
+  EosDev eos;
+  TileGrid tg;
+  Geo g;
+  int tile;  // tile index inside the event
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -89,10 +121,34 @@ struct Pos {
   bool active;
 };
 
+__device__ __forceinline__ Ctx load_ctx(const EventDesc* __restrict__ evs, const GroupTable& gt,
+                                        int stage2) {
+  const int t = tile_of_block(gt.start[gt.nev]);
+  int e = 0;
+  while (e + 1 < gt.nev && t >= gt.start[e + 1]) ++e;
+  const EventDesc& E = evs[e];
+  Ctx c;
+  c.f = E.f;
+  c.p = E.p;
+  c.eos = E.eos;
+  c.tg = E.tg;
+  const double tau = E.clock[0];
+  const bool odd = E.clock[2] != 0.0;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    c.f.u[m] = odd ? E.f.up[m] : E.f.u[m];
+    c.f.up[m] = odd ? E.f.u[m] : E.f.up[m];
+  }
+  c.g.cart = E.cart;
+  c.g.tau1 = tau + E.p.h;
+  c.g.tau = stage2 ? c.g.tau1 : tau;
+  c.tile = t - gt.start[e];
+  return c;
+}
+
 template <int TX, int TY, int TZ>
-__device__ __forceinline__ Pos cell_pos(const StepParams& p, const TileGrid& tg) {
+__device__ __forceinline__ Pos cell_pos(const StepParams& p, const TileGrid& tg, int t) {
   Pos q;
-  const int t = tile_of_block(tg.ntiles);
   const int tk = t % tg.ntz, r = t / tg.ntz;
   const int tj = r % tg.nty, ti = r / tg.nty;
   q.i0 = ti * TX;
@@ -125,62 +181,76 @@ __device__ __forceinline__ double ld_pi(const double* const* pi, int m, int idx,
 // Components 0..3: T~^{d nu} part (if DO_T); 4..13: u~^d pi~ part (if DO_PI).
 // Returns the face's local speed c.  A face whose four stencil cells are exact
 // vacuum (all primitives zero) has H = 0 and c = c_vac, so it skips the arithmetic.
-template <bool DO_T, bool DO_PI, int PI_SRC>
-__device__ __forceinline__ double face_flux(const double* __restrict__ e, const double* const* u,
-                                            const double* const* pi, int base, int a, int n,
-                                            int stride, int axis, double tauf,
-                                            const StepParams& p, const EosDev& eos,
-                                            double H[14]) {
+// R is the arithmetic type (double, or float on the mixed-precision path).
+template <typename R, bool DO_T, bool DO_PI, int PI_SRC>
+__device__ __forceinline__ R face_flux(const double* __restrict__ e, const double* const* u,
+                                       const double* const* pi, int base, int a, int n,
+                                       int stride, int axis, R tauf, const StepParams& p,
+                                       const EosDev& eos, R H[14]) {
   int idx[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) idx[t] = base + clampi(a - 1 + t, 0, n - 1) * stride;
-  double q4[14][4];
+  // Vacuum test first, on the stored FP64 values: every state the kernels write
+  // has u~ = 0 where e = 0 (the root solve and the cutoff return all-zero
+  // primitives), and with PI_SRC 0/1 pi~ is zero there as well, so e alone
+  // decides; as-stored pi~ (PI_SRC 2) is checked too.  A vacuum face then skips
+  // the remaining loads and all arithmetic.
+  double ev[4];
+  bool vac = true;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) q4[0][t] = e[idx[t]];
+  for (int t = 0; t < 4; ++t) {
+    ev[t] = e[idx[t]];
+    vac = vac && (ev[t] == 0.0);
+  }
+  if (PI_SRC == 2 && vac) {
+#pragma unroll
+    for (int m = 0; m < 10; ++m)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) vac = vac && (pi[m][idx[t]] == 0.0);
+  }
+  if (vac) {
+#pragma unroll
+    for (int k = 0; k < 14; ++k) H[k] = R(0);
+    return (R)p.c_vac;
+  }
+  // Load the rest of the 4-cell stencil, converting to R at once.
+  R q4[14][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) q4[0][t] = (R)ev[t];
 #pragma unroll
   for (int m = 0; m < 3; ++m)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) q4[1 + m][t] = u[m][idx[t]];
+    for (int t = 0; t < 4; ++t) q4[1 + m][t] = (R)u[m][idx[t]];
 #pragma unroll
   for (int m = 0; m < 10; ++m)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) q4[4 + m][t] = ld_pi<PI_SRC>(pi, m, idx[t], q4[0][t]);
-  bool vac = true;
-  const int nchk = (PI_SRC == 2) ? 14 : 4;  // with PI_SRC 0/1, e == 0 implies pi~ = 0
-#pragma unroll
-  for (int v = 0; v < 14; ++v)
-    if (v < nchk)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) vac = vac && (q4[v][t] == 0.0);
-  if (vac) {
-#pragma unroll
-    for (int k = 0; k < 14; ++k) H[k] = 0.0;
-    return p.c_vac;
-  }
-  double qL[14], qR[14];
+    for (int t = 0; t < 4; ++t) q4[4 + m][t] = (R)ld_pi<PI_SRC>(pi, m, idx[t], ev[t]);
+  R qL[14], qR[14];
+  const R th = (R)p.theta;
 #pragma unroll
   for (int v = 0; v < 14; ++v) {
-    qL[v] = q4[v][1] + 0.5 * mm_slope(p.theta, q4[v][0], q4[v][1], q4[v][2]);
-    qR[v] = q4[v][2] - 0.5 * mm_slope(p.theta, q4[v][1], q4[v][2], q4[v][3]);
+    const R a0 = q4[v][0], a1 = q4[v][1], a2 = q4[v][2], a3 = q4[v][3];
+    qL[v] = a1 + R(0.5) * mm_slope_r<R>(th, a0, a1, a2);
+    qR[v] = a2 - R(0.5) * mm_slope_r<R>(th, a1, a2, a3);
   }
-  double QL[14], FL[14], QR[14], FR[14], sL, sR;
+  R QL[14], FL[14], QR[14], FR[14], sL, sR;
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
-    const double* q = side ? qR : qL;
-    double* Q = side ? QR : QL;
-    double* F = side ? FR : FL;
-    const double ux = q[1], uy = q[2], ue = q[3];
-    const double ut = sqrt(1.0 + ux * ux + uy * uy + ue * ue);
-    double P, cs2;
-    eos_p_cs2(eos, q[0], P, cs2);
-    const double w = (q[0] > 0.0 ? q[0] : 0.0) + P;
-    const double u4[4] = {ut, ux, uy, ue};
-    const double ud = u4[axis];
+    const R* q = side ? qR : qL;
+    R* Q = side ? QR : QL;
+    R* F = side ? FR : FL;
+    const R ux = q[1], uy = q[2], ue = q[3];
+    const R ut = sqrt(R(1) + ux * ux + uy * uy + ue * ue);
+    R P, cs2;
+    eos_p_cs2_r<R>(eos, q[0], P, cs2);
+    const R w = (q[0] > R(0) ? q[0] : R(0)) + P;
+    const R u4[4] = {ut, ux, uy, ue};
+    const R ud = u4[axis];
     if (DO_T) {
 #pragma unroll
       for (int nu = 0; nu < 4; ++nu) {
-        Q[nu] = tauf * (w * ut * u4[nu] - (nu == 0 ? P : 0.0) + q[4 + sym(0, nu)]);
-        F[nu] = tauf * (w * ud * u4[nu] + (nu == axis ? P : 0.0) + q[4 + sym(axis, nu)]);
+        Q[nu] = tauf * (w * ut * u4[nu] - (nu == 0 ? P : R(0)) + q[4 + sym(0, nu)]);
+        F[nu] = tauf * (w * ud * u4[nu] + (nu == axis ? P : R(0)) + q[4 + sym(axis, nu)]);
       }
     }
     if (DO_PI) {
@@ -190,17 +260,17 @@ __device__ __forceinline__ double face_flux(const double* __restrict__ e, const 
         F[4 + m] = ud * q[4 + m];
       }
     }
-    const double s = local_speed(ut, ux, uy, ue, ud, cs2);
+    const R s = local_speed_r<R>(ut, ux, uy, ue, ud, cs2);
     if (side)
       sR = s;
     else
       sL = s;
   }
-  const double c = fmax(sL, sR);
+  const R c = fmax(sL, sR);
 #pragma unroll
   for (int k = 0; k < 14; ++k) {
     const bool on = k < 4 ? DO_T : DO_PI;
-    H[k] = on ? 0.5 * (FL[k] + FR[k]) - 0.5 * c * (QR[k] - QL[k]) : 0.0;
+    H[k] = on ? R(0.5) * (FL[k] + FR[k]) - R(0.5) * c * (QR[k] - QL[k]) : R(0);
   }
   return c;
 }
@@ -209,12 +279,12 @@ __device__ __forceinline__ double face_flux(const double* __restrict__ e, const 
 // R[q] = -sum_d (H_{+1/2} - H_{-1/2}) / Delta_d.  Every face of the tile is
 // computed once by one thread and staged in LDS (component-major).  Returns
 // max over the computed faces of c / Delta (for the CFL diagnostic).
-template <int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC>
+template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC>
 __device__ __forceinline__ double tile_divergence(const double* __restrict__ e,
                                                   const double* const* u, const double* const* pi,
                                                   const StepParams& p, const EosDev& eos,
                                                   double tauf, const Pos& q, double R[14],
-                                                  double* lds) {
+                                                  RT* lds) {
   constexpr int N = TX * TY * TZ;
 #pragma unroll
   for (int k = 0; k < 14; ++k) R[k] = 0.0;
@@ -250,16 +320,16 @@ __device__ __forceinline__ double tile_divergence(const double* __restrict__ e,
       const int gi = q.i0 + fx, gj = q.j0 + fy, gk = q.k0 + fz;
       const int ga = (d == 0 ? q.i0 : (d == 1 ? q.j0 : q.k0)) + a;  // right cell of the face
       const bool inrow = (d == 0 || gi < p.nx) && (d == 1 || gj < p.ny) && (d == 2 || gk < p.ne);
-      double H[14];
+      RT H[14];
       if (inrow && ga <= nd) {
         const int base = d == 0 ? (gj * p.ne + gk)
                                 : (d == 1 ? (gi * p.ny) * p.ne + gk : (gi * p.ny + gj) * p.ne);
-        const double c = face_flux<DO_T, DO_PI, PI_SRC>(e, u, pi, base, ga - 1, nd, stride, d + 1,
-                                                        tauf, p, eos, H);
-        cfl = fmax(cfl, c * inv_del);
+        const RT c = face_flux<RT, DO_T, DO_PI, PI_SRC>(e, u, pi, base, ga - 1, nd, stride, d + 1,
+                                                        (RT)tauf, p, eos, H);
+        cfl = fmax(cfl, (double)c * inv_del);
       } else {
 #pragma unroll
-        for (int k = 0; k < 14; ++k) H[k] = 0.0;
+        for (int k = 0; k < 14; ++k) H[k] = RT(0);
       }
 #pragma unroll
       for (int k = 0; k < 14; ++k) lds[k * F + f] = H[k];
@@ -277,8 +347,9 @@ __device__ __forceinline__ double tile_divergence(const double* __restrict__ e,
         fm = (q.lx * TY + q.ly) * (TZ + 1) + q.lz;
         fp = fm + 1;
       }
+      const RT rinv = (RT)inv_del;
 #pragma unroll
-      for (int k = 0; k < 14; ++k) R[k] -= (lds[k * F + fp] - lds[k * F + fm]) * inv_del;
+      for (int k = 0; k < 14; ++k) R[k] -= (double)((lds[k * F + fp] - lds[k * F + fm]) * rinv);
     }
     __syncthreads();
   }
@@ -305,36 +376,43 @@ __device__ __forceinline__ double utau(double a, double b, double c) {
 // sigma~, theta, D~u~ from nabla~_mu u~^nu (eq. dtuz), b^nu = pi^{nu beta} g_{beta beta} a^beta.
 // uE/uL: time levels for d_tau u~.  With eta = (eta/s)(e+P) hbarc/T and
 // tau_pi = 5 (eta/s) hbarc/T, eta/tau_pi = (e+P)/5.
+template <typename R>
 __device__ __forceinline__ void pi_source(const double* const* u, const double* const* uE,
                                           const double* const* uL, const StepParams& p,
                                           const EosDev& eos, const Geo& g, const Pos& q,
-                                          double ec, const double pc[10], double S[10]) {
+                                          double ec_d, const double pc_d[10], double S_d[10]) {
+  const R ec = (R)ec_d;
+  R pc[10];
+#pragma unroll
+  for (int m = 0; m < 10; ++m) pc[m] = (R)pc_d[m];
   const int c0 = q.c;
   const int cart = g.cart;
-  const double tau = g.tau;
-  const double inv_tau = 1.0 / tau;
-  const double uc[4] = {utau(u[0][c0], u[1][c0], u[2][c0]), u[0][c0], u[1][c0], u[2][c0]};
-  double G[4][4];
+  const R inv_tau = (R)(1.0 / g.tau);
+  const R u1c = (R)u[0][c0], u2c = (R)u[1][c0], u3c = (R)u[2][c0];
+  const R uc[4] = {sqrt(R(1) + u1c * u1c + u2c * u2c + u3c * u3c), u1c, u2c, u3c};
+  R G[4][4];
   {
-    const double a1 = uE[0][c0], a2 = uE[1][c0], a3 = uE[2][c0];
-    const double b1 = uL[0][c0], b2 = uL[1][c0], b3 = uL[2][c0];
-    const double ea[4] = {utau(a1, a2, a3), a1, a2, a3};
-    const double eb[4] = {utau(b1, b2, b3), b1, b2, b3};
+    const R a1 = (R)uE[0][c0], a2 = (R)uE[1][c0], a3 = (R)uE[2][c0];
+    const R b1 = (R)uL[0][c0], b2 = (R)uL[1][c0], b3 = (R)uL[2][c0];
+    const R ea[4] = {sqrt(R(1) + a1 * a1 + a2 * a2 + a3 * a3), a1, a2, a3};
+    const R eb[4] = {sqrt(R(1) + b1 * b1 + b2 * b2 + b3 * b3), b1, b2, b3};
+    const R ih = (R)p.inv_h;
 #pragma unroll
-    for (int nu = 0; nu < 4; ++nu) G[0][nu] = (eb[nu] - ea[nu]) * p.inv_h;
+    for (int nu = 0; nu < 4; ++nu) G[0][nu] = (eb[nu] - ea[nu]) * ih;
   }
   const int n3[3] = {p.nx, p.ny, p.ne};
   const int co[3] = {q.i, q.j, q.k};
   const int st[3] = {p.ny * p.ne, p.ne, 1};
-  const double ihalf[3] = {0.5 * p.inv_dx, 0.5 * p.inv_dy, 0.5 * p.inv_de * (cart ? 1.0 : inv_tau)};
+  const R ihalf[3] = {(R)(0.5 * p.inv_dx), (R)(0.5 * p.inv_dy),
+                      (R)(0.5 * p.inv_de * (cart ? 1.0 : 1.0 / g.tau))};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int ip = c0 + (clampi(co[d] + 1, 0, n3[d] - 1) - co[d]) * st[d];
     const int im = c0 + (clampi(co[d] - 1, 0, n3[d] - 1) - co[d]) * st[d];
-    const double p1 = u[0][ip], p2 = u[1][ip], p3 = u[2][ip];
-    const double m1 = u[0][im], m2 = u[1][im], m3 = u[2][im];
-    const double up4[4] = {utau(p1, p2, p3), p1, p2, p3};
-    const double um4[4] = {utau(m1, m2, m3), m1, m2, m3};
+    const R p1 = (R)u[0][ip], p2 = (R)u[1][ip], p3 = (R)u[2][ip];
+    const R m1 = (R)u[0][im], m2 = (R)u[1][im], m3 = (R)u[2][im];
+    const R up4[4] = {sqrt(R(1) + p1 * p1 + p2 * p2 + p3 * p3), p1, p2, p3};
+    const R um4[4] = {sqrt(R(1) + m1 * m1 + m2 * m2 + m3 * m3), m1, m2, m3};
 #pragma unroll
     for (int nu = 0; nu < 4; ++nu) G[d + 1][nu] = (up4[nu] - um4[nu]) * ihalf[d];
   }
@@ -342,36 +420,36 @@ __device__ __forceinline__ void pi_source(const double* const* u, const double* 
     G[3][0] += uc[3] * inv_tau;
     G[3][3] += uc[0] * inv_tau;
   }
-  const double theta = G[0][0] + G[1][1] + G[2][2] + G[3][3];
-  double a[4];
+  const R theta = G[0][0] + G[1][1] + G[2][2] + G[3][3];
+  R a[4];
 #pragma unroll
   for (int nu = 0; nu < 4; ++nu)
     a[nu] = uc[0] * G[0][nu] + uc[1] * G[1][nu] + uc[2] * G[2][nu] + uc[3] * G[3][nu];
-  const double gt[4] = {1.0, -1.0, -1.0, -1.0};
-  double b[4];
+  const R gt[4] = {R(1), R(-1), R(-1), R(-1)};
+  R b[4];
 #pragma unroll
   for (int nu = 0; nu < 4; ++nu)
     b[nu] = pc[sym(nu, 0)] * a[0] - pc[sym(nu, 1)] * a[1] - pc[sym(nu, 2)] * a[2] -
             pc[sym(nu, 3)] * a[3];
-  double P, T;
-  eos_p_t(eos, ec, P, T);
-  const double inv_taupi = T * p.inv_taupi_coef;
-  const double eta_over_taupi = 0.2 * (ec + P);
-  const double ue = uc[3];
-  const double third = 1.0 / 3.0;
+  R P, T;
+  eos_p_t_r<R>(eos, ec, P, T);
+  const R inv_taupi = T * (R)p.inv_taupi_coef;
+  const R eta_over_taupi = R(0.2) * (ec + P);
+  const R ue = uc[3];
+  const R third = R(1) / R(3);
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
 #pragma unroll
     for (int nu = mu; nu < 4; ++nu) {
       const int m = sym(mu, nu);
-      const double gmn = (mu == nu) ? gt[mu] : 0.0;
-      const double sig = gt[mu] * G[mu][nu] + gt[nu] * G[nu][mu] - uc[mu] * a[nu] -
-                         uc[nu] * a[mu] - 2.0 * third * (gmn - uc[mu] * uc[nu]) * theta;
-      double s = -pc[m] * inv_taupi + eta_over_taupi * sig - pc[m] * theta * third -
-                 (uc[mu] * b[nu] + uc[nu] * b[mu]);
+      const R gmn = (mu == nu) ? gt[mu] : R(0);
+      const R sig = gt[mu] * G[mu][nu] + gt[nu] * G[nu][mu] - uc[mu] * a[nu] -
+                    uc[nu] * a[mu] - R(2) * third * (gmn - uc[mu] * uc[nu]) * theta;
+      R s = -pc[m] * inv_taupi + eta_over_taupi * sig - pc[m] * theta * third -
+            (uc[mu] * b[nu] + uc[nu] * b[mu]);
       if (!cart) {
-        double I = 0.0;  // Christoffel terms I^{mu nu}
-        if (m == 0 || m == 9) I = 2.0 * ue * pc[3];
+        R I = R(0);  // Christoffel terms I^{mu nu}
+        if (m == 0 || m == 9) I = R(2) * ue * pc[3];
         else if (m == 1) I = ue * pc[6];
         else if (m == 2) I = ue * pc[8];
         else if (m == 3) I = ue * (pc[0] + pc[9]);
@@ -379,7 +457,7 @@ __device__ __forceinline__ void pi_source(const double* const* u, const double* 
         else if (m == 8) I = ue * pc[2];
         s += -(pc[m] * uc[0] + I) * inv_tau;
       }
-      S[m] = s;
+      S_d[m] = (double)s;
     }
   }
 }
@@ -411,7 +489,7 @@ __device__ __forceinline__ void regulate(const EosDev& eos, const StepParams& p,
 // ---------------------------------------------------------------------------
 // Workgroup reduction of the diagnostic partials (wave64 shuffles, then LDS).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void block_partials(double v[kNP], double* out) {
+__device__ __forceinline__ void block_partials(double v[kNP], double* out, int ntiles, int tile) {
   __shared__ double red[kBlock / 64][kNP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -429,7 +507,7 @@ __device__ __forceinline__ void block_partials(double v[kNP], double* out) {
     const int s = threadIdx.x;
     double x = red[0][s];
     for (int w = 1; w < kBlock / 64; ++w) x = is_max_slot(s) ? fmax(x, red[w][s]) : x + red[w][s];
-    out[(size_t)s * gridDim.x + blockIdx.x] = x;  // slot-major: the reduce reads coalesced
+    out[(size_t)s * ntiles + tile] = x;  // slot-major: the reduce reads coalesced
   }
 }
 
@@ -503,14 +581,19 @@ __global__ __launch_bounds__(kBlock) void k_init_conserved(Fields f, StepParams 
 }
 
 // First step: u*1 from one ideal forward-Euler step; u~^{-1} = 2 u~^0 - u*1.
-template <int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_first_estimate(Fields f, StepParams p, EosDev eos,
-                                                            Geo g, TileGrid tg) {
-  __shared__ double lds[lds_doubles<TX, TY, TZ>()];
-  const Pos q = cell_pos<TX, TY, TZ>(p, tg);
+template <typename RT, int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_first_estimate(const EventDesc* __restrict__ evs,
+                                                            GroupTable gt) {
+  __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
+  const Ctx cx = load_ctx(evs, gt, 0);
+  const Fields& f = cx.f;
+  const StepParams& p = cx.p;
+  const EosDev& eos = cx.eos;
+  const Geo& g = cx.g;
+  const Pos q = cell_pos<TX, TY, TZ>(p, cx.tg, cx.tile);
   const double tf = g.cart ? 1.0 : g.tau;
   double R[14];
-  tile_divergence<TX, TY, TZ, true, false, 0>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
+  tile_divergence<RT, TX, TY, TZ, true, false, 0>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
   if (!q.active) return;
   const int c = q.c;
   const double e = f.e[c], u1 = f.u[0][c], u2 = f.u[1][c], u3 = f.u[2][c];
@@ -536,18 +619,23 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(Fields f, StepParams 
 }
 
 // Stage 1 at tau_n (predictor) for the ideal (VISC = false) or viscous path.
-template <int TX, int TY, int TZ, bool VISC>
-__global__ __launch_bounds__(kBlock) void k_stage1(Fields f, StepParams p, EosDev eos, Geo g,
-                                                    TileGrid tg) {
-  __shared__ double lds[lds_doubles<TX, TY, TZ>()];
-  const Pos q = cell_pos<TX, TY, TZ>(p, tg);
+template <typename RT, int TX, int TY, int TZ, bool VISC>
+__global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__ evs,
+                                                    GroupTable gt) {
+  __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
+  const Ctx cx = load_ctx(evs, gt, 0);
+  const Fields& f = cx.f;
+  const StepParams& p = cx.p;
+  const EosDev& eos = cx.eos;
+  const Geo& g = cx.g;
+  const Pos q = cell_pos<TX, TY, TZ>(p, cx.tg, cx.tile);
   double v[kNP];
 #pragma unroll
   for (int s = 0; s < kNP; ++s) v[s] = 0.0;
   const double tf = g.cart ? 1.0 : g.tau;
   double R[14];
   const double cfl =
-      tile_divergence<TX, TY, TZ, true, VISC, VISC ? 1 : 0>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
+      tile_divergence<RT, TX, TY, TZ, true, VISC, VISC ? 1 : 0>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
   v[P_CFL] = cfl * p.h;
   if (q.active) {
     const int c = q.c;
@@ -569,7 +657,7 @@ __global__ __launch_bounds__(kBlock) void k_stage1(Fields f, StepParams p, EosDe
     if (VISC) {
       if (e >= p.eps_cut) {
         double S[10];
-        pi_source(f.u, f.up, f.u, p, eos, g, q, e, pc, S);
+        pi_source<RT>(f.u, f.up, f.u, p, eos, g, q, e, pc, S);
 #pragma unroll
         for (int m = 0; m < 10; ++m) R[4 + m] += S[m];
       }
@@ -602,18 +690,23 @@ __global__ __launch_bounds__(kBlock) void k_stage1(Fields f, StepParams p, EosDe
     f.u1[1][c] = s.u2;
     f.u1[2][c] = s.u3;
   }
-  block_partials(v, f.partial);
+  block_partials(v, f.partial, cx.tg.ntiles, cx.tile);
 }
 
 // Stage 2, part 1 (tau_{n+1}): pi^{n+1} = [ (u^n pi^n + u* pi')/2 + h/2 R_pi(e', u', pi') ] / u'^tau.
-template <int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_stage2_pi(Fields f, StepParams p, EosDev eos, Geo g,
-                                                      TileGrid tg) {
-  __shared__ double lds[lds_doubles<TX, TY, TZ>()];
-  const Pos q = cell_pos<TX, TY, TZ>(p, tg);
+template <typename RT, int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_stage2_pi(const EventDesc* __restrict__ evs,
+                                                      GroupTable gt) {
+  __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
+  const Ctx cx = load_ctx(evs, gt, 1);
+  const Fields& f = cx.f;
+  const StepParams& p = cx.p;
+  const EosDev& eos = cx.eos;
+  const Geo& g = cx.g;
+  const Pos q = cell_pos<TX, TY, TZ>(p, cx.tg, cx.tile);
   const double tf = g.cart ? 1.0 : g.tau;
   double R[14];
-  tile_divergence<TX, TY, TZ, false, true, 2>(f.e1, f.u1, f.pi1, p, eos, tf, q, R, lds);
+  tile_divergence<RT, TX, TY, TZ, false, true, 2>(f.e1, f.u1, f.pi1, p, eos, tf, q, R, lds);
   if (!q.active) return;
   const int c = q.c;
   const double e1 = f.e1[c];
@@ -622,7 +715,7 @@ __global__ __launch_bounds__(kBlock) void k_stage2_pi(Fields f, StepParams p, Eo
   for (int m = 0; m < 10; ++m) pc[m] = f.pi1[m][c];
   if (e1 >= p.eps_cut) {
     double S[10];
-    pi_source(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
+    pi_source<RT>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
 #pragma unroll
     for (int m = 0; m < 10; ++m) R[4 + m] += S[m];
   }
@@ -644,17 +737,22 @@ __global__ __launch_bounds__(kBlock) void k_stage2_pi(Fields f, StepParams p, Eo
 
 // Stage 2, part 2 (tau_{n+1}): T^{n+1} = T^n + [(T' - T^n) + h R_T(e', u', pi^{n+1})]/2,
 // root solve -> (e, u~)^{n+1} (written over e^n and u~^{n-1}), diagnostics.
-template <int TX, int TY, int TZ, bool VISC>
-__global__ __launch_bounds__(kBlock) void k_stage2_T(Fields f, StepParams p, EosDev eos, Geo g,
-                                                     TileGrid tg) {
-  __shared__ double lds[lds_doubles<TX, TY, TZ>()];
-  const Pos q = cell_pos<TX, TY, TZ>(p, tg);
+template <typename RT, int TX, int TY, int TZ, bool VISC>
+__global__ __launch_bounds__(kBlock) void k_stage2_T(const EventDesc* __restrict__ evs,
+                                                     GroupTable gt) {
+  __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
+  const Ctx cx = load_ctx(evs, gt, 1);
+  const Fields& f = cx.f;
+  const StepParams& p = cx.p;
+  const EosDev& eos = cx.eos;
+  const Geo& g = cx.g;
+  const Pos q = cell_pos<TX, TY, TZ>(p, cx.tg, cx.tile);
   double v[kNP];
 #pragma unroll
   for (int s = 0; s < kNP; ++s) v[s] = 0.0;
   const double tf = g.cart ? 1.0 : g.tau;
   double R[14];
-  const double cfl = tile_divergence<TX, TY, TZ, true, false, VISC ? 2 : 0>(f.e1, f.u1, f.pi, p,
+  const double cfl = tile_divergence<RT, TX, TY, TZ, true, false, VISC ? 2 : 0>(f.e1, f.u1, f.pi, p,
                                                                           eos, tf, q, R, lds);
   v[P_CFL] = cfl * p.h;
   if (q.active) {
@@ -694,22 +792,24 @@ __global__ __launch_bounds__(kBlock) void k_stage2_T(Fields f, StepParams p, Eos
     v[P_TSUM] = Tn[0];
     v[P_VAC] = s.e == 0.0 ? 1.0 : 0.0;
   }
-  block_partials(v, f.partial + (size_t)gridDim.x * kNP);
+  block_partials(v, f.partial + (size_t)kNP * cx.tg.ntiles, cx.tg.ntiles, cx.tile);
 }
 
 // Folds the partials of stage1 and stage2T into the accumulated diagnostics.
 // One workgroup per slot; each folds the slot's partials in a fixed order.
 // acc: 0 geo_src, 1 max_cfl, 2 solves, 3 iter_sum, 4 iter_max, 5 fallbacks,
 //      6 nonconv, 7 nans, 8 clamps, 9 eps_max, 10 sum_Ttt, 11 vacuum.
-__global__ __launch_bounds__(kBlock) void k_reduce(Fields f, int nblk, double half_h_vol,
-                                                   double vol) {
+__global__ __launch_bounds__(kBlock) void k_reduce(const EventDesc* __restrict__ evs) {
   __shared__ double sh[2][kBlock / 64];
-  const int s = blockIdx.x;
+  const int e = blockIdx.x / kNP, s = blockIdx.x % kNP;
+  const EventDesc& E = evs[e];
+  const int nblk = E.tg.ntiles;
+  const double* part = E.f.partial;
   const bool mx = is_max_slot(s);
   double x = 0.0, y = 0.0;  // stage1, stage2T
   for (int b = threadIdx.x; b < nblk; b += kBlock) {
-    const double a = f.partial[(size_t)s * nblk + b];
-    const double c = f.partial[(size_t)(kNP + s) * nblk + b];
+    const double a = part[(size_t)s * nblk + b];
+    const double c = part[(size_t)(kNP + s) * nblk + b];
     x = mx ? fmax(x, a) : x + a;
     y = mx ? fmax(y, c) : y + c;
   }
@@ -732,15 +832,31 @@ __global__ __launch_bounds__(kBlock) void k_reduce(Fields f, int nblk, double ha
     x = mx ? fmax(x, sh[0][w]) : x + sh[0][w];
     y = mx ? fmax(y, sh[1][w]) : y + sh[1][w];
   }
-  double* acc = f.acc;
+  const double vol = E.p.dx * E.p.dy * E.p.de;
+  double* acc = E.f.acc;
   switch (s) {
-    case P_GEO: acc[0] += half_h_vol * (x + y); break;
+    case P_GEO: acc[0] += 0.5 * E.p.h * vol * (x + y); break;
     case P_CFL: acc[1] = fmax(acc[1], fmax(x, y)); break;
     case P_EMAX: acc[9] = y; break;
     case P_TSUM: acc[10] = y * vol; break;
     case P_VAC: acc[11] = y; break;
     case P_ITMAX: acc[4] = fmax(acc[4], fmax(x, y)); break;
     default: acc[s] += x + y; break;
+  }
+  if (s == 0) {  // advance the event's clock: tau += h, one more step, swap u~ buffers
+    double* clk = E.clock;
+    clk[0] = clk[0] + E.p.h;
+    clk[1] = clk[1] + 1.0;
+    clk[2] = 1.0 - clk[2];
+  }
+}
+
+// Sets an event's clock at its initial state.
+__global__ void k_set_clock(double* clk, double tau) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    clk[0] = tau;
+    clk[1] = 0.0;
+    clk[2] = 0.0;
   }
 }
 
@@ -801,6 +917,14 @@ struct ktmi_handle {
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
+  // device event table (one entry) and clock, both inside the workspace
+  EventDesc ev{};           // host copy, kept alive for the asynchronous upload
+  EventDesc* dev_ev = nullptr;
+  double* clock = nullptr;
+  bool ev_dirty = true;
+  // graph of one step, replayed by ktmi_step when enabled
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
 };
 
 static std::string g_create_err;
@@ -852,8 +976,8 @@ static bool desc_ok(const ktmi_desc* d, std::string* why) {
     *why = "eps_cut, newton_tol and newton_maxit must be positive";
     return false;
   }
-  if (d->precision != KTMI_FP64) {
-    *why = "only KTMI_FP64 is available";
+  if (d->precision != KTMI_FP64 && d->precision != KTMI_MIXED) {
+    *why = "precision must be KTMI_FP64 or KTMI_MIXED";
     return false;
   }
   if (d->guess != KTMI_GUESS_PREV && d->guess != KTMI_GUESS_COLD) {
@@ -974,13 +1098,21 @@ static Geo geo(const ktmi_handle* h, double tau, double tau1) {
   return g;
 }
 
-// Launches one stencil kernel family member for the handle's tile shape.
-template <template <int, int, int> class K, typename... Args>
-static void launch_tiled(const ktmi_handle* h, Args... args) {
-  const dim3 grid(h->tg.ntiles), block(kBlock);
-  switch (h->tile) {
-#define KTMI_TILE_CASE(id, X, Y, Z) \
-  case id: K<X, Y, Z>::launch(grid, block, h->stream, args...); break;
+// One grouped launch of stencil kernel K over the events of a table that share
+// a tile shape, precision and mode.
+template <template <typename, int, int, int> class K>
+static void launch_class(hipStream_t s, int tile, int precision, const EventDesc* evs,
+                         const GroupTable& gt) {
+  const dim3 grid(gt.start[gt.nev]), block(kBlock);
+  const bool mixed = precision == KTMI_MIXED;
+  switch (tile) {
+#define KTMI_TILE_CASE(id, X, Y, Z)                         \
+  case id:                                                  \
+    if (mixed)                                              \
+      K<float, X, Y, Z>::launch(grid, block, s, evs, gt);   \
+    else                                                    \
+      K<double, X, Y, Z>::launch(grid, block, s, evs, gt);  \
+    break;
     KTMI_TILE_CASE(0, 4, 4, 16)
     KTMI_TILE_CASE(1, 2, 8, 16)
     KTMI_TILE_CASE(2, 4, 8, 8)
@@ -992,55 +1124,90 @@ static void launch_tiled(const ktmi_handle* h, Args... args) {
   }
 }
 
-template <int X, int Y, int Z>
-struct LFirst {
-  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
-                     TileGrid tg) {
-    hipLaunchKernelGGL((k_first_estimate<X, Y, Z>), g, b, 0, s, f, p, e, geo, tg);
+#define KTMI_LAUNCHER(NAME, KERNEL)                                                       \
+  template <typename RT, int X, int Y, int Z>                                             \
+  struct NAME {                                                                           \
+    static void launch(dim3 g, dim3 b, hipStream_t s, const EventDesc* evs, GroupTable gt) { \
+      hipLaunchKernelGGL((KERNEL), g, b, 0, s, evs, gt);                                  \
+    }                                                                                     \
+  };
+KTMI_LAUNCHER(LFirst, (k_first_estimate<RT, X, Y, Z>))
+KTMI_LAUNCHER(LStage1V, (k_stage1<RT, X, Y, Z, true>))
+KTMI_LAUNCHER(LStage1I, (k_stage1<RT, X, Y, Z, false>))
+KTMI_LAUNCHER(LStage2Pi, (k_stage2_pi<RT, X, Y, Z>))
+KTMI_LAUNCHER(LStage2TV, (k_stage2_T<RT, X, Y, Z, true>))
+KTMI_LAUNCHER(LStage2TI, (k_stage2_T<RT, X, Y, Z, false>))
+#undef KTMI_LAUNCHER
+
+static GroupTable single_table(const ktmi_handle* h) {
+  GroupTable gt;
+  memset(&gt, 0, sizeof(gt));
+  gt.nev = 1;
+  gt.start[0] = 0;
+  gt.start[1] = h->tg.ntiles;
+  return gt;
+}
+
+static EventDesc make_event(const ktmi_handle* h) {
+  EventDesc ev;
+  memset(&ev, 0, sizeof(ev));
+  ev.f = h->f;
+  ev.p = step_params(h);
+  ev.eos = h->eos;
+  ev.tg = h->tg;
+  ev.cart = h->d.cartesian;
+  ev.viscous = h->d.viscous;
+  ev.clock = h->clock;
+  return ev;
+}
+
+// Uploads the handle's event table when its parameters changed.
+static int upload_event(ktmi_handle* h) {
+  if (!h->ev_dirty) return KTMI_OK;
+  h->ev = make_event(h);
+  HIP_TRY(h, hipMemcpyAsync(h->dev_ev, &h->ev, sizeof(EventDesc), hipMemcpyHostToDevice,
+                            h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));  // h->ev may change before a later upload
+  h->ev_dirty = false;
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
   }
-};
-template <int X, int Y, int Z>
-struct LStage1V {
-  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
-                     TileGrid tg) {
-    hipLaunchKernelGGL((k_stage1<X, Y, Z, true>), g, b, 0, s, f, p, e, geo, tg);
+  return KTMI_OK;
+}
+
+// The kernels of one step for the events of one class (same tile, precision, mode).
+static int enqueue_class_step(ktmi_handle* h, hipStream_t s, int tile, int precision, int viscous,
+                              const EventDesc* evs, const GroupTable& gt) {
+  int rc;
+  if (viscous) {
+    rc = launch(h, K_STAGE1, [&] { launch_class<LStage1V>(s, tile, precision, evs, gt); });
+    if (rc) return rc;
+    rc = launch(h, K_STAGE2PI, [&] { launch_class<LStage2Pi>(s, tile, precision, evs, gt); });
+    if (rc) return rc;
+    return launch(h, K_STAGE2T, [&] { launch_class<LStage2TV>(s, tile, precision, evs, gt); });
   }
-};
-template <int X, int Y, int Z>
-struct LStage1I {
-  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
-                     TileGrid tg) {
-    hipLaunchKernelGGL((k_stage1<X, Y, Z, false>), g, b, 0, s, f, p, e, geo, tg);
-  }
-};
-template <int X, int Y, int Z>
-struct LStage2Pi {
-  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
-                     TileGrid tg) {
-    hipLaunchKernelGGL((k_stage2_pi<X, Y, Z>), g, b, 0, s, f, p, e, geo, tg);
-  }
-};
-template <int X, int Y, int Z>
-struct LStage2TV {
-  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
-                     TileGrid tg) {
-    hipLaunchKernelGGL((k_stage2_T<X, Y, Z, true>), g, b, 0, s, f, p, e, geo, tg);
-  }
-};
-template <int X, int Y, int Z>
-struct LStage2TI {
-  static void launch(dim3 g, dim3 b, hipStream_t s, Fields f, StepParams p, EosDev e, Geo geo,
-                     TileGrid tg) {
-    hipLaunchKernelGGL((k_stage2_T<X, Y, Z, false>), g, b, 0, s, f, p, e, geo, tg);
-  }
-};
+  rc = launch(h, K_STAGE1, [&] { launch_class<LStage1I>(s, tile, precision, evs, gt); });
+  if (rc) return rc;
+  return launch(h, K_STAGE2T, [&] { launch_class<LStage2TI>(s, tile, precision, evs, gt); });
+}
+
+static int enqueue_step(ktmi_handle* h) {
+  const GroupTable gt = single_table(h);
+  int rc = enqueue_class_step(h, h->stream, h->tile, h->d.precision, h->d.viscous, h->dev_ev, gt);
+  if (rc) return rc;
+  return launch(h, K_REDUCE, [&] {
+    hipLaunchKernelGGL(k_reduce, dim3(kNP), dim3(kBlock), 0, h->stream, h->dev_ev);
+  });
+}
 
 static int finish_initial(ktmi_handle* h) {
-  const StepParams p = step_params(h);
-  const int nb = h->nblk;
-  const Geo g = geo(h, h->tau, h->tau + h->d.h);
-  (void)nb;
-  int rc = launch(h, K_FIRST, [&] { launch_tiled<LFirst>(h, h->f, p, h->eos, g, h->tg); });
+  if (int rc = upload_event(h)) return rc;
+  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, h->stream, h->clock, h->tau);
+  const GroupTable gt = single_table(h);
+  int rc = launch(h, K_FIRST, [&] {
+    launch_class<LFirst>(h->stream, h->tile, h->d.precision, h->dev_ev, gt);
+  });
   if (rc) return rc;
   rc = launch(h, K_INIT, [&] {
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, h->stream, h->f.acc, 32);
@@ -1051,12 +1218,57 @@ static int finish_initial(ktmi_handle* h) {
   return KTMI_OK;
 }
 
+// u~ buffers of the current state (the kernels swap roles every step).
+static double* const* cur_u(const ktmi_handle* h) { return (h->step & 1) ? h->f.up : h->f.u; }
+static double* const* prev_u(const ktmi_handle* h) { return (h->step & 1) ? h->f.u : h->f.up; }
+
 static int check_setup(ktmi_handle* h) {
   if (!h->bound) return fail(h, KTMI_ESTATE, "no workspace bound");
   if (!h->eos_set) return fail(h, KTMI_ESTATE, "EoS table must be set after binding");
   return KTMI_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Groups: many events stepped together.  Events are sorted into classes of
+// equal (mode, precision, tile shape); per class and stage one launch covers
+// the tiles of all its events (the kernels find their event from the tile
+// index), then one reduce launch serves every event.
+// ---------------------------------------------------------------------------
+struct ktmi_group {
+  std::vector<ktmi_handle*> hs;  // in class order
+  hipStream_t stream = nullptr;
+  struct Class {
+    int tile, precision, viscous;
+    int first;  // index of the class's first event in the device table
+    GroupTable gt;
+  };
+  std::vector<Class> classes;
+  EventDesc* dev = nullptr;           // nev entries in class order
+  std::vector<EventDesc> host;        // kept alive for the asynchronous upload
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  std::string err;
+  ktmi_handle timing_stub;  // carries the stream and error text for launch()
+};
+
+static int group_fail(ktmi_group* g, int code, const std::string& msg) {
+  g->err = msg;
+  return code;
+}
+
+static int enqueue_group_step(ktmi_group* g) {
+  ktmi_handle* h = &g->timing_stub;
+  for (const auto& c : g->classes) {
+    int rc = enqueue_class_step(h, g->stream, c.tile, c.precision, c.viscous, g->dev + c.first, c.gt);
+    if (rc) return group_fail(g, rc, h->err);
+  }
+  const int nev = (int)g->hs.size();
+  hipLaunchKernelGGL(k_reduce, dim3(kNP * nev), dim3(kBlock), 0, g->stream, g->dev);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return group_fail(g, KTMI_EHIP, hipGetErrorString(e));
+  return KTMI_OK;
+}
 
 extern "C" {
 
@@ -1081,6 +1293,8 @@ size_t ktmi_workspace_bytes(const ktmi_desc* d) {
   bytes += ((2 * nb * kNP + 31) / 32 * 32) * sizeof(double);  // partials
   bytes += 32 * sizeof(double);                               // accumulators
   bytes += 3 * (size_t)kEosMaxRows * sizeof(double);          // EoS table
+  bytes += 3 * (size_t)kEosMaxRows * sizeof(float);           // its FP32 copy
+  bytes += 4096 + 512;                                         // event table, clock
   return bytes;
 }
 
@@ -1099,6 +1313,7 @@ int ktmi_create(const ktmi_desc* d, ktmi_handle** out) {
   h->eos.kind = 0;
   h->eos.c_sb = 47.5 * M_PI * M_PI / 30.0 / (kHbarc * kHbarc * kHbarc);
   h->eos.inv_csb = 1.0 / h->eos.c_sb;
+  h->eos.inv_csb_f = (float)h->eos.inv_csb;
   h->eos_set = true;  // ideal gas until a table is set
   *out = h;
   return KTMI_OK;
@@ -1135,6 +1350,13 @@ int ktmi_bind(ktmi_handle* h, void* ws, size_t bytes, void* stream) {
   f.acc = rest;
   rest += 32;
   h->eos_store = rest;
+  rest += 3 * (size_t)kEosMaxRows;                       // FP64 table
+  rest += (3 * (size_t)kEosMaxRows * sizeof(float) + 7) / 8;  // FP32 copy
+  rest = (double*)(((uintptr_t)rest + 255) / 256 * 256);
+  h->dev_ev = (EventDesc*)rest;
+  h->clock = rest + 4096 / 8;
+  static_assert(sizeof(EventDesc) <= 4096, "event table slot");
+  h->ev_dirty = true;
   h->bound = true;
   return KTMI_OK;
 }
@@ -1145,8 +1367,10 @@ int ktmi_set_eos_conformal(ktmi_handle* h, double c_sb) {
   h->eos.kind = 0;
   h->eos.c_sb = c_sb;
   h->eos.inv_csb = 1.0 / c_sb;
+  h->eos.inv_csb_f = (float)(1.0 / c_sb);
   h->cs2_vac = 1.0 / 3.0;
   h->eos_set = true;
+  h->ev_dirty = true;
   return KTMI_OK;
 }
 
@@ -1163,17 +1387,38 @@ int ktmi_set_eos_table(ktmi_handle* h, double e0, double de, int n, const double
   HIP_TRY(h, hipMemcpyAsync(dP, P, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(h, hipMemcpyAsync(dT, T, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(h, hipMemcpyAsync(dC, cs2, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+  // FP32 copy for the mixed-precision path (rounded on the host)
+  float* fP = (float*)(dC + kEosMaxRows);
+  float* fT = fP + kEosMaxRows;
+  float* fC = fT + kEosMaxRows;
+  std::vector<float> tmp((size_t)3 * n);
+  for (int i = 0; i < n; ++i) {
+    tmp[i] = (float)P[i];
+    tmp[(size_t)n + i] = (float)T[i];
+    tmp[(size_t)2 * n + i] = (float)cs2[i];
+  }
+  HIP_TRY(h, hipMemcpyAsync(fP, tmp.data(), sizeof(float) * n, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(fT, tmp.data() + n, sizeof(float) * n, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(fC, tmp.data() + 2 * n, sizeof(float) * n, hipMemcpyHostToDevice,
+                            h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->eos.Pf = fP;
+  h->eos.Tf = fT;
+  h->eos.cs2f = fC;
+  h->eos.e0_f = (float)e0;
+  h->eos.de_f = (float)de;
+  h->eos.inv_de_f = (float)(1.0 / de);
   h->eos.kind = 1;
   h->eos.n = n;
   h->eos.e0 = e0;
   h->eos.de = de;
   h->eos.inv_de = 1.0 / de;
-  h->cs2_vac = (e0 >= 0.0) ? cs2[0] : cs2[0];  // lookups clamp e = 0 to the first row
+  h->cs2_vac = cs2[0];  // lookups clamp e = 0 to the first row
   h->eos.P = dP;
   h->eos.T = dT;
   h->eos.cs2 = dC;
   h->eos_set = true;
+  h->ev_dirty = true;
   return KTMI_OK;
 }
 
@@ -1234,35 +1479,45 @@ int ktmi_step(ktmi_handle* h, int nsteps) {
   if (!h) return KTMI_EINVAL;
   if (!h->ready) return fail(h, KTMI_ESTATE, "set an initial state first");
   if (nsteps < 0) return fail(h, KTMI_EINVAL, "negative step count");
-  const StepParams p = step_params(h);
-  hipStream_t s = h->stream;
-  const double vol = h->d.dx * h->d.dy * h->d.de;
-  for (int it = 0; it < nsteps; ++it) {
-    const double t0 = h->tau, t1 = h->tau + h->d.h;
-    const Geo g0 = geo(h, t0, t1), g1 = geo(h, t1, t1);
-    const TileGrid tg = h->tg;
-    int rc;
-    if (h->d.viscous) {
-      rc = launch(h, K_STAGE1, [&] { launch_tiled<LStage1V>(h, h->f, p, h->eos, g0, tg); });
-      if (rc) return rc;
-      rc = launch(h, K_STAGE2PI, [&] { launch_tiled<LStage2Pi>(h, h->f, p, h->eos, g1, tg); });
-      if (rc) return rc;
-      rc = launch(h, K_STAGE2T, [&] { launch_tiled<LStage2TV>(h, h->f, p, h->eos, g1, tg); });
-    } else {
-      rc = launch(h, K_STAGE1, [&] { launch_tiled<LStage1I>(h, h->f, p, h->eos, g0, tg); });
-      if (rc) return rc;
-      rc = launch(h, K_STAGE2T, [&] { launch_tiled<LStage2TI>(h, h->f, p, h->eos, g1, tg); });
+  if (int rc = upload_event(h)) return rc;
+  const bool graph = h->use_graph && !h->timing;
+  if (graph && !h->gexec) {  // capture one step; every step issues the same launches
+    hipGraph_t g = nullptr;
+    HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_step(h);
+    const hipError_t ec = hipStreamEndCapture(h->stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
     }
-    if (rc) return rc;
-    const int nt = tg.ntiles;
-    rc = launch(h, K_REDUCE, [&] {
-      hipLaunchKernelGGL(k_reduce, dim3(kNP), dim3(kBlock), 0, s, h->f, nt, 0.5 * h->d.h * vol,
-                         vol);
-    });
-    if (rc) return rc;
-    for (int m = 0; m < 3; ++m) std::swap(h->f.u[m], h->f.up[m]);
-    h->tau = t1;
+    if (ec != hipSuccess) return hip_fail(h, ec, "hipStreamEndCapture");
+    const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      h->gexec = nullptr;
+      return hip_fail(h, ei, "hipGraphInstantiate");
+    }
+  }
+  for (int it = 0; it < nsteps; ++it) {
+    if (graph) {
+      HIP_TRY(h, hipGraphLaunch(h->gexec, h->stream));
+    } else if (int rc = enqueue_step(h)) {
+      return rc;
+    }
+    h->tau += h->d.h;
     h->step++;
+  }
+  return KTMI_OK;
+}
+
+int ktmi_set_graph(ktmi_handle* h, int on) {
+  if (!h) return KTMI_EINVAL;
+  if (on && !h->stream)
+    return fail(h, KTMI_EINVAL, "graph replay needs a non-default stream (bind one)");
+  h->use_graph = on != 0;
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
   }
   return KTMI_OK;
 }
@@ -1278,7 +1533,7 @@ int ktmi_read(ktmi_handle* h, int field, double* dst) {
   if (field == KTMI_F_EPS)
     src = h->f.e;
   else if (field >= KTMI_F_UX && field < KTMI_F_UX + 3)
-    src = h->f.u[field - KTMI_F_UX];
+    src = cur_u(h)[field - KTMI_F_UX];
   else if (field >= KTMI_F_PI && field < KTMI_F_PI + 10) {
     hipLaunchKernelGGL(k_read_pi, dim3(h->nblk), dim3(kBlock), 0, s, h->f.e,
                        h->f.pi[field - KTMI_F_PI], dst, n);
@@ -1287,7 +1542,7 @@ int ktmi_read(ktmi_handle* h, int field, double* dst) {
   } else if (field >= KTMI_F_T && field < KTMI_F_T + 4)
     src = h->f.T[field - KTMI_F_T];
   else if (field >= KTMI_F_UPREV && field < KTMI_F_UPREV + 3)
-    src = h->f.up[field - KTMI_F_UPREV];
+    src = prev_u(h)[field - KTMI_F_UPREV];
   else
     return fail(h, KTMI_EINVAL, "unknown field id");
   HIP_TRY(h, hipMemcpyAsync(dst, src, nb, hipMemcpyDeviceToDevice, s));
@@ -1367,7 +1622,141 @@ int ktmi_set_tile(ktmi_handle* h, int t) {
   if (t < -1 || t >= kNumTiles) return fail(h, KTMI_EINVAL, "tile index out of range");
   h->tile = t < 0 ? auto_tile(&h->d) : t;
   h->tg = tile_grid(&h->d, h->tile);
+  h->ev_dirty = true;
   return KTMI_OK;
+}
+
+size_t ktmi_group_workspace_bytes(int nev) {
+  if (nev < 1) return 0;
+  return (size_t)nev * sizeof(EventDesc) + 256;
+}
+
+int ktmi_group_create(ktmi_handle* const* hs, int nev, void* ws, size_t bytes, ktmi_group** out) {
+  if (!out) return fail(nullptr, KTMI_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!hs || nev < 1) return fail(nullptr, KTMI_EINVAL, "need at least one handle");
+  if (!ws || bytes < ktmi_group_workspace_bytes(nev) || ((uintptr_t)ws) % 256)
+    return fail(nullptr, KTMI_EINVAL, "group workspace too small or not 256-byte aligned");
+  for (int i = 0; i < nev; ++i) {
+    if (!hs[i] || !hs[i]->ready)
+      return fail(nullptr, KTMI_ESTATE, "every handle needs an initial state before grouping");
+    if (hs[i]->stream != hs[0]->stream)
+      return fail(nullptr, KTMI_EINVAL, "all handles of a group must share one stream");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(nullptr, KTMI_EINVAL, "a handle appears twice");
+  }
+  ktmi_group* g = new ktmi_group();
+  g->stream = hs[0]->stream;
+  g->timing_stub.stream = g->stream;
+  g->dev = (EventDesc*)ws;
+  // classes in first-seen order; events keep their order inside a class
+  std::vector<int> order;
+  std::vector<std::vector<int>> members;
+  for (int i = 0; i < nev; ++i) {
+    const ktmi_handle* h = hs[i];
+    int c = -1;
+    for (size_t k = 0; k < g->classes.size(); ++k)
+      if (g->classes[k].tile == h->tile && g->classes[k].precision == h->d.precision &&
+          g->classes[k].viscous == h->d.viscous)
+        c = (int)k;
+    if (c < 0) {
+      ktmi_group::Class cl{};
+      cl.tile = h->tile;
+      cl.precision = h->d.precision;
+      cl.viscous = h->d.viscous;
+      g->classes.push_back(cl);
+      members.emplace_back();
+      c = (int)g->classes.size() - 1;
+    }
+    members[c].push_back(i);
+  }
+  int pos = 0;
+  for (size_t k = 0; k < g->classes.size(); ++k) {
+    auto& cl = g->classes[k];
+    if ((int)members[k].size() > kMaxGroup) {
+      delete g;
+      return fail(nullptr, KTMI_EINVAL, "too many events of one class (max 128)");
+    }
+    cl.first = pos;
+    memset(&cl.gt, 0, sizeof(cl.gt));
+    cl.gt.nev = (int)members[k].size();
+    int t = 0;
+    for (int m = 0; m < cl.gt.nev; ++m) {
+      ktmi_handle* h = hs[members[k][m]];
+      cl.gt.start[m] = t;
+      t += h->tg.ntiles;
+      g->hs.push_back(h);
+      g->host.push_back(make_event(h));
+      pos++;
+    }
+    cl.gt.start[cl.gt.nev] = t;
+  }
+  const hipError_t e = hipMemcpyAsync(g->dev, g->host.data(), sizeof(EventDesc) * nev,
+                                      hipMemcpyHostToDevice, g->stream);
+  const hipError_t e2 = e == hipSuccess ? hipStreamSynchronize(g->stream) : e;
+  if (e2 != hipSuccess) {
+    delete g;
+    return fail(nullptr, KTMI_EHIP, std::string("group table upload: ") + hipGetErrorString(e2));
+  }
+  *out = g;
+  return KTMI_OK;
+}
+
+int ktmi_group_step(ktmi_group* g, int nsteps) {
+  if (!g) return KTMI_EINVAL;
+  if (nsteps < 0) return group_fail(g, KTMI_EINVAL, "negative step count");
+  if (g->use_graph && !g->gexec) {
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return group_fail(g, KTMI_EHIP, hipGetErrorString(e));
+    const int rc = enqueue_group_step(g);
+    e = hipStreamEndCapture(g->stream, &gr);
+    if (rc) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    if (e != hipSuccess) return group_fail(g, KTMI_EHIP, hipGetErrorString(e));
+    e = hipGraphInstantiate(&g->gexec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+      g->gexec = nullptr;
+      return group_fail(g, KTMI_EHIP, hipGetErrorString(e));
+    }
+  }
+  for (int it = 0; it < nsteps; ++it) {
+    if (g->use_graph) {
+      const hipError_t e = hipGraphLaunch(g->gexec, g->stream);
+      if (e != hipSuccess) return group_fail(g, KTMI_EHIP, hipGetErrorString(e));
+    } else if (int rc = enqueue_group_step(g)) {
+      return rc;
+    }
+    for (ktmi_handle* h : g->hs) {
+      h->tau += h->d.h;
+      h->step++;
+    }
+  }
+  return KTMI_OK;
+}
+
+int ktmi_group_set_graph(ktmi_group* g, int on) {
+  if (!g) return KTMI_EINVAL;
+  if (on && !g->stream) return group_fail(g, KTMI_EINVAL, "graph replay needs a non-default stream");
+  g->use_graph = on != 0;
+  if (g->gexec) {
+    (void)hipGraphExecDestroy(g->gexec);
+    g->gexec = nullptr;
+  }
+  return KTMI_OK;
+}
+
+int ktmi_group_class_count(const ktmi_group* g) { return g ? (int)g->classes.size() : KTMI_EINVAL; }
+
+const char* ktmi_group_last_error(const ktmi_group* g) { return g ? g->err.c_str() : ""; }
+
+void ktmi_group_destroy(ktmi_group* g) {
+  if (!g) return;
+  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+  delete g;
 }
 
 const char* ktmi_last_error(const ktmi_handle* h) {
@@ -1381,6 +1770,7 @@ void ktmi_destroy(ktmi_handle* h) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : h->pool) (void)hipEventDestroy(e);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   delete h;
 }
 

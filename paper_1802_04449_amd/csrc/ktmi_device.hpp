@@ -30,6 +30,11 @@ struct EosDev {
   const double* P;
   const double* T;
   const double* cs2;
+  // FP32 copy of the table for the mixed-precision flux and relaxation arithmetic
+  float inv_csb_f, e0_f, de_f, inv_de_f;
+  const float* Pf;
+  const float* Tf;
+  const float* cs2f;
 };
 
 // Root-solve outcome flags (counted in the diagnostics).
@@ -258,6 +263,101 @@ __device__ __forceinline__ double local_speed(double ut, double ux, double uy, d
   const double inv_den = 1.0 / (1.0 - v2 * cs2);
   const double a = vd * (1.0 - cs2);
   return (fabs(a) + root) * inv_den;  // = max(|a + root|, |a - root|) / den, root >= 0
+}
+
+// ---------------------------------------------------------------------------
+// Precision-generic versions for the flux and relaxation arithmetic: R = double
+// (FP64 path) or float (mixed path; table values from the FP32 copy).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void eos_p_cs2_r(const EosDev& q, R e, R& P, R& cs2);
+
+template <>
+__device__ __forceinline__ void eos_p_cs2_r<double>(const EosDev& q, double e, double& P,
+                                                     double& cs2) {
+  eos_p_cs2(q, e, P, cs2);
+}
+
+template <>
+__device__ __forceinline__ void eos_p_cs2_r<float>(const EosDev& q, float e, float& P, float& cs2) {
+  e = e > 0.0f ? e : 0.0f;
+  if (q.kind == 0) {
+    P = e * (1.0f / 3.0f);
+    cs2 = 1.0f / 3.0f;
+    return;
+  }
+  const int n = q.n;
+  float x = (e - q.e0_f) * q.inv_de_f;
+  x = x >= 0.0f ? x : 0.0f;
+  if (x >= (float)(n - 1)) {
+    const float slope = (q.Pf[n - 1] - q.Pf[n - 2]) * q.inv_de_f;
+    P = q.Pf[n - 1] + (e - (q.e0_f + (float)(n - 1) * q.de_f)) * slope;
+    cs2 = q.cs2f[n - 1];
+    return;
+  }
+  int i = (int)floorf(x);
+  i = i > n - 2 ? n - 2 : (i < 0 ? 0 : i);
+  const float f = x - (float)i;
+  P = q.Pf[i] + f * (q.Pf[i + 1] - q.Pf[i]);
+  cs2 = q.cs2f[i] + f * (q.cs2f[i + 1] - q.cs2f[i]);
+}
+
+template <typename R>
+__device__ __forceinline__ void eos_p_t_r(const EosDev& q, R e, R& P, R& T);
+
+template <>
+__device__ __forceinline__ void eos_p_t_r<double>(const EosDev& q, double e, double& P, double& T) {
+  eos_p_t(q, e, P, T);
+}
+
+template <>
+__device__ __forceinline__ void eos_p_t_r<float>(const EosDev& q, float e, float& P, float& T) {
+  e = e > 0.0f ? e : 0.0f;
+  if (q.kind == 0) {
+    P = e * (1.0f / 3.0f);
+    T = sqrtf(sqrtf(e * q.inv_csb_f));
+    return;
+  }
+  const int n = q.n;
+  float x = (e - q.e0_f) * q.inv_de_f;
+  x = x >= 0.0f ? x : 0.0f;
+  if (x >= (float)(n - 1)) {
+    const float slope = (q.Pf[n - 1] - q.Pf[n - 2]) * q.inv_de_f;
+    const float elast = q.e0_f + (float)(n - 1) * q.de_f;
+    P = q.Pf[n - 1] + (e - elast) * slope;
+    T = q.Tf[n - 1] * sqrtf(sqrtf((e + P) / (elast + q.Pf[n - 1])));
+    return;
+  }
+  int i = (int)floorf(x);
+  i = i > n - 2 ? n - 2 : (i < 0 ? 0 : i);
+  const float f = x - (float)i;
+  P = q.Pf[i] + f * (q.Pf[i + 1] - q.Pf[i]);
+  T = q.Tf[i] + f * (q.Tf[i + 1] - q.Tf[i]);
+}
+
+template <typename R>
+__device__ __forceinline__ R minmod3_r(R a, R b, R c) {
+  if (a > R(0) && b > R(0) && c > R(0)) return fmin(a, fmin(b, c));
+  if (a < R(0) && b < R(0) && c < R(0)) return fmax(a, fmax(b, c));
+  return R(0);
+}
+
+template <typename R>
+__device__ __forceinline__ R mm_slope_r(R th, R qm, R q0, R qp) {
+  return minmod3_r<R>(th * (q0 - qm), R(0.5) * (qp - qm), th * (qp - q0));
+}
+
+template <typename R>
+__device__ __forceinline__ R local_speed_r(R ut, R ux, R uy, R ue, R ud, R cs2) {
+  const R inv = R(1) / ut;
+  const R vd = ud * inv;
+  const R v2 = (ux * ux + uy * uy + ue * ue) * inv * inv;
+  R disc = inv * inv * (R(1) - v2 * cs2 - vd * vd * (R(1) - cs2));
+  disc = disc < R(0) ? R(0) : disc;
+  const R root = sqrt(cs2 * disc);
+  const R inv_den = R(1) / (R(1) - v2 * cs2);
+  const R a = vd * (R(1) - cs2);
+  return (fabs(a) + root) * inv_den;
 }
 
 // pi~ component index of the symmetric pair (mu, nu).

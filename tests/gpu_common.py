@@ -102,3 +102,31 @@ def dense_compare(gpu_fields, ref_fields, eps_min):
     sub_g = {k: v[m] for k, v in gpu_fields.items()}
     sub_r = {k: v[m] for k, v in ref_fields.items()}
     return compare(sub_g, sub_r)
+
+
+def precision_errors(gpu_fields, ref_fields, eps_min=0.1):
+    """Per-field errors of a reduced-precision run against an FP64 reference.
+    'max' = max|d| / scale over all cells, 'max_hydro' the same over cells with
+    e >= eps_min (0.1 GeV/fm^3, the typical freeze-out energy density below which
+    hydrodynamics is no longer applied), 'l2' = ||d||_2 / ||scale field||_2.  The
+    scale is shared by a tensor's components, as in compare(): max|ref| over the
+    group (max u~^tau for velocities) for 'max', and the L2 norm of the whole
+    tensor (of u~^tau for velocities) for 'l2'."""
+    out = {}
+    ux, uy, ue = ref_fields["ux"], ref_fields["uy"], ref_fields["ue"]
+    ut = np.sqrt(1 + ux ** 2 + uy ** 2 + ue ** 2)
+    m = ref_fields["eps"] >= eps_min
+    for gname, names in GROUPS.items():
+        if gname in ("u", "uprev"):
+            scale, l2s = float(ut.max()), float(np.sqrt((ut ** 2).sum()))
+        else:
+            scale = max(float(np.abs(ref_fields[n]).max()) for n in names)
+            l2s = float(np.sqrt(sum((ref_fields[n] ** 2).sum() for n in names)))
+        scale = scale if scale > 0 else 1.0
+        l2s = l2s if l2s > 0 else 1.0
+        for n in names:
+            d = np.abs(gpu_fields[n] - ref_fields[n])
+            out[n] = {"max": float(d.max()) / scale,
+                      "max_hydro": float(d[m].max()) / scale if m.any() else 0.0,
+                      "l2": float(np.sqrt((d ** 2).sum())) / l2s}
+    return out

@@ -27,7 +27,8 @@ def test_exports_every_declared_symbol():
 def test_binding_names_match_abi():
     import paper_1802_04449_amd as K
     for n in _declared():
-        if n in ("ktmi_kernel_count", "ktmi_kernel_name", "ktmi_last_error"):
+        if n in ("ktmi_kernel_count", "ktmi_kernel_name", "ktmi_last_error",
+                 "ktmi_group_last_error"):
             continue
         assert hasattr(K, n), f"binding lacks {n}"
 
@@ -99,3 +100,9 @@ def test_tile_shapes_cover_256_threads():
             K.ktmi_set_tile(h, n)
     finally:
         K.ktmi_destroy(h)
+
+
+def test_group_workspace_size():
+    import paper_1802_04449_amd as K
+    assert K.ktmi_group_workspace_bytes(0) == 0
+    assert K.ktmi_group_workspace_bytes(64) > 64 * 400

@@ -1,0 +1,65 @@
+"""Mixed precision (FP32 reconstruction, fluxes, local speed and shear relaxation
+source; FP64 root solve, geometric source and state) against the FP64 oracle.
+
+Bar for well-conditioned states: relative error <= 1e-6 in e and in the
+velocity components, in the L2 norm over the grid and in the max norm over the
+cells where hydrodynamics applies (e >= 0.1 GeV/fm^3).  The mini-jet state is
+ill-conditioned in dilute near-light-speed cells (see test_gpu_parity.py); its
+bar is 1e-6 in e and u~ over cells with e >= 1 GeV/fm^3, and elsewhere 10x the
+oracle's own response to a relative input perturbation of FP32's unit roundoff.
+Every field's error is printed.
+"""
+import json
+import sys
+
+import pytest
+
+from hydro_inputs import workloads as W
+
+from . import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+BAR = 1e-6
+GATED = ("eps", "ux", "uy", "ue")
+
+
+def _run(wl, steps):
+    import paper_1802_04449_amd as K
+    print(f"[gpu-case] mixed {wl.name} steps={steps}", flush=True)
+    gf = G.run_gpu(wl, steps, precision=K.KTMI_MIXED).fields()
+    of = G.run_oracle(wl, steps).fields()
+    err = G.precision_errors(gf, of)
+    print(json.dumps({k: {m: f"{v:.2e}" for m, v in e.items()} for k, e in err.items()}), flush=True)
+    sys.stdout.flush()
+    return gf, of, err
+
+
+def _check(wl, steps):
+    _, _, err = _run(wl, steps)
+    for k in GATED:
+        assert err[k]["l2"] <= BAR and err[k]["max_hydro"] <= BAR, (k, err[k])
+
+
+def test_mixed_gubser_ideal_33():
+    _check(W.gubser_ideal_33(), 50)
+
+
+def test_mixed_viscous_hotspots():
+    _check(W.hotspots_viscous(nx=45, ny=39, ne=13, dx=0.35, dy=0.35, de=0.4, steps=20, seed=5), 20)
+
+
+def test_mixed_viscous_fine_grid():
+    _check(W.hotspots_viscous(nx=65, ny=65, ne=17, dx=0.16, dy=0.16, de=0.3, steps=60, seed=5), 60)
+
+
+def test_mixed_minijets_conditioning_aware():
+    wl = W.hotspots_minijets(nx=41, ny=41, ne=9, dx=0.35, dy=0.35, de=0.45, steps=10, seed=4)
+    gf, of, err = _run(wl, 10)
+    dense = G.precision_errors(gf, of, eps_min=1.0)
+    for k in GATED:
+        assert dense[k]["max_hydro"] <= BAR, (k, dense[k])
+    ref, sens = G.conditioning(wl, 10, rel=2.0 ** -24)
+    rel = G.compare(gf, ref)
+    print(json.dumps({k: [f"{rel[k]:.1e}", f"{sens[k]:.1e}"] for k in rel}), flush=True)
+    for k in GATED:
+        assert rel[k] <= max(BAR, 10.0 * sens[k]), (k, rel[k], sens[k])
