@@ -46,7 +46,11 @@ enum {
 };
 
 enum { KTMI_FP64 = 0, KTMI_MIXED = 1 };                               /* precision */
-enum { KTMI_GUESS_PREV = 0, KTMI_GUESS_COLD = 1 };                    /* root-solve start */
+/* Start of the per-cell root solve: the cell's e from the previous stage, E
+ * itself (cold), or the learned guess (ktmi_set_mlp).  The result does not
+ * depend on the start beyond the solve tolerance (a polish step follows). */
+enum { KTMI_GUESS_PREV = 0, KTMI_GUESS_COLD = 1, KTMI_GUESS_MLP = 2 };
+enum { KTMI_MLP_FP32 = 0, KTMI_MLP_BF16 = 1 }; /* forward of the learned guess */
 
 /* Field ids for ktmi_read. */
 enum {
@@ -178,8 +182,8 @@ int ktmi_set_graph(ktmi_handle *h, int on);
  * workspaces and states; the group only needs a device table of
  * ktmi_group_workspace_bytes(nev) bytes (256-byte aligned, caller-owned).  All
  * handles must share one stream and have an initial state; rebuild the group
- * after changing a handle's tile or EoS.  ktmi_read / ktmi_diag on a member
- * handle see the grouped steps. */
+ * after changing a handle's tile, EoS, guess mode or network.  ktmi_read /
+ * ktmi_diag on a member handle see the grouped steps. */
 typedef struct ktmi_group ktmi_group;
 size_t ktmi_group_workspace_bytes(int nev);
 int ktmi_group_create(ktmi_handle *const *hs, int nev, void *dev_ws, size_t bytes,
@@ -189,6 +193,50 @@ int ktmi_group_set_graph(ktmi_group *g, int on);
 int ktmi_group_class_count(const ktmi_group *g);
 const char *ktmi_group_last_error(const ktmi_group *g);
 void ktmi_group_destroy(ktmi_group *g);
+
+/* Learned root-solve guess (not part of the paper's method; the paper notes
+ * only that the root solve needs a varying number of iterations, App. A.3).
+ * Network 4 -> 32 -> 32 -> 1 with tanh hidden layers on the features
+ * f = (ln E / 5, M/E, (M/E)^2, ln(max(lo/E, 1e-30)) / 10) of K = (E, K^i),
+ * M = |K^i|, lo = max(0, E - M^2/E); guess = lo + sigmoid(z) (E - lo), inside
+ * the root bracket [lo, E].  Parameters: ktmi_mlp_nparam() FP32 values,
+ * W1[32][4], b1[32], W2[32][32], b2[32], w3[32], b3 (device arrays).
+ * KTMI_MLP_FP32 evaluates per thread in FP32; KTMI_MLP_BF16 runs the 32 x 32
+ * layer on the BF16 matrix cores (FP32 accumulation) for 64 cells at a time. */
+int ktmi_mlp_nparam(void);
+
+/* Copies the parameters (device) into h's workspace and selects the forward
+ * mode; later steps with guess KTMI_GUESS_MLP use them.  Stream-ordered. */
+int ktmi_set_mlp(ktmi_handle *h, const float *params, int mode);
+
+/* Changes the guess mode of h (KTMI_GUESS_*; MLP needs ktmi_set_mlp first).
+ * Groups that hold h must be rebuilt. */
+int ktmi_set_guess(ktmi_handle *h, int guess);
+
+/* Training samples from h's current state, one per cell (device arrays of
+ * nx*ny*ne): E = K^tau, M = |K^i| with K = T~^{tau .}/tau - pi~^{tau .}, and
+ * eps = the cell's e (the root of that K; 0 in vacuum).  Async. */
+int ktmi_harvest(ktmi_handle *h, double *E, double *M, double *eps);
+
+/* guess[i] for n samples (device arrays E, M); samples with E < emin or not
+ * finite get guess = E.  mode KTMI_MLP_*.  Async on stream (hipStream_t). */
+int ktmi_mlp_forward(const float *params, int n, const double *E, const double *M, double emin,
+                     double *guess, int mode, void *stream);
+
+/* Gradient of the mean over the samples with E >= emin (finite) of
+ * ((guess - eps)/E)^2.  out (device, ktmi_mlp_nparam() + 2 floats): the
+ * gradient, then the mean loss, then the sample count.  The backward pass is
+ * FP32; mode selects the forward as above.  Deterministic (fixed reduction
+ * order).  ws: caller-owned device scratch of ktmi_mlp_grad_workspace_bytes(n)
+ * bytes.  KTMI_EINVAL on bad arguments or a short workspace.  Async. */
+size_t ktmi_mlp_grad_workspace_bytes(int n);
+int ktmi_mlp_grad(const float *params, int n, const double *E, const double *M, const double *eps,
+                  double emin, int mode, float *out, void *ws, size_t bytes, void *stream);
+
+/* One Adam step (Kingma & Ba 2015; bias-corrected moments, t counts from 1) on
+ * params with gradient grad and moment arrays m, v (device, updated).  Async. */
+int ktmi_mlp_adam(float *params, const float *grad, float *m, float *v, int t, float lr, float b1,
+                  float b2, float epsilon, void *stream);
 
 /* Message of the last error on h (or of the last failed ktmi_create if h is
  * NULL).  Valid until the next call on h. */

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libktmi.so")
 
 KTMI_OK, KTMI_EINVAL, KTMI_ESTATE, KTMI_EHIP = 0, -22, -5, -71
 KTMI_FP64, KTMI_MIXED = 0, 1
-KTMI_GUESS_PREV, KTMI_GUESS_COLD = 0, 1
+KTMI_GUESS_PREV, KTMI_GUESS_COLD, KTMI_GUESS_MLP = 0, 1, 2
+KTMI_MLP_FP32, KTMI_MLP_BF16 = 0, 1
 KTMI_F_EPS, KTMI_F_UX, KTMI_F_PI, KTMI_F_T, KTMI_F_UPREV = 0, 1, 4, 14, 18
 
 FIELDS = {"eps": 0, "ux": 1, "uy": 2, "ue": 3}
@@ -51,7 +52,7 @@ def _load():
         raise ImportError(f"{LIB_PATH} is missing: build it with python -c "
                           "'import __graft_entry__ as g; g.build()' (no CPU fallback exists)")
     lib = C.CDLL(LIB_PATH)
-    vp, dp, sz = C.c_void_p, C.POINTER(C.c_double), C.c_size_t
+    vp, dp, sz, f = C.c_void_p, C.POINTER(C.c_double), C.c_size_t, C.c_float
     sig = {
         "ktmi_desc_default": (None, [C.POINTER(ktmi_desc)]),
         "ktmi_create": (C.c_int, [C.POINTER(ktmi_desc), C.POINTER(vp)]),
@@ -81,6 +82,15 @@ def _load():
         "ktmi_group_class_count": (C.c_int, [vp]),
         "ktmi_group_last_error": (C.c_char_p, [vp]),
         "ktmi_group_destroy": (None, [vp]),
+        "ktmi_mlp_nparam": (C.c_int, []),
+        "ktmi_set_mlp": (C.c_int, [vp, vp, C.c_int]),
+        "ktmi_set_guess": (C.c_int, [vp, C.c_int]),
+        "ktmi_harvest": (C.c_int, [vp, vp, vp, vp]),
+        "ktmi_mlp_forward": (C.c_int, [vp, C.c_int, vp, vp, C.c_double, vp, C.c_int, vp]),
+        "ktmi_mlp_grad_workspace_bytes": (sz, [C.c_int]),
+        "ktmi_mlp_grad": (C.c_int, [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, vp, vp, sz,
+                                    vp]),
+        "ktmi_mlp_adam": (C.c_int, [vp, vp, vp, vp, C.c_int, f, f, f, f, vp]),
         "ktmi_last_error": (C.c_char_p, [vp]),
         "ktmi_destroy": (None, [vp]),
     }
@@ -232,6 +242,46 @@ def ktmi_group_destroy(g):
     lib.ktmi_group_destroy(g)
 
 
+def ktmi_mlp_nparam() -> int:
+    return int(lib.ktmi_mlp_nparam())
+
+
+def ktmi_set_mlp(h, params_ptr: int, mode: int):
+    _check(lib.ktmi_set_mlp(h, C.c_void_p(params_ptr), int(mode)), h)
+
+
+def ktmi_set_guess(h, guess: int):
+    _check(lib.ktmi_set_guess(h, int(guess)), h)
+
+
+def ktmi_harvest(h, E_ptr: int, M_ptr: int, eps_ptr: int):
+    _check(lib.ktmi_harvest(h, C.c_void_p(E_ptr), C.c_void_p(M_ptr), C.c_void_p(eps_ptr)), h)
+
+
+def ktmi_mlp_forward(params_ptr, n, E_ptr, M_ptr, emin, guess_ptr, mode, stream_ptr):
+    _check(lib.ktmi_mlp_forward(C.c_void_p(params_ptr), int(n), C.c_void_p(E_ptr),
+                                C.c_void_p(M_ptr), float(emin), C.c_void_p(guess_ptr), int(mode),
+                                C.c_void_p(stream_ptr)))
+
+
+def ktmi_mlp_grad_workspace_bytes(n: int) -> int:
+    return int(lib.ktmi_mlp_grad_workspace_bytes(int(n)))
+
+
+def ktmi_mlp_grad(params_ptr, n, E_ptr, M_ptr, eps_ptr, emin, mode, out_ptr, ws_ptr, ws_bytes,
+                  stream_ptr):
+    _check(lib.ktmi_mlp_grad(C.c_void_p(params_ptr), int(n), C.c_void_p(E_ptr),
+                             C.c_void_p(M_ptr), C.c_void_p(eps_ptr), float(emin), int(mode),
+                             C.c_void_p(out_ptr), C.c_void_p(ws_ptr), int(ws_bytes),
+                             C.c_void_p(stream_ptr)))
+
+
+def ktmi_mlp_adam(params_ptr, grad_ptr, m_ptr, v_ptr, t, lr, b1, b2, epsilon, stream_ptr):
+    _check(lib.ktmi_mlp_adam(C.c_void_p(params_ptr), C.c_void_p(grad_ptr), C.c_void_p(m_ptr),
+                             C.c_void_p(v_ptr), int(t), float(lr), float(b1), float(b2),
+                             float(epsilon), C.c_void_p(stream_ptr)))
+
+
 def ktmi_destroy(h):
     lib.ktmi_destroy(h)
 
@@ -322,6 +372,20 @@ class Hydro:
 
     def set_graph(self, on=True):
         ktmi_set_graph(self.h, on)
+
+    def set_mlp(self, params, mode=KTMI_MLP_FP32):
+        """Network parameters (device float32 tensor of ktmi_mlp_nparam() values)."""
+        ktmi_set_mlp(self.h, params.data_ptr(), mode)
+
+    def set_guess(self, guess):
+        ktmi_set_guess(self.h, guess)
+
+    def harvest(self):
+        """(E, M, eps) of every cell of the current state, device tensors."""
+        t = self.torch
+        out = [t.empty(self.ncell, dtype=t.float64, device=self.device) for _ in range(3)]
+        ktmi_harvest(self.h, *[o.data_ptr() for o in out])
+        return out
 
 
 class Group:

@@ -6,7 +6,7 @@ import subprocess
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
-SOURCES = [os.path.join(_HERE, "csrc", "ktmi.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("ktmi.hip", "ktmi_mlp.hip")]
 LIB = os.path.join(_HERE, "libktmi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

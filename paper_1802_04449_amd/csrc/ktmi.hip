@@ -29,11 +29,23 @@
 
 #include "../../include/ktmi.h"
 #include "ktmi_device.hpp"
+#include "ktmi_mlp.hpp"
 
 namespace ktmi {
 
 constexpr int kBlock = 256;
 constexpr int kNP = 12;            // diagnostic partials per workgroup
+
+// Optional lower bound on the waves per SIMD of the stencil kernels (the
+// compiler then caps their registers accordingly); 0 leaves it to the compiler.
+#ifndef KTMI_WAVES_PER_EU
+#define KTMI_WAVES_PER_EU 0
+#endif
+#if KTMI_WAVES_PER_EU > 0
+#define KTMI_OCC __attribute__((amdgpu_waves_per_eu(KTMI_WAVES_PER_EU)))
+#else
+#define KTMI_OCC
+#endif
 constexpr int kEosMaxRows = 8192;  // table capacity reserved in the workspace
 
 // Partial slots.  Sums: 0, 2, 3, 5-8, 10, 11.  Maxima: 1, 4, 9.
@@ -110,6 +122,29 @@ __device__ __forceinline__ int tile_of_block(int nb) {
   const int b = blockIdx.x, x = b & 7, k = b >> 3;
   const int per = nb >> 3, rem = nb & 7;
   return x * per + (x < rem ? x : rem) + k;
+}
+
+// Starting point of the root solve of K = (E, K1, K2, K3): the previous
+// stage's e, E itself (cold), or (NET kernels only) the network's guess.
+// Every lane of the wave calls it (the matrix-core forward runs on whole
+// waves); lanes with act = false only take part.  The guess mode is uniform
+// over a workgroup.  The network lives in separate kernel instances (NET) so
+// that its registers do not lower the occupancy of the others.
+template <bool NET>
+__device__ __forceinline__ double root_guess(const StepParams& p, bool act, double E, double K1,
+                                             double K2, double K3, double prev) {
+  if (NET && p.guess == KTMI_GUESS_MLP) {
+    const double M2 = K1 * K1 + K2 * K2 + K3 * K3;
+    const bool use = act && E >= p.eps_cut && E < 1e300 && M2 < 1e300;
+    if (p.mlp_mfma) {
+      if (__ballot(use) == 0) return prev;
+      const double g = mlp_guess_wave(p.mlp, reinterpret_cast<const uint16_t*>(p.mlp + kMlpPad),
+                                      use ? E : 1.0, use ? M2 : 0.0);
+      return use ? g : prev;
+    }
+    return use ? mlp_guess_lane(p.mlp, E, M2) : prev;
+  }
+  return p.guess == KTMI_GUESS_COLD ? E : prev;
 }
 
 // Position of this thread's cell.
@@ -190,11 +225,12 @@ __device__ __forceinline__ R face_flux(const double* __restrict__ e, const doubl
   int idx[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) idx[t] = base + clampi(a - 1 + t, 0, n - 1) * stride;
-  // Vacuum test first, on the stored FP64 values: every state the kernels write
-  // has u~ = 0 where e = 0 (the root solve and the cutoff return all-zero
-  // primitives), and with PI_SRC 0/1 pi~ is zero there as well, so e alone
-  // decides; as-stored pi~ (PI_SRC 2) is checked too.  A vacuum face then skips
-  // the remaining loads and all arithmetic.
+  // Vacuum faces skip all arithmetic.  Every state the kernels write has u~ = 0
+  // where e = 0 (the root solve and the cutoff return all-zero primitives), and
+  // with PI_SRC 0/1 pi~ reads as zero there too, so e alone decides: it is
+  // loaded first and a vacuum face skips the other loads.  As-stored pi~
+  // (PI_SRC 2) can be nonzero where e = 0, so there the whole stencil is loaded
+  // at once (no dependent second round of loads) and e and pi~ decide.
   double ev[4];
   bool vac = true;
 #pragma unroll
@@ -202,29 +238,38 @@ __device__ __forceinline__ R face_flux(const double* __restrict__ e, const doubl
     ev[t] = e[idx[t]];
     vac = vac && (ev[t] == 0.0);
   }
-  if (PI_SRC == 2 && vac) {
+  R q4[14][4];
+  if (PI_SRC == 2) {
 #pragma unroll
     for (int m = 0; m < 10; ++m)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) vac = vac && (pi[m][idx[t]] == 0.0);
+      for (int t = 0; t < 4; ++t) {
+        const double x = pi[m][idx[t]];
+        vac = vac && (x == 0.0);
+        q4[4 + m][t] = (R)x;
+      }
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) q4[1 + m][t] = (R)u[m][idx[t]];
   }
   if (vac) {
 #pragma unroll
     for (int k = 0; k < 14; ++k) H[k] = R(0);
     return (R)p.c_vac;
   }
-  // Load the rest of the 4-cell stencil, converting to R at once.
-  R q4[14][4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) q4[0][t] = (R)ev[t];
+  if (PI_SRC != 2) {
 #pragma unroll
-  for (int m = 0; m < 3; ++m)
+    for (int m = 0; m < 3; ++m)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) q4[1 + m][t] = (R)u[m][idx[t]];
+      for (int t = 0; t < 4; ++t) q4[1 + m][t] = (R)u[m][idx[t]];
 #pragma unroll
-  for (int m = 0; m < 10; ++m)
+    for (int m = 0; m < 10; ++m)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) q4[4 + m][t] = (R)ld_pi<PI_SRC>(pi, m, idx[t], ev[t]);
+      for (int t = 0; t < 4; ++t) q4[4 + m][t] = (R)ld_pi<PI_SRC>(pi, m, idx[t], ev[t]);
+  }
   R qL[14], qR[14];
   const R th = (R)p.theta;
 #pragma unroll
@@ -559,18 +604,26 @@ __global__ __launch_bounds__(kBlock) void k_init_primitive(Fields f, StepParams 
 }
 
 // Initial conserved state: root solve of K = T~/tau0 - pi~^{tau .} from E.
+template <bool NET>
 __global__ __launch_bounds__(kBlock) void k_init_conserved(Fields f, StepParams p, EosDev eos,
                                                             Geo g, int visc) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= p.ncell) return;
+  const bool act = c < p.ncell;  // no early exit: root_guess needs whole waves
   const double tf = g.cart ? 1.0 : g.tau;
-  double pv[10];
+  double pv[10], K0 = 1.0, K1 = 0.0, K2 = 0.0, K3 = 0.0;
+  if (act) {
 #pragma unroll
-  for (int m = 0; m < 10; ++m) pv[m] = visc ? f.pi[m][c] : 0.0;
-  const double K0 = f.T[0][c] / tf - pv[0], K1 = f.T[1][c] / tf - pv[1];
-  const double K2 = f.T[2][c] / tf - pv[2], K3 = f.T[3][c] / tf - pv[3];
+    for (int m = 0; m < 10; ++m) pv[m] = visc ? f.pi[m][c] : 0.0;
+    K0 = f.T[0][c] / tf - pv[0];
+    K1 = f.T[1][c] / tf - pv[1];
+    K2 = f.T[2][c] / tf - pv[2];
+    K3 = f.T[3][c] / tf - pv[3];
+  }
+  // no previous stage here: the cold start E unless the network guesses
+  const double x0 = root_guess<NET>(p, act, K0, K1, K2, K3, K0);
+  if (!act) return;
   int it, fl;
-  const Prim s = con2prim(eos, p, K0, K1, K2, K3, K0, it, fl);
+  const Prim s = con2prim(eos, p, K0, K1, K2, K3, x0, it, fl);
   f.e[c] = s.e;
   f.u[0][c] = s.u1;
   f.u[1][c] = s.u2;
@@ -594,33 +647,40 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(const EventDesc* __re
   const double tf = g.cart ? 1.0 : g.tau;
   double R[14];
   tile_divergence<RT, TX, TY, TZ, true, false, 0>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
-  if (!q.active) return;
   const int c = q.c;
-  const double e = f.e[c], u1 = f.u[0][c], u2 = f.u[1][c], u3 = f.u[2][c];
-  const double ut = utau(u1, u2, u3);
-  double P, cs2;
-  eos_p_cs2(eos, e, P, cs2);
-  const double w = (e > 0.0 ? e : 0.0) + P;
-  if (!g.cart) {
-    R[0] += -(w * u3 * u3 + P);
-    R[3] += -(w * ut * u3);
-  }
-  const double u4[4] = {ut, u1, u2, u3};
-  double K[4];
-  const double inv_tf1 = 1.0 / (g.cart ? 1.0 : g.tau1);
+  double K[4] = {1.0, 0.0, 0.0, 0.0}, e = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+  if (q.active) {
+    e = f.e[c];
+    u1 = f.u[0][c];
+    u2 = f.u[1][c];
+    u3 = f.u[2][c];
+    const double ut = utau(u1, u2, u3);
+    double P, cs2;
+    eos_p_cs2(eos, e, P, cs2);
+    const double w = (e > 0.0 ? e : 0.0) + P;
+    if (!g.cart) {
+      R[0] += -(w * u3 * u3 + P);
+      R[3] += -(w * ut * u3);
+    }
+    const double u4[4] = {ut, u1, u2, u3};
+    const double inv_tf1 = 1.0 / (g.cart ? 1.0 : g.tau1);
 #pragma unroll
-  for (int nu = 0; nu < 4; ++nu)
-    K[nu] = (tf * (w * ut * u4[nu] - (nu == 0 ? P : 0.0)) + p.h * R[nu]) * inv_tf1;
+    for (int nu = 0; nu < 4; ++nu)
+      K[nu] = (tf * (w * ut * u4[nu] - (nu == 0 ? P : 0.0)) + p.h * R[nu]) * inv_tf1;
+  }
+  // the current e is a close start; the network is not used here
+  const double x0 = root_guess<false>(p, q.active, K[0], K[1], K[2], K[3], e);
+  if (!q.active) return;
   int it, fl;
-  const Prim s = con2prim(eos, p, K[0], K[1], K[2], K[3], e, it, fl);
+  const Prim s = con2prim(eos, p, K[0], K[1], K[2], K[3], x0, it, fl);
   f.up[0][c] = 2.0 * u1 - s.u1;
   f.up[1][c] = 2.0 * u2 - s.u2;
   f.up[2][c] = 2.0 * u3 - s.u3;
 }
 
 // Stage 1 at tau_n (predictor) for the ideal (VISC = false) or viscous path.
-template <typename RT, int TX, int TY, int TZ, bool VISC>
-__global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__ evs,
+template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET>
+__global__ __launch_bounds__(kBlock) KTMI_OCC void k_stage1(const EventDesc* __restrict__ evs,
                                                     GroupTable gt) {
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 0);
@@ -637,6 +697,7 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
   const double cfl =
       tile_divergence<RT, TX, TY, TZ, true, VISC, VISC ? 1 : 0>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
   v[P_CFL] = cfl * p.h;
+  double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0;
   if (q.active) {
     const int c = q.c;
     const double e = f.e[c], u1 = f.u[0][c], u2 = f.u[1][c], u3 = f.u[2][c];
@@ -680,10 +741,15 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
       f.T1[nu][c] = T1[nu];
     }
     const double inv_tf1 = 1.0 / (g.cart ? 1.0 : g.tau1);
-    const double K0 = T1[0] * inv_tf1 - p1[0];
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) K[nu] = T1[nu] * inv_tf1 - p1[nu];
+    prev = e;
+  }
+  const double x0 = root_guess<NET>(p, q.active, K[0], K[1], K[2], K[3], prev);
+  if (q.active) {
+    const int c = q.c;
     int it, fl;
-    const Prim s = con2prim(eos, p, K0, T1[1] * inv_tf1 - p1[1], T1[2] * inv_tf1 - p1[2],
-                            T1[3] * inv_tf1 - p1[3], p.guess_cold ? K0 : e, it, fl);
+    const Prim s = con2prim(eos, p, K[0], K[1], K[2], K[3], x0, it, fl);
     count_solve(v, it, fl);
     f.e1[c] = s.e;
     f.u1[0][c] = s.u1;
@@ -695,7 +761,7 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
 
 // Stage 2, part 1 (tau_{n+1}): pi^{n+1} = [ (u^n pi^n + u* pi')/2 + h/2 R_pi(e', u', pi') ] / u'^tau.
 template <typename RT, int TX, int TY, int TZ>
-__global__ __launch_bounds__(kBlock) void k_stage2_pi(const EventDesc* __restrict__ evs,
+__global__ __launch_bounds__(kBlock) KTMI_OCC void k_stage2_pi(const EventDesc* __restrict__ evs,
                                                       GroupTable gt) {
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 1);
@@ -737,8 +803,8 @@ __global__ __launch_bounds__(kBlock) void k_stage2_pi(const EventDesc* __restric
 
 // Stage 2, part 2 (tau_{n+1}): T^{n+1} = T^n + [(T' - T^n) + h R_T(e', u', pi^{n+1})]/2,
 // root solve -> (e, u~)^{n+1} (written over e^n and u~^{n-1}), diagnostics.
-template <typename RT, int TX, int TY, int TZ, bool VISC>
-__global__ __launch_bounds__(kBlock) void k_stage2_T(const EventDesc* __restrict__ evs,
+template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET>
+__global__ __launch_bounds__(kBlock) KTMI_OCC void k_stage2_T(const EventDesc* __restrict__ evs,
                                                      GroupTable gt) {
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 1);
@@ -755,6 +821,7 @@ __global__ __launch_bounds__(kBlock) void k_stage2_T(const EventDesc* __restrict
   const double cfl = tile_divergence<RT, TX, TY, TZ, true, false, VISC ? 2 : 0>(f.e1, f.u1, f.pi, p,
                                                                           eos, tf, q, R, lds);
   v[P_CFL] = cfl * p.h;
+  double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0;
   if (q.active) {
     const int c = q.c;
     const double e1 = f.e1[c], u1 = f.u1[0][c], u2 = f.u1[1][c], u3 = f.u1[2][c];
@@ -779,17 +846,22 @@ __global__ __launch_bounds__(kBlock) void k_stage2_T(const EventDesc* __restrict
       f.T[nu][c] = Tn[nu];
     }
     const double inv_tf1 = 1.0 / (g.cart ? 1.0 : g.tau1);
-    const double K0 = Tn[0] * inv_tf1 - pc[0];
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) K[nu] = Tn[nu] * inv_tf1 - pc[nu];
+    prev = e1;
+    v[P_TSUM] = Tn[0];
+  }
+  const double x0 = root_guess<NET>(p, q.active, K[0], K[1], K[2], K[3], prev);
+  if (q.active) {
+    const int c = q.c;
     int it, fl;
-    const Prim s = con2prim(eos, p, K0, Tn[1] * inv_tf1 - pc[1], Tn[2] * inv_tf1 - pc[2],
-                            Tn[3] * inv_tf1 - pc[3], p.guess_cold ? K0 : e1, it, fl);
+    const Prim s = con2prim(eos, p, K[0], K[1], K[2], K[3], x0, it, fl);
     count_solve(v, it, fl);
     f.e[c] = s.e;
     f.up[0][c] = s.u1;  // becomes u~^{n+1} after the host swaps u and up
     f.up[1][c] = s.u2;
     f.up[2][c] = s.u3;
     v[P_EMAX] = s.e;
-    v[P_TSUM] = Tn[0];
     v[P_VAC] = s.e == 0.0 ? 1.0 : 0.0;
   }
   block_partials(v, f.partial + (size_t)kNP * cx.tg.ntiles, cx.tg.ntiles, cx.tile);
@@ -868,6 +940,34 @@ __global__ __launch_bounds__(kBlock) void k_read_pi(const double* __restrict__ e
   if (c < n) dst[c] = e[c] == 0.0 ? 0.0 : pi[c];
 }
 
+// Copies the network parameters into the handle's workspace and appends W2 as BF16.
+__global__ void k_mlp_pack(const float* __restrict__ src, float* __restrict__ dst) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < kMlpNParam) dst[k] = src[k];
+  if (k < kMlpH * kMlpH)
+    reinterpret_cast<uint16_t*>(dst + kMlpPad)[k] = (uint16_t)to_bf16(src[kOW2 + k]);
+}
+
+// Training samples from the current state: E = K^tau, M = |K|, with
+// K = T~^{tau .}/tau - pi~^{tau .}, and the cell's e (the root of that K).
+__global__ __launch_bounds__(kBlock) void k_harvest(Fields f, const double* __restrict__ clk,
+                                                    int cart, int visc, int n,
+                                                    double* __restrict__ E, double* __restrict__ M,
+                                                    double* __restrict__ eps) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= n) return;
+  const double tf = cart ? 1.0 : clk[0];
+  const double e = f.e[c];
+  const bool pv = visc && e != 0.0;
+  const double K0 = f.T[0][c] / tf - (pv ? f.pi[0][c] : 0.0);
+  const double K1 = f.T[1][c] / tf - (pv ? f.pi[1][c] : 0.0);
+  const double K2 = f.T[2][c] / tf - (pv ? f.pi[2][c] : 0.0);
+  const double K3 = f.T[3][c] / tf - (pv ? f.pi[3][c] : 0.0);
+  E[c] = K0;
+  M[c] = sqrt(K1 * K1 + K2 * K2 + K3 * K3);
+  eps[c] = e;
+}
+
 __global__ void k_zero(double* p, int n) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c < n) p[c] = 0.0;
@@ -925,6 +1025,10 @@ struct ktmi_handle {
   // graph of one step, replayed by ktmi_step when enabled
   bool use_graph = false;
   hipGraphExec_t gexec = nullptr;
+  // learned root-solve guess: parameters copied into the workspace
+  float* mlp_dev = nullptr;
+  bool mlp_ok = false;
+  int mlp_mode = KTMI_MLP_FP32;
 };
 
 static std::string g_create_err;
@@ -980,7 +1084,7 @@ static bool desc_ok(const ktmi_desc* d, std::string* why) {
     *why = "precision must be KTMI_FP64 or KTMI_MIXED";
     return false;
   }
-  if (d->guess != KTMI_GUESS_PREV && d->guess != KTMI_GUESS_COLD) {
+  if (d->guess != KTMI_GUESS_PREV && d->guess != KTMI_GUESS_COLD && d->guess != KTMI_GUESS_MLP) {
     *why = "unknown guess mode";
     return false;
   }
@@ -1058,7 +1162,9 @@ static StepParams step_params(const ktmi_handle* h) {
   p.newton_tol = h->d.newton_tol;
   p.pi_reg = h->d.pi_reg;
   p.newton_maxit = h->d.newton_maxit;
-  p.guess_cold = h->d.guess == KTMI_GUESS_COLD;
+  p.guess = h->d.guess;
+  p.mlp_mfma = h->mlp_mode == KTMI_MLP_BF16;
+  p.mlp = h->mlp_ok ? h->mlp_dev : nullptr;
   return p;
 }
 
@@ -1100,18 +1206,22 @@ static Geo geo(const ktmi_handle* h, double tau, double tau1) {
 
 // One grouped launch of stencil kernel K over the events of a table that share
 // a tile shape, precision and mode.
-template <template <typename, int, int, int> class K>
-static void launch_class(hipStream_t s, int tile, int precision, const EventDesc* evs,
+template <template <typename, int, int, int, bool> class K>
+static void launch_class(hipStream_t s, int tile, int precision, bool net, const EventDesc* evs,
                          const GroupTable& gt) {
   const dim3 grid(gt.start[gt.nev]), block(kBlock);
   const bool mixed = precision == KTMI_MIXED;
   switch (tile) {
-#define KTMI_TILE_CASE(id, X, Y, Z)                         \
-  case id:                                                  \
-    if (mixed)                                              \
-      K<float, X, Y, Z>::launch(grid, block, s, evs, gt);   \
-    else                                                    \
-      K<double, X, Y, Z>::launch(grid, block, s, evs, gt);  \
+#define KTMI_TILE_CASE(id, X, Y, Z)                                  \
+  case id:                                                           \
+    if (mixed && net)                                                \
+      K<float, X, Y, Z, true>::launch(grid, block, s, evs, gt);      \
+    else if (mixed)                                                  \
+      K<float, X, Y, Z, false>::launch(grid, block, s, evs, gt);     \
+    else if (net)                                                    \
+      K<double, X, Y, Z, true>::launch(grid, block, s, evs, gt);     \
+    else                                                             \
+      K<double, X, Y, Z, false>::launch(grid, block, s, evs, gt);    \
     break;
     KTMI_TILE_CASE(0, 4, 4, 16)
     KTMI_TILE_CASE(1, 2, 8, 16)
@@ -1124,19 +1234,21 @@ static void launch_class(hipStream_t s, int tile, int precision, const EventDesc
   }
 }
 
+// N: the kernel instance with the learned guess (only where a root solve
+// takes a network guess; the others ignore it and are never launched with it).
 #define KTMI_LAUNCHER(NAME, KERNEL)                                                       \
-  template <typename RT, int X, int Y, int Z>                                             \
+  template <typename RT, int X, int Y, int Z, bool N>                                     \
   struct NAME {                                                                           \
     static void launch(dim3 g, dim3 b, hipStream_t s, const EventDesc* evs, GroupTable gt) { \
       hipLaunchKernelGGL((KERNEL), g, b, 0, s, evs, gt);                                  \
     }                                                                                     \
   };
 KTMI_LAUNCHER(LFirst, (k_first_estimate<RT, X, Y, Z>))
-KTMI_LAUNCHER(LStage1V, (k_stage1<RT, X, Y, Z, true>))
-KTMI_LAUNCHER(LStage1I, (k_stage1<RT, X, Y, Z, false>))
+KTMI_LAUNCHER(LStage1V, (k_stage1<RT, X, Y, Z, true, N>))
+KTMI_LAUNCHER(LStage1I, (k_stage1<RT, X, Y, Z, false, N>))
 KTMI_LAUNCHER(LStage2Pi, (k_stage2_pi<RT, X, Y, Z>))
-KTMI_LAUNCHER(LStage2TV, (k_stage2_T<RT, X, Y, Z, true>))
-KTMI_LAUNCHER(LStage2TI, (k_stage2_T<RT, X, Y, Z, false>))
+KTMI_LAUNCHER(LStage2TV, (k_stage2_T<RT, X, Y, Z, true, N>))
+KTMI_LAUNCHER(LStage2TI, (k_stage2_T<RT, X, Y, Z, false, N>))
 #undef KTMI_LAUNCHER
 
 static GroupTable single_table(const ktmi_handle* h) {
@@ -1178,23 +1290,28 @@ static int upload_event(ktmi_handle* h) {
 
 // The kernels of one step for the events of one class (same tile, precision, mode).
 static int enqueue_class_step(ktmi_handle* h, hipStream_t s, int tile, int precision, int viscous,
-                              const EventDesc* evs, const GroupTable& gt) {
+                              bool net, const EventDesc* evs, const GroupTable& gt) {
   int rc;
   if (viscous) {
-    rc = launch(h, K_STAGE1, [&] { launch_class<LStage1V>(s, tile, precision, evs, gt); });
+    rc = launch(h, K_STAGE1, [&] { launch_class<LStage1V>(s, tile, precision, net, evs, gt); });
     if (rc) return rc;
-    rc = launch(h, K_STAGE2PI, [&] { launch_class<LStage2Pi>(s, tile, precision, evs, gt); });
+    rc = launch(h, K_STAGE2PI,
+                [&] { launch_class<LStage2Pi>(s, tile, precision, false, evs, gt); });
     if (rc) return rc;
-    return launch(h, K_STAGE2T, [&] { launch_class<LStage2TV>(s, tile, precision, evs, gt); });
+    return launch(h, K_STAGE2T,
+                  [&] { launch_class<LStage2TV>(s, tile, precision, net, evs, gt); });
   }
-  rc = launch(h, K_STAGE1, [&] { launch_class<LStage1I>(s, tile, precision, evs, gt); });
+  rc = launch(h, K_STAGE1, [&] { launch_class<LStage1I>(s, tile, precision, net, evs, gt); });
   if (rc) return rc;
-  return launch(h, K_STAGE2T, [&] { launch_class<LStage2TI>(s, tile, precision, evs, gt); });
+  return launch(h, K_STAGE2T, [&] { launch_class<LStage2TI>(s, tile, precision, net, evs, gt); });
 }
+
+static bool uses_net(const ktmi_handle* h) { return h->d.guess == KTMI_GUESS_MLP; }
 
 static int enqueue_step(ktmi_handle* h) {
   const GroupTable gt = single_table(h);
-  int rc = enqueue_class_step(h, h->stream, h->tile, h->d.precision, h->d.viscous, h->dev_ev, gt);
+  int rc = enqueue_class_step(h, h->stream, h->tile, h->d.precision, h->d.viscous, uses_net(h),
+                              h->dev_ev, gt);
   if (rc) return rc;
   return launch(h, K_REDUCE, [&] {
     hipLaunchKernelGGL(k_reduce, dim3(kNP), dim3(kBlock), 0, h->stream, h->dev_ev);
@@ -1206,7 +1323,7 @@ static int finish_initial(ktmi_handle* h) {
   hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, h->stream, h->clock, h->tau);
   const GroupTable gt = single_table(h);
   int rc = launch(h, K_FIRST, [&] {
-    launch_class<LFirst>(h->stream, h->tile, h->d.precision, h->dev_ev, gt);
+    launch_class<LFirst>(h->stream, h->tile, h->d.precision, false, h->dev_ev, gt);
   });
   if (rc) return rc;
   rc = launch(h, K_INIT, [&] {
@@ -1225,21 +1342,24 @@ static double* const* prev_u(const ktmi_handle* h) { return (h->step & 1) ? h->f
 static int check_setup(ktmi_handle* h) {
   if (!h->bound) return fail(h, KTMI_ESTATE, "no workspace bound");
   if (!h->eos_set) return fail(h, KTMI_ESTATE, "EoS table must be set after binding");
+  if (h->d.guess == KTMI_GUESS_MLP && !h->mlp_ok)
+    return fail(h, KTMI_ESTATE, "guess mode KTMI_GUESS_MLP needs ktmi_set_mlp first");
   return KTMI_OK;
 }
 
 
 // ---------------------------------------------------------------------------
 // Groups: many events stepped together.  Events are sorted into classes of
-// equal (mode, precision, tile shape); per class and stage one launch covers
-// the tiles of all its events (the kernels find their event from the tile
-// index), then one reduce launch serves every event.
+// equal (mode, precision, tile shape, guess kind); per class and stage one
+// launch covers the tiles of all its events (the kernels find their event from
+// the tile index), then one reduce launch serves every event.
 // ---------------------------------------------------------------------------
 struct ktmi_group {
   std::vector<ktmi_handle*> hs;  // in class order
   hipStream_t stream = nullptr;
   struct Class {
     int tile, precision, viscous;
+    bool net;   // learned root-solve guess
     int first;  // index of the class's first event in the device table
     GroupTable gt;
   };
@@ -1260,7 +1380,8 @@ static int group_fail(ktmi_group* g, int code, const std::string& msg) {
 static int enqueue_group_step(ktmi_group* g) {
   ktmi_handle* h = &g->timing_stub;
   for (const auto& c : g->classes) {
-    int rc = enqueue_class_step(h, g->stream, c.tile, c.precision, c.viscous, g->dev + c.first, c.gt);
+    int rc = enqueue_class_step(h, g->stream, c.tile, c.precision, c.viscous, c.net, g->dev + c.first,
+                                c.gt);
     if (rc) return group_fail(g, rc, h->err);
   }
   const int nev = (int)g->hs.size();
@@ -1295,6 +1416,7 @@ size_t ktmi_workspace_bytes(const ktmi_desc* d) {
   bytes += 3 * (size_t)kEosMaxRows * sizeof(double);          // EoS table
   bytes += 3 * (size_t)kEosMaxRows * sizeof(float);           // its FP32 copy
   bytes += 4096 + 512;                                         // event table, clock
+  bytes += (kMlpDevBytes + 255) / 256 * 256;                   // network parameters
   return bytes;
 }
 
@@ -1328,6 +1450,7 @@ int ktmi_bind(ktmi_handle* h, void* ws, size_t bytes, void* stream) {
   if (h->ready && (char*)ws != h->ws)
     return fail(h, KTMI_ESTATE, "workspace cannot change after the initial state is set");
   if (h->eos.kind == 1 && (char*)ws != h->ws) h->eos_set = false;  // table lives in the old workspace
+  if ((char*)ws != h->ws) h->mlp_ok = false;  // so do the network parameters
   h->ws = (char*)ws;
   h->ws_bytes = bytes;
   h->stream = (hipStream_t)stream;
@@ -1355,6 +1478,7 @@ int ktmi_bind(ktmi_handle* h, void* ws, size_t bytes, void* stream) {
   rest = (double*)(((uintptr_t)rest + 255) / 256 * 256);
   h->dev_ev = (EventDesc*)rest;
   h->clock = rest + 4096 / 8;
+  h->mlp_dev = (float*)(rest + (4096 + 512) / 8);
   static_assert(sizeof(EventDesc) <= 4096, "event table slot");
   h->ev_dirty = true;
   h->bound = true;
@@ -1468,8 +1592,12 @@ int ktmi_set_initial_conserved(ktmi_handle* h, const double* T4, const double* p
   const StepParams p = step_params(h);
   const Geo g = geo(h, h->tau, h->tau);
   int rc = launch(h, K_INIT, [&] {
-    hipLaunchKernelGGL(k_init_conserved, dim3(h->nblk), dim3(kBlock), 0, s, h->f, p, h->eos, g,
-                       h->d.viscous);
+    if (uses_net(h))
+      hipLaunchKernelGGL(k_init_conserved<true>, dim3(h->nblk), dim3(kBlock), 0, s, h->f, p,
+                         h->eos, g, h->d.viscous);
+    else
+      hipLaunchKernelGGL(k_init_conserved<false>, dim3(h->nblk), dim3(kBlock), 0, s, h->f, p,
+                         h->eos, g, h->d.viscous);
   });
   if (rc) return rc;
   return finish_initial(h);
@@ -1519,6 +1647,44 @@ int ktmi_set_graph(ktmi_handle* h, int on) {
     (void)hipGraphExecDestroy(h->gexec);
     h->gexec = nullptr;
   }
+  return KTMI_OK;
+}
+
+int ktmi_set_mlp(ktmi_handle* h, const float* params, int mode) {
+  if (!h) return KTMI_EINVAL;
+  if (!h->bound) return fail(h, KTMI_ESTATE, "bind a workspace before setting the network");
+  if (!params) return fail(h, KTMI_EINVAL, "null parameter pointer");
+  if (mode != KTMI_MLP_FP32 && mode != KTMI_MLP_BF16)
+    return fail(h, KTMI_EINVAL, "mode must be KTMI_MLP_FP32 or KTMI_MLP_BF16");
+  hipLaunchKernelGGL(k_mlp_pack, dim3((kMlpNParam + 255) / 256), dim3(256), 0, h->stream, params,
+                     h->mlp_dev);
+  HIP_TRY(h, hipGetLastError());
+  h->mlp_ok = true;
+  h->mlp_mode = mode;
+  h->ev_dirty = true;  // the next step re-uploads the event table (and re-captures a graph)
+  return KTMI_OK;
+}
+
+int ktmi_set_guess(ktmi_handle* h, int guess) {
+  if (!h) return KTMI_EINVAL;
+  if (guess != KTMI_GUESS_PREV && guess != KTMI_GUESS_COLD && guess != KTMI_GUESS_MLP)
+    return fail(h, KTMI_EINVAL, "unknown guess mode");
+  if (guess == KTMI_GUESS_MLP && !h->mlp_ok)
+    return fail(h, KTMI_ESTATE, "guess mode KTMI_GUESS_MLP needs ktmi_set_mlp first");
+  h->d.guess = guess;
+  h->ev_dirty = true;
+  return KTMI_OK;
+}
+
+int ktmi_harvest(ktmi_handle* h, double* E, double* M, double* eps) {
+  if (!h) return KTMI_EINVAL;
+  if (!h->ready) return fail(h, KTMI_ESTATE, "no state to harvest");
+  if (!E || !M || !eps) return fail(h, KTMI_EINVAL, "null output pointer");
+  const int n = h->d.nx * h->d.ny * h->d.ne;
+  Fields f = h->f;
+  hipLaunchKernelGGL(k_harvest, dim3(h->nblk), dim3(kBlock), 0, h->stream, f, h->clock,
+                     h->d.cartesian, h->d.viscous, n, E, M, eps);
+  HIP_TRY(h, hipGetLastError());
   return KTMI_OK;
 }
 
@@ -1657,13 +1823,14 @@ int ktmi_group_create(ktmi_handle* const* hs, int nev, void* ws, size_t bytes, k
     int c = -1;
     for (size_t k = 0; k < g->classes.size(); ++k)
       if (g->classes[k].tile == h->tile && g->classes[k].precision == h->d.precision &&
-          g->classes[k].viscous == h->d.viscous)
+          g->classes[k].viscous == h->d.viscous && g->classes[k].net == uses_net(h))
         c = (int)k;
     if (c < 0) {
       ktmi_group::Class cl{};
       cl.tile = h->tile;
       cl.precision = h->d.precision;
       cl.viscous = h->d.viscous;
+      cl.net = uses_net(h);
       g->classes.push_back(cl);
       members.emplace_back();
       c = (int)g->classes.size() - 1;
