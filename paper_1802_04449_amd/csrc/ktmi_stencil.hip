@@ -1,0 +1,59 @@
+// ktmi_stencil.hip -- instances of one stencil pass of the RK2 step for one
+// arithmetic type, and the launcher the host code calls for them.  The build
+// compiles this file once per (pass, type) with -DKTMI_PASS=<0..5>
+// -DKTMI_RT=<double|float> -DKTMI_LAUNCH_FN=launch_pass<P>_<f64|f32>, so the
+// instances compile in parallel.  Passes: 0 first-step estimate, 1 / 2 stage 1
+// (viscous / ideal), 3 stage 2 pi, 4 / 5 stage 2 T (viscous / ideal).
+#include "ktmi_kernels.hpp"
+
+#if !defined(KTMI_PASS) || !defined(KTMI_RT) || !defined(KTMI_LAUNCH_FN)
+#error "build with -DKTMI_PASS, -DKTMI_RT and -DKTMI_LAUNCH_FN"
+#endif
+
+namespace ktmi {
+namespace {
+
+template <int X, int Y, int Z, bool N>
+void launch_tile(dim3 g, dim3 b, hipStream_t s, const EventDesc* evs, const GroupTable& gt) {
+#if KTMI_PASS == 0
+  hipLaunchKernelGGL((k_first_estimate<KTMI_RT, X, Y, Z>), g, b, 0, s, evs, gt);
+#elif KTMI_PASS == 1
+  hipLaunchKernelGGL((k_stage1<KTMI_RT, X, Y, Z, true, N>), g, b, 0, s, evs, gt);
+#elif KTMI_PASS == 2
+  hipLaunchKernelGGL((k_stage1<KTMI_RT, X, Y, Z, false, N>), g, b, 0, s, evs, gt);
+#elif KTMI_PASS == 3
+  hipLaunchKernelGGL((k_stage2_pi<KTMI_RT, X, Y, Z>), g, b, 0, s, evs, gt);
+#elif KTMI_PASS == 4
+  hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, true, N>), g, b, 0, s, evs, gt);
+#elif KTMI_PASS == 5
+  hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, false, N>), g, b, 0, s, evs, gt);
+#else
+#error "KTMI_PASS out of range"
+#endif
+}
+
+// passes without a root solve have no network instances
+constexpr bool kHasNet = KTMI_PASS != 0 && KTMI_PASS != 3;
+
+}  // namespace
+
+// One launch over the tiles of every event in gt (events of one class).
+void KTMI_LAUNCH_FN(hipStream_t s, int tile, bool net, const EventDesc* evs,
+                    const GroupTable& gt) {
+  const dim3 grid(gt.start[gt.nev]), block(kBlock);
+  switch (tile) {
+#define KTMI_TILE_CASE(id, X, Y, Z)                        \
+  case id:                                                 \
+    if (kHasNet && net)                                    \
+      launch_tile<X, Y, Z, kHasNet>(grid, block, s, evs, gt); \
+    else                                                   \
+      launch_tile<X, Y, Z, false>(grid, block, s, evs, gt); \
+    break;
+    KTMI_TILE_LIST(KTMI_TILE_CASE)
+#undef KTMI_TILE_CASE
+    default:
+      break;
+  }
+}
+
+}  // namespace ktmi
