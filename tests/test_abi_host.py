@@ -106,3 +106,35 @@ def test_group_workspace_size():
     import paper_1802_04449_amd as K
     assert K.ktmi_group_workspace_bytes(0) == 0
     assert K.ktmi_group_workspace_bytes(64) > 64 * 400
+
+
+def test_learned_guess_argument_checks():
+    """Network entry points reject bad arguments before touching a device."""
+    import paper_1802_04449_amd as K
+    assert K.ktmi_mlp_nparam() == 1249
+    assert K.ktmi_mlp_grad_workspace_bytes(0) == 0
+    assert K.ktmi_mlp_grad_workspace_bytes(1) >= (1249 + 2) * 4
+    # the gradient workspace stops growing once every workgroup sweeps several chunks
+    assert K.ktmi_mlp_grad_workspace_bytes(10 ** 7) == K.ktmi_mlp_grad_workspace_bytes(10 ** 6)
+    lib = K.lib
+    assert lib.ktmi_mlp_forward(None, 4, None, None, 1e-7, None, 0, None) == K.KTMI_EINVAL
+    assert lib.ktmi_mlp_forward(8, 0, None, None, 1e-7, None, 0, None) == K.KTMI_OK  # empty input
+    assert lib.ktmi_mlp_forward(8, 4, 8, 8, 1e-7, 8, 7, None) == K.KTMI_EINVAL        # bad mode
+    assert lib.ktmi_mlp_grad(8, 0, 8, 8, 8, 1e-7, 0, 8, 8, 1 << 20, None) == K.KTMI_EINVAL
+    assert lib.ktmi_mlp_grad(8, 1000, 8, 8, 8, 1e-7, 0, 8, 8, 16, None) == K.KTMI_EINVAL  # short ws
+    assert lib.ktmi_mlp_adam(8, 8, 8, 8, 0, 1e-3, 0.9, 0.999, 1e-8, None) == K.KTMI_EINVAL  # t < 1
+    assert lib.ktmi_mlp_adam(8, 8, 8, 8, 1, 1e-3, 1.0, 0.999, 1e-8, None) == K.KTMI_EINVAL  # b1 = 1
+    d = _desc(guess=K.KTMI_GUESS_MLP)
+    h = K.ktmi_create(d)  # the mode is accepted; the parameters are checked at set-up
+    try:
+        with pytest.raises(K.KtmiError, match="bind"):
+            K.ktmi_set_mlp(h, 8, K.KTMI_MLP_FP32)
+        with pytest.raises(K.KtmiError, match="unknown guess"):
+            K.ktmi_set_guess(h, 5)
+        with pytest.raises(K.KtmiError, match="ktmi_set_mlp"):
+            K.ktmi_set_guess(h, K.KTMI_GUESS_MLP)
+        K.ktmi_set_guess(h, K.KTMI_GUESS_COLD)
+        with pytest.raises(K.KtmiError, match="no state"):
+            K.ktmi_harvest(h, 8, 8, 8)
+    finally:
+        K.ktmi_destroy(h)
