@@ -34,6 +34,38 @@ BYTES_PER_CELL = {"stage1": (21 + 18) * 8, "stage2_pi": (31 + 10) * 8, "stage2_T
 BYTES_PER_CELL_IDEAL = {"stage1": (8 + 5) * 8, "stage2_T": (8 + 4) * 8}
 
 
+def source_sha256() -> str:
+    """Hash of the kernel sources: counter-derived traffic recorded under
+    profiles/ is used only while it matches the code being timed."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1802_04449_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp")))
+    files.append(os.path.join(ROOT, "include", "ktmi.h"))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload` from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE (calibrated against a plain copy), or None when no record exists
+    for the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_sha256():
+        return None
+    r = rec.get("bytes_per_launch", {}).get(workload, {}).get(kernel)
+    return None if r is None else r["fetch_bytes"] + r["write_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +84,12 @@ def main():
     ap.add_argument("--tile", type=int, default=-1, help="tile shape index (-1: library default)")
     ap.add_argument("--precision", type=int, default=0,
                     help="0: plain FP64; 1: mixed (FP32 flux/relaxation, FP64 root solve and sources)")
+    ap.add_argument("--guess", default="prev", choices=["prev", "mlp"],
+                    help="root-solve start for batch64: previous stage, or a network trained "
+                         "first on harvested states (GPU training kernels)")
+    ap.add_argument("--no-paths", action="store_true",
+                    help="skip the extra measurements: the same workload in mixed precision, and "
+                         "the 64-event batch with mixed precision and the learned guess")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (counter calibration)")
     args = ap.parse_args()
@@ -70,7 +108,7 @@ def main():
     from hydro_inputs import workloads as W
 
     if args.workload == "batch64":
-        print(json.dumps(bench_batch(args)), flush=True)
+        print(json.dumps(bench_batch(args, learned=args.guess == "mlp")), flush=True)
         return
     wl = {"hotspots": W.hotspots_viscous, "gubser_dense": W.gubser_dense_viscous,
           "large": W.large_event}[args.workload](steps=args.steps)
@@ -139,8 +177,10 @@ def main():
                    "eos": "1555-row synthetic crossover table",
                    "path": "plain FP64" if args.precision == 0 else "mixed FP32/FP64"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_cell": bpc[dom]},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (measured_traffic(wl.name, dom) if args.precision == 0 else None),
+                     "algorithmic_bytes": bytes_launch, "bytes_per_cell": bpc[dom],
+                     "avg_launch_ms": per_kernel[dom]["avg_ms"]},
         "kernels": {n: round(v["avg_ms"], 4) for n, v in per_kernel.items()},
         "tile": list(K.ktmi_tile_shape(K.ktmi_get_tile(g.h))),
         "tile_ms_per_step": ({str(K.ktmi_tile_shape(t)): round(v, 3) for t, v in tile_times.items()}
@@ -152,44 +192,121 @@ def main():
                     "paper_hardware": "AMD FirePro S9150, 385x385x115 cells"},
     }
     out["graph"] = bool(args.graph)
+    if args.precision == 0 and not args.no_paths:
+        del g
+        torch.cuda.synchronize()
+        out["paths"] = {"mixed_fp32_fp64": mixed_path(wl, args)}
+        b = bench_batch(args, precision=1, learned=True, steps=10, warmup=2)
+        out["paths"]["batch64_mixed_learned"] = {
+            k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "newton_mean", "training")}
+        out["paths"]["batch64_mixed_learned"]["cells"] = b["config"]["cells"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 
-def bench_batch(args):
+def mixed_path(wl, args):
+    """The same workload with FP32 reconstruction, fluxes and relaxation source
+    (FP64 root solve, geometric source and state); errors against the FP64
+    oracle are bounded by the GPU tests (<= 1e-6 in e and u~)."""
+    import torch
+
+    import paper_1802_04449_amd as K
+    g = K.Hydro(precision=K.KTMI_MIXED, **wl.params)
+    g.set_eos(wl.eos)
+    if wl.T4 is not None:
+        g.set_initial_conserved(wl.T4)
+    else:
+        g.set_initial(wl.ic)
+    g.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": wl.ncell * args.steps / dt, "unit": "cell-updates/s",
+            "ms_per_step": dt / args.steps * 1e3, "steps": args.steps}
+
+
+def train_guess(wls, steps_at=(0, 5, 10), train_steps=1500):
+    """Learned root-solve guess for a set of events: harvest (E, M, e) from FP64
+    runs of the given events at a few times, train on the GPU (library kernels)."""
+    import paper_1802_04449_amd as K
+    from paper_1802_04449_amd import mlp
+    states = []
+    for wl in wls:
+        g = K.Hydro(**wl.params)
+        g.set_eos(wl.eos)
+        g.set_initial(wl.ic)
+        done = 0
+        for t in steps_at:
+            g.step(t - done)
+            done = t
+            states.append(g.harvest())
+        del g
+    E, M, e = mlp.samples_from_states(states, emin=1e-7, seed=1)
+    tr = mlp.Trainer(E, M, e, seed=3)
+    loss0 = tr.loss()
+    t0 = time.perf_counter()
+    tr.train(train_steps, batch=4096)
+    dt = time.perf_counter() - t0
+    return tr.params, {"samples": int(E.size), "adam_steps": train_steps, "loss_initial": loss0,
+                       "loss_final": tr.loss(), "train_s": dt}
+
+
+def bench_batch(args, precision=None, learned=False, steps=None, warmup=None):
     """64 uneven events (grids 101^2..301^2 x {1, 33, 65, 105}, eta/s in {0, 0.08, 0.16})
-    stepped together: per stage one launch per (mode, tile, precision) class."""
+    stepped together: per stage one launch per (mode, tile, precision, guess) class.
+    learned: root solves start from a network trained first on harvested states
+    of two of the events."""
     import torch
 
     import paper_1802_04449_amd as K
     from hydro_inputs import workloads as W
 
-    evs = W.event_batch(nev=64, steps=args.steps)
+    precision = args.precision if precision is None else precision
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    evs = W.event_batch(nev=64, steps=steps)
+    params, train = (None, None)
+    if learned:
+        params, train = train_guess([evs[0], evs[1]])
     st = torch.cuda.Stream()
     hs = []
     for wl in evs:
-        h = K.Hydro(stream=st, precision=args.precision, **wl.params)
+        guess = K.KTMI_GUESS_MLP if learned else K.KTMI_GUESS_PREV
+        h = K.Hydro(stream=st, precision=precision, guess=guess, **wl.params)
         h.set_eos(wl.eos)
+        if learned:
+            h.set_mlp(params, K.KTMI_MLP_BF16)
         h.set_initial(wl.ic)
         hs.append(h)
     grp = K.Group(hs)
     if args.graph:
         grp.set_graph(True)
-    grp.step(args.warmup)
+    grp.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    grp.step(args.steps)
+    grp.step(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     cells = sum(wl.ncell for wl in evs)
-    return {"metric": "cell-updates/s of viscous KT+RK2 step, plain FP64 vs batched/learned/FP32 @1e-6",
-            "value": cells * args.steps / dt, "unit": "cell-updates/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f64" if args.precision == 0 else "f32+f64", "data": "synthetic",
-            "config": {"workload": "batch of 64 uneven events", "cells": cells,
-                       "classes": grp.classes, "graph": bool(args.graph)}}
+    diags = [h.diag() for h in hs]
+    solves = sum(d["solves"] for d in diags)
+    iters = sum(d["newton_mean"] * d["solves"] for d in diags)
+    path = ("FP64" if precision == 0 else "mixed FP32/FP64") + (", learned guess" if learned else "")
+    out = {"metric": "cell-updates/s of viscous KT+RK2 step, plain FP64 vs batched/learned/FP32 @1e-6",
+           "value": cells * steps / dt, "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": dt / steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if precision == 0 else "f32+f64", "data": "synthetic",
+           "config": {"workload": "batch of 64 uneven events", "cells": cells, "path": path,
+                      "classes": grp.classes, "graph": bool(args.graph)},
+           "newton_mean": iters / max(solves, 1)}
+    if train:
+        out["training"] = train
+    del grp, hs
+    return out
 
 
 def copy_calibration():

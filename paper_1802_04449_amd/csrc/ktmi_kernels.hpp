@@ -227,14 +227,19 @@ __device__ __forceinline__ R face_flux(const double* __restrict__ e, const doubl
   }
   R q4[14][4];
   if (PI_SRC == 2) {
+    // Without the pi~ flux only the components in T~'s density (tau nu) and
+    // flux (axis nu) matter: the others are neither loaded nor tested.
 #pragma unroll
-    for (int m = 0; m < 10; ++m)
+    for (int m = 0; m < 10; ++m) {
+      const bool used = DO_PI || m < 4 || m == sym(axis, 1) || m == sym(axis, 2) ||
+                        m == sym(axis, 3);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const double x = pi[m][idx[t]];
+        const double x = used ? pi[m][idx[t]] : 0.0;
         vac = vac && (x == 0.0);
         q4[4 + m][t] = (R)x;
       }
+    }
 #pragma unroll
     for (int m = 0; m < 3; ++m)
 #pragma unroll

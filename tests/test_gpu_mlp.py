@@ -155,7 +155,10 @@ def test_adam_matches_reference():
                     0.999, 1e-8, torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     pr, mr, vr = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
-    O.mlp_adam(pr, g.astype(np.float64), mr, vr, 3, lr=1e-2)
+    # the kernel receives the hyper-parameters as FP32 values: give the reference the same
+    f32 = lambda x: float(np.float32(x))
+    O.mlp_adam(pr, g.astype(np.float64), mr, vr, 3, lr=f32(1e-2), b1=f32(0.9), b2=f32(0.999),
+               epsilon=f32(1e-8))
     # FP32 update: a few ulps of parameters of size ~1
     np.testing.assert_allclose(pt.cpu().numpy(), pr, rtol=1e-6, atol=1e-6)
     np.testing.assert_allclose(mt.cpu().numpy(), mr, rtol=1e-6, atol=1e-7)
@@ -257,3 +260,32 @@ def test_learned_guess_saves_iterations(trained):
     for name in ("mlp_fp32", "mlp_bf16"):
         assert res[name]["newton_mean"] <= res["cold"]["newton_mean"] - 0.3, res
         assert res[name]["newton_mean"] < res["prev"]["newton_mean"], res
+
+
+def test_batched_learned_mixed_matches_oracle(trained):
+    """The combined path: uneven events stepped as one group, mixed precision,
+    root solves started from the network (BF16 forward); each event within the
+    reduced-precision bar (1e-6 in e and u~, L2 and hydro-cell max norms) of the
+    FP64 oracle."""
+    import torch
+    import paper_1802_04449_amd as K
+    evs = W.event_batch(nev=3, seed0=40, steps=6,
+                        sizes=[(41, 9, 0.08), (35, 1, 0.16), (39, 7, 0.0)])
+    st = torch.cuda.Stream()
+    hs = []
+    for wl in evs:
+        h = K.Hydro(stream=st, precision=K.KTMI_MIXED, guess=K.KTMI_GUESS_MLP, **wl.params)
+        h.set_eos(wl.eos)
+        h.set_mlp(trained.params, K.KTMI_MLP_BF16)
+        h.set_initial(wl.ic)
+        hs.append(h)
+    grp = K.Group(hs)
+    _say(f"batched learned mixed: {grp.classes} classes")
+    grp.step(6)
+    torch.cuda.synchronize()
+    for wl, h in zip(evs, hs):
+        err = G.precision_errors(h.fields(), G.run_oracle(wl, 6).fields())
+        _say(f"{wl.name}: " + ", ".join(f"{k} l2 {err[k]['l2']:.1e} max {err[k]['max_hydro']:.1e}"
+                                       for k in ("eps", "ux", "uy", "ue")))
+        for k in ("eps", "ux", "uy", "ue"):
+            assert err[k]["l2"] <= 1e-6 and err[k]["max_hydro"] <= 1e-6, (wl.name, k, err[k])
