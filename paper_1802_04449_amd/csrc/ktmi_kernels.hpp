@@ -208,7 +208,7 @@ template <typename R, bool DO_T, bool DO_PI, int PI_SRC>
 __device__ __forceinline__ R face_flux(const double* __restrict__ e, const double* const* u,
                                        const double* const* pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
-                                       const EosDev& eos, R H[14]) {
+                                       const EosDev& eos, R* out, int F) {
   int idx[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) idx[t] = base + clampi(a - 1 + t, 0, n - 1) * stride;
@@ -247,7 +247,7 @@ __device__ __forceinline__ R face_flux(const double* __restrict__ e, const doubl
   }
   if (vac) {
 #pragma unroll
-    for (int k = 0; k < 14; ++k) H[k] = R(0);
+    for (int k = 0; k < 14; ++k) out[k * F] = R(0);
     return (R)p.c_vac;
   }
 #pragma unroll
@@ -270,44 +270,50 @@ __device__ __forceinline__ R face_flux(const double* __restrict__ e, const doubl
     qL[v] = a1 + R(0.5) * mm_slope_r<R>(th, a0, a1, a2);
     qR[v] = a2 - R(0.5) * mm_slope_r<R>(th, a1, a2, a3);
   }
-  R QL[14], FL[14], QR[14], FR[14], sL, sR;
+  // Scalars of the two states first (u~^tau, P, c_s^2, e + P, speed), then each
+  // flux component from them and the face states, straight to LDS: only the
+  // face states stay live, not the Q and F arrays of both sides.
+  R ut[2], P[2], w[2], ud[2], sp[2];
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     const R* q = side ? qR : qL;
-    R* Q = side ? QR : QL;
-    R* F = side ? FR : FL;
     const R ux = q[1], uy = q[2], ue = q[3];
-    const R ut = sqrt(R(1) + ux * ux + uy * uy + ue * ue);
-    R P, cs2;
-    eos_p_cs2_r<R>(eos, q[0], P, cs2);
-    const R w = (q[0] > R(0) ? q[0] : R(0)) + P;
-    const R u4[4] = {ut, ux, uy, ue};
-    const R ud = u4[axis];
-    if (DO_T) {
-#pragma unroll
-      for (int nu = 0; nu < 4; ++nu) {
-        Q[nu] = tauf * (w * ut * u4[nu] - (nu == 0 ? P : R(0)) + q[4 + sym(0, nu)]);
-        F[nu] = tauf * (w * ud * u4[nu] + (nu == axis ? P : R(0)) + q[4 + sym(axis, nu)]);
-      }
-    }
-    if (DO_PI) {
-#pragma unroll
-      for (int m = 0; m < 10; ++m) {
-        Q[4 + m] = ut * q[4 + m];
-        F[4 + m] = ud * q[4 + m];
-      }
-    }
-    const R s = local_speed_r<R>(ut, ux, uy, ue, ud, cs2);
-    if (side)
-      sR = s;
-    else
-      sL = s;
+    ut[side] = sqrt(R(1) + ux * ux + uy * uy + ue * ue);
+    R cs2;
+    eos_p_cs2_r<R>(eos, q[0], P[side], cs2);
+    w[side] = (q[0] > R(0) ? q[0] : R(0)) + P[side];
+    const R u4[4] = {ut[side], ux, uy, ue};
+    ud[side] = u4[axis];
+    sp[side] = local_speed_r<R>(ut[side], ux, uy, ue, ud[side], cs2);
   }
-  const R c = fmax(sL, sR);
+  const R c = fmax(sp[0], sp[1]);
+  if (DO_T) {
 #pragma unroll
-  for (int k = 0; k < 14; ++k) {
-    const bool on = k < 4 ? DO_T : DO_PI;
-    H[k] = on ? R(0.5) * (FL[k] + FR[k]) - R(0.5) * c * (QR[k] - QL[k]) : R(0);
+    for (int nu = 0; nu < 4; ++nu) {
+      R Q[2], Fx[2];
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const R* q = side ? qR : qL;
+        const R un = nu == 0 ? ut[side] : q[nu];
+        Q[side] = tauf * (w[side] * ut[side] * un - (nu == 0 ? P[side] : R(0)) + q[4 + sym(0, nu)]);
+        Fx[side] =
+            tauf * (w[side] * ud[side] * un + (nu == axis ? P[side] : R(0)) + q[4 + sym(axis, nu)]);
+      }
+      out[nu * F] = R(0.5) * (Fx[0] + Fx[1]) - R(0.5) * c * (Q[1] - Q[0]);
+    }
+  } else {
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) out[nu * F] = R(0);
+  }
+#pragma unroll
+  for (int m = 0; m < 10; ++m) {
+    if (DO_PI) {
+      const R QL = ut[0] * qL[4 + m], QR = ut[1] * qR[4 + m];
+      const R FL = ud[0] * qL[4 + m], FR = ud[1] * qR[4 + m];
+      out[(4 + m) * F] = R(0.5) * (FL + FR) - R(0.5) * c * (QR - QL);
+    } else {
+      out[(4 + m) * F] = R(0);
+    }
   }
   return c;
 }
@@ -357,19 +363,16 @@ __device__ __forceinline__ double tile_divergence(const double* __restrict__ e,
       const int gi = q.i0 + fx, gj = q.j0 + fy, gk = q.k0 + fz;
       const int ga = (d == 0 ? q.i0 : (d == 1 ? q.j0 : q.k0)) + a;  // right cell of the face
       const bool inrow = (d == 0 || gi < p.nx) && (d == 1 || gj < p.ny) && (d == 2 || gk < p.ne);
-      RT H[14];
       if (inrow && ga <= nd) {
         const int base = d == 0 ? (gj * p.ne + gk)
                                 : (d == 1 ? (gi * p.ny) * p.ne + gk : (gi * p.ny + gj) * p.ne);
         const RT c = face_flux<RT, DO_T, DO_PI, PI_SRC>(e, u, pi, base, ga - 1, nd, stride, d + 1,
-                                                        (RT)tauf, p, eos, H);
+                                                        (RT)tauf, p, eos, lds + f, F);
         cfl = fmax(cfl, (double)c * inv_del);
       } else {
 #pragma unroll
-        for (int k = 0; k < 14; ++k) H[k] = RT(0);
+        for (int k = 0; k < 14; ++k) lds[k * F + f] = RT(0);
       }
-#pragma unroll
-      for (int k = 0; k < 14; ++k) lds[k * F + f] = H[k];
     }
     __syncthreads();
     if (q.active) {

@@ -71,3 +71,24 @@ def test_group_matches_single_events():
     # one member against the oracle as well
     of = G.run_oracle(evs[2], 6).fields()
     G.assert_parity(grouped[2].fields(), of, 1e-12, "grouped event vs oracle")
+
+
+def test_autotuner_selects_a_tile_and_results_do_not_change():
+    """The autotuner times every tile shape on the event and keeps the fastest;
+    the state it then produces equals an untuned run's (any tile gives the same
+    fields)."""
+    import paper_1802_04449_amd as K
+    from paper_1802_04449_amd import autotune
+    print("[gpu-case] autotune", flush=True)
+    wl = W.hotspots_viscous(nx=41, ny=37, ne=13, dx=0.35, dy=0.35, de=0.4, steps=4, seed=14)
+    tuned = _make(wl, None)
+    tile, times = autotune.tune(tuned, steps=1, repeats=1, use_cache=False)
+    assert 0 <= tile < K.ktmi_tile_count() and K.ktmi_get_tile(tuned.h) == tile
+    assert set(times) == set(range(K.ktmi_tile_count()))
+    assert times[tile] == min(times.values())
+    # restart from the initial state with the chosen tile, compare with the default tile
+    tuned.set_initial(wl.ic)
+    tuned.step(4)
+    plain = _make(wl, None)
+    plain.step(4)
+    _same(tuned, plain, "autotuned tile")
