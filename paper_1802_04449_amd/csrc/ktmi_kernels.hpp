@@ -198,6 +198,129 @@ __device__ __forceinline__ double ld_pi(const double* const* pi, int m, int idx,
 }
 
 // KT face flux H = [F(Q^r) + F(Q^l)]/2 - c (Q^r - Q^l)/2 (Sec. III, eq. flux_out)
+// at the face between cells a and a+1 along `axis` (1 = x, 2 = y, 3 = eta),
+// from a minmod reconstruction of the primitives on the 4-cell stencil
+// a-1 .. a+2 (generalized minmod with theta; zero-gradient boundaries by index
+// clamping).  Q_T = tau Tc^{tau nu}, F_T = tau Tc^{axis nu}; Q_pi = u~^tau
+// pi~, F_pi = u~^axis pi~; c = max local speed of the two face states.  The
+// components the pass uses (T~'s if DO_T, pi~'s if DO_PI) go to out[k * F];
+// returns c.
+//
+// Evaluated as a stream to keep few values live: e and u~ first (face states,
+// u~^tau, P, c_s^2, e + P, speeds, the fluid part of T~'s Q and F), then one
+// pi~ component at a time (its face states, its own flux, its terms in T~'s Q
+// and F), then T~'s flux.  The arithmetic of every component is that of
+// tau (w u u - P g + pi) and u pi as written, in that order.
+template <typename R, bool DO_T, bool DO_PI, int PI_SRC>
+__device__ __forceinline__ R face_flux_stream(const double* __restrict__ e, const double* const* u,
+                                       const double* const* pi, int base, int a, int n,
+                                       int stride, int axis, R tauf, const StepParams& p,
+                                       const EosDev& eos, R* out, int F) {
+  int idx[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) idx[t] = base + clampi(a - 1 + t, 0, n - 1) * stride;
+  static_assert(PI_SRC != 2, "as-stored pi~ needs face_flux_all");
+  // Vacuum faces: every state the kernels write has u~ = 0 where e = 0, and
+  // pi~ reads as zero there (PI_SRC 0/1), so e alone decides and a vacuum face
+  // skips the other loads.
+  double ev[4];
+  bool vac = true;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    ev[t] = e[idx[t]];
+    vac = vac && (ev[t] == 0.0);
+  }
+  if (vac) {
+#pragma unroll
+    for (int k = 0; k < 14; ++k)
+      if (k < 4 ? DO_T : DO_PI) out[k * F] = R(0);
+    return (R)p.c_vac;
+  }
+  const R th = (R)p.theta;
+  // e and u~ face states
+  R fL[4], fR[4];
+  {
+    R q4[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) q4[0][t] = (R)ev[t];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) q4[1 + m][t] = (R)u[m][idx[t]];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      fL[v] = q4[v][1] + R(0.5) * mm_slope_r<R>(th, q4[v][0], q4[v][1], q4[v][2]);
+      fR[v] = q4[v][2] - R(0.5) * mm_slope_r<R>(th, q4[v][1], q4[v][2], q4[v][3]);
+    }
+  }
+  R ut[2], ud[2], AQ[2][4], AF[2][4], sp[2];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const R* q = side ? fR : fL;
+    const R ux = q[1], uy = q[2], ue = q[3];
+    ut[side] = sqrt(R(1) + ux * ux + uy * uy + ue * ue);
+    R P, cs2;
+    eos_p_cs2_r<R>(eos, q[0], P, cs2);
+    const R w = (q[0] > R(0) ? q[0] : R(0)) + P;
+    const R u4[4] = {ut[side], ux, uy, ue};
+    ud[side] = u4[axis];
+    if (DO_T) {
+#pragma unroll
+      for (int nu = 0; nu < 4; ++nu) {
+        AQ[side][nu] = w * ut[side] * u4[nu] - (nu == 0 ? P : R(0));
+        AF[side][nu] = w * ud[side] * u4[nu] + (nu == axis ? P : R(0));
+      }
+    }
+    sp[side] = local_speed_r<R>(ut[side], ux, uy, ue, ud[side], cs2);
+  }
+  const R c = fmax(sp[0], sp[1]);
+  // pi~ components, one at a time
+#pragma unroll
+  for (int m = 0; m < 10; ++m) {
+    bool inT = false;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) inT = inT || m == sym(0, nu) || m == sym(axis, nu);
+    const bool need = PI_SRC != 0 && (DO_PI || (DO_T && inT));
+    if (!need) {  // no pi~ (ideal), or a component T~'s flux does not use
+      if (DO_PI) out[(4 + m) * F] = R(0);
+      continue;
+    }
+    R p4[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) p4[t] = (R)ld_pi<PI_SRC>(pi, m, idx[t], ev[t]);
+    const R pL = p4[1] + R(0.5) * mm_slope_r<R>(th, p4[0], p4[1], p4[2]);
+    const R pR = p4[2] - R(0.5) * mm_slope_r<R>(th, p4[1], p4[2], p4[3]);
+    if (DO_PI) {
+      const R QL = ut[0] * pL, QR = ut[1] * pR;
+      const R FL = ud[0] * pL, FR = ud[1] * pR;
+      out[(4 + m) * F] = R(0.5) * (FL + FR) - R(0.5) * c * (QR - QL);
+    }
+    if (DO_T) {
+#pragma unroll
+      for (int nu = 0; nu < 4; ++nu) {
+        if (m == sym(0, nu)) {
+          AQ[0][nu] = AQ[0][nu] + pL;
+          AQ[1][nu] = AQ[1][nu] + pR;
+        }
+        if (m == sym(axis, nu)) {
+          AF[0][nu] = AF[0][nu] + pL;
+          AF[1][nu] = AF[1][nu] + pR;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu) {
+    if (DO_T) {
+      const R Q0 = tauf * AQ[0][nu], Q1 = tauf * AQ[1][nu];
+      const R F0 = tauf * AF[0][nu], F1 = tauf * AF[1][nu];
+      out[nu * F] = R(0.5) * (F0 + F1) - R(0.5) * c * (Q1 - Q0);
+    }
+  }
+  return c;
+}
+
+// KT face flux H = [F(Q^r) + F(Q^l)]/2 - c (Q^r - Q^l)/2 (Sec. III, eq. flux_out)
 // at the face between cells a and a+1 along `axis` (1 = x, 2 = y, 3 = eta).
 // `base` is the flat index of the row's cell with coordinate 0 along the axis.
 // Components 0..3: T~^{d nu} part (if DO_T); 4..13: u~^d pi~ part (if DO_PI).
@@ -205,7 +328,7 @@ __device__ __forceinline__ double ld_pi(const double* const* pi, int m, int idx,
 // vacuum (all primitives zero) has H = 0 and c = c_vac, so it skips the arithmetic.
 // R is the arithmetic type (double, or float on the mixed-precision path).
 template <typename R, bool DO_T, bool DO_PI, int PI_SRC>
-__device__ __forceinline__ R face_flux(const double* __restrict__ e, const double* const* u,
+__device__ __forceinline__ R face_flux_all(const double* __restrict__ e, const double* const* u,
                                        const double* const* pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
                                        const EosDev& eos, R* out, int F) {
@@ -333,12 +456,51 @@ __device__ __forceinline__ double tile_divergence(const double* __restrict__ e,
   for (int k = 0; k < 14; ++k) R[k] = 0.0;
   double cfl = 0.0;
   const int tid = threadIdx.x;
+  // Whole-tile vacuum test for the stage-2 passes (their faces read as-stored
+  // pi~, so a per-face test needs all of the stencil's pi~).  Every face stencil
+  // of the tile reads cells in the box [i0 - 2, i0 + TX + 1] x [j0 - 2, j0 + TY
+  // + 1] x [k0 - 2, k0 + TZ + 1] (clamped to the grid).  When that box is vacuum
+  // (e = 0 and pi~ = 0), every face is a vacuum face: H = 0, c = c_vac, the
+  // values the per-face test gives, decided in one or two rounds of loads for
+  // the whole workgroup instead of one per face round.
+  if (PI_SRC == 2) {
+    constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4, NB = BX * BY * BZ;
+    // the tile's own cells first (one load per thread, which the cell phase
+    // reuses): a tile with matter skips the rest of the test
+    int nz = q.active && e[q.c] != 0.0;
+    int any = __syncthreads_or(nz);
+    if (!any) {
+      for (int b = tid; b < NB; b += kBlock) {
+        const int bx = b / (BY * BZ), by = (b / BZ) % BY, bz = b % BZ;
+        const int i = clampi(q.i0 - 2 + bx, 0, p.nx - 1), j = clampi(q.j0 - 2 + by, 0, p.ny - 1);
+        const int k = clampi(q.k0 - 2 + bz, 0, p.ne - 1);
+        nz |= e[(i * p.ny + j) * p.ne + k] != 0.0;
+      }
+      any = __syncthreads_or(nz);
+    }
+    if (!any) {  // e = 0 in the whole box: pi~ decides
+      for (int b = tid; b < NB; b += kBlock) {
+        const int bx = b / (BY * BZ), by = (b / BZ) % BY, bz = b % BZ;
+        const int i = clampi(q.i0 - 2 + bx, 0, p.nx - 1), j = clampi(q.j0 - 2 + by, 0, p.ny - 1);
+        const int k = clampi(q.k0 - 2 + bz, 0, p.ne - 1);
+        const int c = (i * p.ny + j) * p.ne + k;
+#pragma unroll
+        for (int m = 0; m < 10; ++m) nz |= pi[m][c] != 0.0;
+      }
+      any = __syncthreads_or(nz);
+    }
+    if (!any) {
+      const double cv = (double)(RT)p.c_vac;
+      if (p.nx > 1) cfl = fmax(cfl, cv * p.inv_dx);
+      if (p.ny > 1) cfl = fmax(cfl, cv * p.inv_dy);
+      if (p.ne > 1) cfl = fmax(cfl, cv * (p.inv_de / tauf));
+      return cfl;
+    }
+  }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int nd = d == 0 ? p.nx : (d == 1 ? p.ny : p.ne);
     if (nd == 1) continue;  // both faces see identical states: zero divergence
-    constexpr int dummy = 0;
-    (void)dummy;
     const int Td = d == 0 ? TX : (d == 1 ? TY : TZ);
     const int F = (Td + 1) * (N / Td);
     const double inv_del = d == 0 ? p.inv_dx : (d == 1 ? p.inv_dy : p.inv_de / tauf);
@@ -366,12 +528,20 @@ __device__ __forceinline__ double tile_divergence(const double* __restrict__ e,
       if (inrow && ga <= nd) {
         const int base = d == 0 ? (gj * p.ne + gk)
                                 : (d == 1 ? (gi * p.ny) * p.ne + gk : (gi * p.ny + gj) * p.ne);
-        const RT c = face_flux<RT, DO_T, DO_PI, PI_SRC>(e, u, pi, base, ga - 1, nd, stride, d + 1,
+        // stage 1 (pi~ masked by e): the streamed evaluation (fewer registers);
+        // stage 2 (as-stored pi~): all loads at once with the per-face e/pi~ test
+        RT c;
+        if constexpr (PI_SRC == 2)
+          c = face_flux_all<RT, DO_T, DO_PI, PI_SRC>(e, u, pi, base, ga - 1, nd, stride, d + 1,
+                                                     (RT)tauf, p, eos, lds + f, F);
+        else
+          c = face_flux_stream<RT, DO_T, DO_PI, PI_SRC>(e, u, pi, base, ga - 1, nd, stride, d + 1,
                                                         (RT)tauf, p, eos, lds + f, F);
         cfl = fmax(cfl, (double)c * inv_del);
       } else {
 #pragma unroll
-        for (int k = 0; k < 14; ++k) lds[k * F + f] = RT(0);
+        for (int k = 0; k < 14; ++k)
+          if (k < 4 ? DO_T : DO_PI) lds[k * F + f] = RT(0);
       }
     }
     __syncthreads();
@@ -389,7 +559,8 @@ __device__ __forceinline__ double tile_divergence(const double* __restrict__ e,
       }
       const RT rinv = (RT)inv_del;
 #pragma unroll
-      for (int k = 0; k < 14; ++k) R[k] -= (double)((lds[k * F + fp] - lds[k * F + fm]) * rinv);
+      for (int k = 0; k < 14; ++k)  // only the components this pass evaluates
+        if (k < 4 ? DO_T : DO_PI) R[k] -= (double)((lds[k * F + fp] - lds[k * F + fm]) * rinv);
     }
     __syncthreads();
   }
