@@ -104,11 +104,26 @@ struct Ctx {
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Workgroups are dispatched to the 8 XCDs round robin (block b -> XCD b % 8).
-// Give XCD x a contiguous range of tile ids so neighbouring tiles share its L2.
+// Tiles are dealt to the XCDs in chunks of KTMI_CHUNK consecutive tile ids
+// (chunk j -> XCD j % 8): inside a chunk consecutive tiles (eta, then y
+// neighbours) share one XCD's L2, and every XCD gets chunks from all over the
+// grid, so a grid whose matter sits in the middle (most heavy-ion events) loads
+// the XCDs evenly.  The last nb % (8 KTMI_CHUNK) tiles map one to one.
+#ifndef KTMI_CHUNK
+#define KTMI_CHUNK 64
+#endif
 __device__ __forceinline__ int tile_of_block(int nb) {
   const int b = blockIdx.x, x = b & 7, k = b >> 3;
+#if KTMI_CHUNK > 0
+  constexpr int C = KTMI_CHUNK;
+  const int K0 = (nb / (8 * C)) * C;  // blocks per XCD inside whole rounds of chunks
+  if (k < K0) return ((k / C) * 8 + x) * C + k % C;
+  return b;
+#else
+  // contiguous range of tile ids per XCD
   const int per = nb >> 3, rem = nb & 7;
   return x * per + (x < rem ? x : rem) + k;
+#endif
 }
 
 // Starting point of the root solve of K = (E, K1, K2, K3): the previous
