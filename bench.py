@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--tile", type=int, default=-1, help="tile shape index (-1: library default)")
     ap.add_argument("--precision", type=int, default=0,
                     help="0: plain FP64; 1: mixed (FP32 flux/relaxation, FP64 root solve and sources)")
+    ap.add_argument("--quiet-skip", action="store_true",
+                    help="skip tiles whose neighbourhood stayed vacuum (bitwise identical results)")
     ap.add_argument("--guess", default="prev", choices=["prev", "mlp"],
                     help="root-solve start for batch64: previous stage, or a network trained "
                          "first on harvested states (GPU training kernels)")
@@ -116,6 +118,8 @@ def main():
     stream = torch.cuda.Stream() if args.graph else None
     g = K.Hydro(tile=args.tile, precision=args.precision, stream=stream, **p)
     g.set_eos(wl.eos)
+    if args.quiet_skip:
+        g.set_quiet_skip(True)
 
     def initial():
         if wl.T4 is not None:
@@ -175,7 +179,8 @@ def main():
                    "dx": p["dx"], "deta": p["de"], "tau0": p["tau0"], "h": p["h"],
                    "eta_over_s": p["etas"], "ic": wl.note or "200 Gaussian hotspots, seed 1",
                    "eos": "1555-row synthetic crossover table",
-                   "path": "plain FP64" if args.precision == 0 else "mixed FP32/FP64"},
+                   "path": ("plain FP64" if args.precision == 0 else "mixed FP32/FP64") +
+                           (", quiet tiles skipped" if args.quiet_skip else "")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic(wl.name, dom) if args.precision == 0 else None),
@@ -196,6 +201,7 @@ def main():
         del g
         torch.cuda.synchronize()
         out["paths"] = {"mixed_fp32_fp64": mixed_path(wl, args)}
+        out["paths"]["fp64_quiet_skip"] = mixed_path(wl, args, precision=0, quiet=True)
         b = bench_batch(args, precision=1, learned=True, steps=10, warmup=2)
         out["paths"]["batch64_mixed_learned"] = {
             k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "newton_mean", "training")}
@@ -205,15 +211,19 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def mixed_path(wl, args):
+def mixed_path(wl, args, precision=1, quiet=False):
     """The same workload with FP32 reconstruction, fluxes and relaxation source
-    (FP64 root solve, geometric source and state); errors against the FP64
-    oracle are bounded by the GPU tests (<= 1e-6 in e and u~)."""
+    (FP64 root solve, geometric source and state; errors against the FP64
+    oracle are bounded by the GPU tests, <= 1e-6 in e and u~), or (precision 0,
+    quiet) in FP64 with quiet tiles skipped (fields and diagnostics identical to
+    the full computation bit for bit, tested)."""
     import torch
 
     import paper_1802_04449_amd as K
-    g = K.Hydro(precision=K.KTMI_MIXED, **wl.params)
+    g = K.Hydro(precision=precision, **wl.params)
     g.set_eos(wl.eos)
+    if quiet:
+        g.set_quiet_skip(True)
     if wl.T4 is not None:
         g.set_initial_conserved(wl.T4)
     else:
@@ -224,8 +234,11 @@ def mixed_path(wl, args):
     g.step(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"value": wl.ncell * args.steps / dt, "unit": "cell-updates/s",
-            "ms_per_step": dt / args.steps * 1e3, "steps": args.steps}
+    out = {"value": wl.ncell * args.steps / dt, "unit": "cell-updates/s",
+           "ms_per_step": dt / args.steps * 1e3, "steps": args.steps}
+    if quiet:
+        out["quiet_tiles"], out["tiles"] = K.ktmi_quiet_tiles(g.h)
+    return out
 
 
 def train_guess(wls, steps_at=(0, 5, 10), train_steps=1500):

@@ -175,6 +175,22 @@ int ktmi_get_tile(const ktmi_handle *h);
  * stream. */
 int ktmi_set_graph(ktmi_handle *h, int on);
 
+/* Quiet-tile skipping (off by default; not part of the paper's method).  A
+ * tile whose cells were vacuum before and after the last step (e = 0 before,
+ * after stage 1 and after the step, pi~ = 0 after stage 1 and after the step,
+ * K^tau below the cutoff) is quiet; a step skips every tile whose neighbours
+ * within 6 cells are all quiet, because each pass would rewrite exactly the
+ * values its buffers hold (zero fluxes, zero sources, T~ unchanged).  Fields
+ * and diagnostics equal those of the full computation bit for bit.  Needs an
+ * EoS with P(0) = 0 (KTMI_ESTATE otherwise, also when a later table breaks
+ * it).  Turning it on or off, or changing the tile shape, marks every tile
+ * as not quiet, so the next step computes all of them.  A group uses the
+ * setting its members had when it was created. */
+int ktmi_set_quiet_skip(ktmi_handle *h, int on);
+
+/* Number of quiet tiles after the last step, and of tiles.  Synchronizes. */
+int ktmi_quiet_tiles(ktmi_handle *h, long *quiet, long *total);
+
 /* Groups: step many events (possibly of different grids and modes) together.
  * Events are sorted into classes of equal (viscous, precision, tile); per class
  * and stage a single launch covers the tiles of all its events (at most 128 per

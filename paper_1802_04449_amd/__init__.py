@@ -85,6 +85,8 @@ def _load():
         "ktmi_mlp_nparam": (C.c_int, []),
         "ktmi_set_mlp": (C.c_int, [vp, vp, C.c_int]),
         "ktmi_set_guess": (C.c_int, [vp, C.c_int]),
+        "ktmi_set_quiet_skip": (C.c_int, [vp, C.c_int]),
+        "ktmi_quiet_tiles": (C.c_int, [vp, C.POINTER(C.c_long), C.POINTER(C.c_long)]),
         "ktmi_harvest": (C.c_int, [vp, vp, vp, vp]),
         "ktmi_mlp_forward": (C.c_int, [vp, C.c_int, vp, vp, C.c_double, vp, C.c_int, vp]),
         "ktmi_mlp_grad_workspace_bytes": (sz, [C.c_int]),
@@ -254,6 +256,16 @@ def ktmi_set_guess(h, guess: int):
     _check(lib.ktmi_set_guess(h, int(guess)), h)
 
 
+def ktmi_set_quiet_skip(h, on: bool):
+    _check(lib.ktmi_set_quiet_skip(h, int(bool(on))), h)
+
+
+def ktmi_quiet_tiles(h):
+    q, t = C.c_long(), C.c_long()
+    _check(lib.ktmi_quiet_tiles(h, C.byref(q), C.byref(t)), h)
+    return q.value, t.value
+
+
 def ktmi_harvest(h, E_ptr: int, M_ptr: int, eps_ptr: int):
     _check(lib.ktmi_harvest(h, C.c_void_p(E_ptr), C.c_void_p(M_ptr), C.c_void_p(eps_ptr)), h)
 
@@ -379,6 +391,9 @@ class Hydro:
 
     def set_guess(self, guess):
         ktmi_set_guess(self.h, guess)
+
+    def set_quiet_skip(self, on=True):
+        ktmi_set_quiet_skip(self.h, on)
 
     def harvest(self):
         """(E, M, eps) of every cell of the current state, device tensors."""

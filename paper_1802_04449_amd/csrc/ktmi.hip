@@ -203,6 +203,9 @@ struct ktmi_handle {
   // learned root-solve guess: parameters copied into the workspace
   float* mlp_dev = nullptr;
   bool mlp_ok = false;
+  // quiet-tile skipping (off by default); P of the EoS at e = 0 (must be 0 for it)
+  bool quiet_on = false;
+  double eos_p0 = 0.0;
   int mlp_mode = KTMI_MLP_FP32;
 };
 
@@ -303,6 +306,11 @@ static int max_tiles(const ktmi_desc* d) {
   return m;
 }
 
+// Doubles reserved for the quiet-tile flags: 3 ints per tile of the largest grid.
+static size_t quiet_doubles(const ktmi_desc* d) {
+  return ((size_t)3 * max_tiles(d) + 63) / 64 * 32;
+}
+
 static const int kNumFields = 39;  // e, u(3), up(3), pi(10), T(4), e1, u1(3), pi1(10), T1(4)
 
 static size_t field_stride(const ktmi_desc* d) {
@@ -337,6 +345,9 @@ static StepParams step_params(const ktmi_handle* h) {
   p.newton_tol = h->d.newton_tol;
   p.pi_reg = h->d.pi_reg;
   p.newton_maxit = h->d.newton_maxit;
+  // quiet tiles: neighbourhood radius in tiles covering 6 cells per axis
+  const int td[3] = {kTiles[h->tile].tx, kTiles[h->tile].ty, kTiles[h->tile].tz};
+  for (int a = 0; a < 3; ++a) p.quiet_r[a] = h->quiet_on ? (6 + td[a] - 1) / td[a] : 0;
   p.guess = h->d.guess;
   p.mlp_mfma = h->mlp_mode == KTMI_MLP_BF16;
   p.mlp = h->mlp_ok ? h->mlp_dev : nullptr;
@@ -461,6 +472,16 @@ static int enqueue_step(ktmi_handle* h) {
   });
 }
 
+// Marks every tile as not quiet (the next step computes them all).
+static int clear_quiet(ktmi_handle* h) {
+  if (!h->bound) return KTMI_OK;
+  const int n = (int)quiet_doubles(&h->d);
+  hipLaunchKernelGGL(k_zero, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, h->stream,
+                     (double*)h->f.quiet, n);
+  HIP_TRY(h, hipGetLastError());
+  return KTMI_OK;
+}
+
 static int finish_initial(ktmi_handle* h) {
   if (int rc = upload_event(h)) return rc;
   hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, h->stream, h->clock, h->tau);
@@ -473,6 +494,7 @@ static int finish_initial(ktmi_handle* h) {
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, h->stream, h->f.acc, 32);
   });
   if (rc) return rc;
+  if (int rc2 = clear_quiet(h)) return rc2;
   h->step = 0;
   h->ready = true;
   return KTMI_OK;
@@ -556,6 +578,7 @@ size_t ktmi_workspace_bytes(const ktmi_desc* d) {
   size_t bytes = (size_t)kNumFields * fs * sizeof(double);
   bytes += ((2 * nb * kNP + 31) / 32 * 32) * sizeof(double);  // partials
   bytes += 32 * sizeof(double);                               // accumulators
+  bytes += quiet_doubles(d) * sizeof(double);                 // quiet-tile flags
   bytes += 3 * (size_t)kEosMaxRows * sizeof(double);          // EoS table
   bytes += 3 * (size_t)kEosMaxRows * sizeof(float);           // its FP32 copy
   bytes += 4096 + 512;                                         // event table, clock
@@ -615,6 +638,8 @@ int ktmi_bind(ktmi_handle* h, void* ws, size_t bytes, void* stream) {
   rest += (2 * (size_t)max_tiles(&h->d) * kNP + 31) / 32 * 32;
   f.acc = rest;
   rest += 32;
+  f.quiet = (int*)rest;  // 3 x max tiles flags
+  rest += quiet_doubles(&h->d);
   h->eos_store = rest;
   rest += 3 * (size_t)kEosMaxRows;                       // FP64 table
   rest += (3 * (size_t)kEosMaxRows * sizeof(float) + 7) / 8;  // FP32 copy
@@ -636,6 +661,7 @@ int ktmi_set_eos_conformal(ktmi_handle* h, double c_sb) {
   h->eos.inv_csb = 1.0 / c_sb;
   h->eos.inv_csb_f = (float)(1.0 / c_sb);
   h->cs2_vac = 1.0 / 3.0;
+  h->eos_p0 = 0.0;
   h->eos_set = true;
   h->ev_dirty = true;
   return KTMI_OK;
@@ -648,6 +674,9 @@ int ktmi_set_eos_table(ktmi_handle* h, double e0, double de, int n, const double
   if (n < 2 || n > kEosMaxRows) return fail(h, KTMI_EINVAL, "table rows must be in [2, 8192]");
   if (!(de > 0)) return fail(h, KTMI_EINVAL, "de must be > 0");
   if (!P || !T || !cs2) return fail(h, KTMI_EINVAL, "null table column");
+  const double p0 = e0 == 0.0 ? P[0] : NAN;  // P at e = 0
+  if (h->quiet_on && p0 != 0.0)
+    return fail(h, KTMI_ESTATE, "quiet-tile skipping needs P(0) = 0: turn it off first");
   double* dP = h->eos_store;
   double* dT = dP + kEosMaxRows;
   double* dC = dT + kEosMaxRows;
@@ -681,6 +710,7 @@ int ktmi_set_eos_table(ktmi_handle* h, double e0, double de, int n, const double
   h->eos.de = de;
   h->eos.inv_de = 1.0 / de;
   h->cs2_vac = cs2[0];  // lookups clamp e = 0 to the first row
+  h->eos_p0 = p0;
   h->eos.P = dP;
   h->eos.T = dT;
   h->eos.cs2 = dC;
@@ -932,7 +962,33 @@ int ktmi_set_tile(ktmi_handle* h, int t) {
   h->tile = t < 0 ? auto_tile(&h->d) : t;
   h->tg = tile_grid(&h->d, h->tile);
   h->ev_dirty = true;
+  return clear_quiet(h);  // flags are per tile of the old shape
+}
+
+int ktmi_quiet_tiles(ktmi_handle* h, long* quiet, long* total) {
+  if (!h || !quiet || !total) return KTMI_EINVAL;
+  if (!h->ready) return fail(h, KTMI_ESTATE, "no state");
+  const int nt = h->tg.ntiles;
+  std::vector<int> flags(nt);
+  // the step with clock parity p writes flag buffer 1 - p: after an odd number
+  // of steps the latest flags are in buffer 1
+  const int* src = h->f.quiet + ((h->step & 1) ? nt : 0);
+  HIP_TRY(h, hipMemcpyAsync(flags.data(), src, sizeof(int) * nt, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  long n = 0;
+  for (int v : flags) n += v != 0;
+  *quiet = n;
+  *total = nt;
   return KTMI_OK;
+}
+
+int ktmi_set_quiet_skip(ktmi_handle* h, int on) {
+  if (!h) return KTMI_EINVAL;
+  if (on && h->eos_p0 != 0.0)
+    return fail(h, KTMI_ESTATE, "quiet-tile skipping needs an EoS with P(0) = 0");
+  h->quiet_on = on != 0;
+  h->ev_dirty = true;
+  return clear_quiet(h);
 }
 
 size_t ktmi_group_workspace_bytes(int nev) {

@@ -20,6 +20,7 @@ struct StepParams {
   double eps_cut, theta, newton_tol, pi_reg;
   double c_vac;  // local speed of a vacuum state, sqrt(cs2(0))
   int newton_maxit;
+  int quiet_r[3];          // quiet-tile skipping: neighbourhood radius in tiles (0: off)
   int guess;               // root-solve start: 0 previous stage, 1 cold (E), 2 network
   int mlp_mfma;            // network forward: 0 FP32 per lane, 1 BF16 matrix cores per wave
   const float* mlp;        // network parameters (FP32), then W2 as BF16

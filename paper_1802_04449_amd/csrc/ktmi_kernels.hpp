@@ -56,6 +56,7 @@ struct Fields {
   double* T1[4];
   double* partial;  // [2][kNP][nblk]: stage1 then stage2T, slot-major
   double* acc;      // [16] accumulated diagnostics
+  int* quiet;       // [3][ntiles]: quiet flags by clock parity (2), stage-2pi part (1)
 };
 
 struct Geo {
@@ -99,6 +100,9 @@ struct Ctx {
   TileGrid tg;
   Geo g;
   int tile;  // tile index inside the event
+  const int* qcur;  // quiet flags after the previous step
+  int* qnext;       // quiet flags after this step
+  int* qpi;         // this step's stage-2pi part of the flags
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -180,6 +184,10 @@ __device__ __forceinline__ Ctx load_ctx(const EventDesc* __restrict__ evs, const
   c.g.tau1 = tau + E.p.h;
   c.g.tau = stage2 ? c.g.tau1 : tau;
   c.tile = t - gt.start[e];
+  const int nt = E.tg.ntiles;
+  c.qcur = E.f.quiet + (odd ? nt : 0);
+  c.qnext = E.f.quiet + (odd ? 0 : nt);
+  c.qpi = E.f.quiet + 2 * nt;
   return c;
 }
 
@@ -201,6 +209,42 @@ __device__ __forceinline__ Pos cell_pos(const StepParams& p, const TileGrid& tg,
   q.active = tid < TX * TY * TZ && q.i < p.nx && q.j < p.ny && q.k < p.ne;
   q.c = (q.i * p.ny + q.j) * p.ne + q.k;
   return q;
+}
+
+// Quiet tiles (optional, StepParams::quiet_r[0] > 0).  A tile is quiet after a
+// step when every cell had e = 0 before the step, after stage 1 and after it,
+// pi~ = 0 after stage 1 and after it, and K^tau below the cutoff: its state is
+// a vacuum with at most a dilute T~ that no flux or source changes.  A step can
+// skip a tile (no loads, no stores) when every tile within quiet_r tiles
+// (6 cells: the reach of stage 1 and stage 2 stencils and gradients) was
+// quiet after the previous step: all three passes would then reproduce exactly
+// the values its buffers hold.  Returns the block-uniform decision.
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ bool tile_asleep(const StepParams& p, const TileGrid& tg,
+                                            const int* __restrict__ qcur, int tile) {
+  if (p.quiet_r[0] <= 0) return false;
+  const int tk = tile % tg.ntz, r = tile / tg.ntz;
+  const int tj = r % tg.nty, ti = r / tg.nty;
+  const int rx = p.quiet_r[0], ry = p.quiet_r[1], rz = p.quiet_r[2];
+  const int wx = 2 * rx + 1, wy = 2 * ry + 1, wz = 2 * rz + 1;
+  int awake = 0;
+  for (int n = threadIdx.x; n < wx * wy * wz; n += kBlock) {
+    const int a = ti - rx + n / (wy * wz), b = tj - ry + (n / wz) % wy, c = tk - rz + n % wz;
+    if (a < 0 || a >= tg.ntx || b < 0 || b >= tg.nty || c < 0 || c >= tg.ntz) continue;
+    awake |= qcur[(a * tg.nty + b) * tg.ntz + c] == 0;
+  }
+  return __syncthreads_or(awake) == 0;
+}
+
+// Max over the tile's faces of c / Delta when every face is a vacuum face.
+template <typename RT>
+__device__ __forceinline__ double vacuum_cfl(const StepParams& p, double tauf) {
+  const double cv = (double)(RT)p.c_vac;
+  double cfl = 0.0;
+  if (p.nx > 1) cfl = fmax(cfl, cv * p.inv_dx);
+  if (p.ny > 1) cfl = fmax(cfl, cv * p.inv_dy);
+  if (p.ne > 1) cfl = fmax(cfl, cv * (p.inv_de / tauf));
+  return cfl;
 }
 
 // pi~ at a cell: PI_SRC 0 -> 0, 1 -> zero where e == 0 (vacuum), 2 -> as stored.
@@ -504,13 +548,7 @@ __device__ __forceinline__ double tile_divergence(const double* __restrict__ e,
       }
       any = __syncthreads_or(nz);
     }
-    if (!any) {
-      const double cv = (double)(RT)p.c_vac;
-      if (p.nx > 1) cfl = fmax(cfl, cv * p.inv_dx);
-      if (p.ny > 1) cfl = fmax(cfl, cv * p.inv_dy);
-      if (p.ne > 1) cfl = fmax(cfl, cv * (p.inv_de / tauf));
-      return cfl;
-    }
+    if (!any) return vacuum_cfl<RT>(p, tauf);
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -851,6 +889,11 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
 #pragma unroll
   for (int s = 0; s < kNP; ++s) v[s] = 0.0;
   const double tf = g.cart ? 1.0 : g.tau;
+  if (tile_asleep<TX, TY, TZ>(p, cx.tg, cx.qcur, cx.tile)) {
+    v[P_CFL] = vacuum_cfl<RT>(p, tf) * p.h;  // what the vacuum faces would give
+    block_partials(v, f.partial, cx.tg.ntiles, cx.tile);
+    return;
+  }
   double R[14];
   const double cfl =
       tile_divergence<RT, TX, TY, TZ, true, VISC, VISC ? 1 : 0>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
@@ -929,35 +972,45 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ>()))) void k_stage2_p
   const EosDev& eos = cx.eos;
   const Geo& g = cx.g;
   const Pos q = cell_pos<TX, TY, TZ>(p, cx.tg, cx.tile);
+  if (tile_asleep<TX, TY, TZ>(p, cx.tg, cx.qcur, cx.tile)) return;
   const double tf = g.cart ? 1.0 : g.tau;
   double R[14];
   tile_divergence<RT, TX, TY, TZ, false, true, 2>(f.e1, f.u1, f.pi1, p, eos, tf, q, R, lds);
-  if (!q.active) return;
-  const int c = q.c;
-  const double e1 = f.e1[c];
-  double pc[10];
+  bool quiet = true;  // this cell's part of the quiet-tile test
+  if (q.active) {
+    const int c = q.c;
+    const double e1 = f.e1[c];
+    double pc[10];
 #pragma unroll
-  for (int m = 0; m < 10; ++m) pc[m] = f.pi1[m][c];
-  if (e1 >= p.eps_cut) {
-    double S[10];
-    pi_source<RT>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
+    for (int m = 0; m < 10; ++m) pc[m] = f.pi1[m][c];
+    if (e1 >= p.eps_cut) {
+      double S[10];
+      pi_source<RT>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
 #pragma unroll
-    for (int m = 0; m < 10; ++m) R[4 + m] += S[m];
+      for (int m = 0; m < 10; ++m) R[4 + m] += S[m];
+    }
+    const double en = f.e[c];
+    const double a1 = f.u[0][c], a2 = f.u[1][c], a3 = f.u[2][c];
+    const double utn = utau(a1, a2, a3);
+    const double uts = utau(2.0 * a1 - f.up[0][c], 2.0 * a2 - f.up[1][c], 2.0 * a3 - f.up[2][c]);
+    const double inv_ut1 = 1.0 / utau(f.u1[0][c], f.u1[1][c], f.u1[2][c]);
+    double pn[10];
+#pragma unroll
+    for (int m = 0; m < 10; ++m) {
+      const double pin = en == 0.0 ? 0.0 : f.pi[m][c];
+      pn[m] = (0.5 * (utn * pin + uts * pc[m]) + 0.5 * p.h * R[4 + m]) * inv_ut1;
+    }
+    regulate(eos, p, e1, pn);
+#pragma unroll
+    for (int m = 0; m < 10; ++m) f.pi[m][c] = pn[m];
+    quiet = en == 0.0 && e1 == 0.0;
+#pragma unroll
+    for (int m = 0; m < 10; ++m) quiet = quiet && pc[m] == 0.0 && pn[m] == 0.0;
   }
-  const double en = f.e[c];
-  const double a1 = f.u[0][c], a2 = f.u[1][c], a3 = f.u[2][c];
-  const double utn = utau(a1, a2, a3);
-  const double uts = utau(2.0 * a1 - f.up[0][c], 2.0 * a2 - f.up[1][c], 2.0 * a3 - f.up[2][c]);
-  const double inv_ut1 = 1.0 / utau(f.u1[0][c], f.u1[1][c], f.u1[2][c]);
-  double pn[10];
-#pragma unroll
-  for (int m = 0; m < 10; ++m) {
-    const double pin = en == 0.0 ? 0.0 : f.pi[m][c];
-    pn[m] = (0.5 * (utn * pin + uts * pc[m]) + 0.5 * p.h * R[4 + m]) * inv_ut1;
+  if (p.quiet_r[0] > 0) {
+    const int all = __syncthreads_and(quiet);
+    if (threadIdx.x == 0) cx.qpi[cx.tile] = all;
   }
-  regulate(eos, p, e1, pn);
-#pragma unroll
-  for (int m = 0; m < 10; ++m) f.pi[m][c] = pn[m];
 }
 
 // Stage 2, part 2 (tau_{n+1}): T^{n+1} = T^n + [(T' - T^n) + h R_T(e', u', pi^{n+1})]/2,
@@ -976,6 +1029,17 @@ __global__ __launch_bounds__(kBlock) void k_stage2_T(const EventDesc* __restrict
 #pragma unroll
   for (int s = 0; s < kNP; ++s) v[s] = 0.0;
   const double tf = g.cart ? 1.0 : g.tau;
+  if (tile_asleep<TX, TY, TZ>(p, cx.tg, cx.qcur, cx.tile)) {
+    // the diagnostics the vacuum cells would give; T~ is unchanged
+    v[P_CFL] = vacuum_cfl<RT>(p, tf) * p.h;
+    if (q.active) {
+      v[P_TSUM] = f.T[0][q.c];
+      v[P_VAC] = 1.0;
+    }
+    block_partials(v, f.partial + (size_t)kNP * cx.tg.ntiles, cx.tg.ntiles, cx.tile);
+    if (threadIdx.x == 0) cx.qnext[cx.tile] = 1;
+    return;
+  }
   double R[14];
   const double cfl = tile_divergence<RT, TX, TY, TZ, true, false, VISC ? 2 : 0>(f.e1, f.u1, f.pi, p,
                                                                           eos, tf, q, R, lds);
@@ -1011,17 +1075,25 @@ __global__ __launch_bounds__(kBlock) void k_stage2_T(const EventDesc* __restrict
     v[P_TSUM] = Tn[0];
   }
   const double x0 = root_guess<NET>(p, q.active, K[0], K[1], K[2], K[3], prev);
+  bool quiet = true;  // this cell's part of the quiet-tile test
   if (q.active) {
     const int c = q.c;
     int it, fl;
     const Prim s = con2prim(eos, p, K[0], K[1], K[2], K[3], x0, it, fl);
     count_solve(v, it, fl);
+    if (p.quiet_r[0] > 0)  // e before and after stage 1 (viscous: tested in stage2pi)
+      quiet = VISC || (f.e[c] == 0.0 && prev == 0.0);
+    quiet = quiet && s.e == 0.0 && !(K[0] >= p.eps_cut);
     f.e[c] = s.e;
     f.up[0][c] = s.u1;  // becomes u~^{n+1} after the host swaps u and up
     f.up[1][c] = s.u2;
     f.up[2][c] = s.u3;
     v[P_EMAX] = s.e;
     v[P_VAC] = s.e == 0.0 ? 1.0 : 0.0;
+  }
+  if (p.quiet_r[0] > 0) {
+    const int all = __syncthreads_and(quiet);
+    if (threadIdx.x == 0) cx.qnext[cx.tile] = all && (!VISC || cx.qpi[cx.tile]);
   }
   block_partials(v, f.partial + (size_t)kNP * cx.tg.ntiles, cx.tg.ntiles, cx.tile);
 }
