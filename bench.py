@@ -87,8 +87,8 @@ def main():
     ap.add_argument("--quiet-skip", action="store_true",
                     help="skip tiles whose neighbourhood stayed vacuum (bitwise identical results)")
     ap.add_argument("--guess", default="prev", choices=["prev", "mlp"],
-                    help="root-solve start for batch64: previous stage, or a network trained "
-                         "first on harvested states (GPU training kernels)")
+                    help="root-solve start: previous stage, or a network trained first on states "
+                         "harvested from the same workload (GPU training kernels)")
     ap.add_argument("--no-paths", action="store_true",
                     help="skip the extra measurements: the same workload in mixed precision, and "
                          "the 64-event batch with mixed precision and the learned guess")
@@ -116,8 +116,14 @@ def main():
           "large": W.large_event}[args.workload](steps=args.steps)
     p = wl.params
     stream = torch.cuda.Stream() if args.graph else None
-    g = K.Hydro(tile=args.tile, precision=args.precision, stream=stream, **p)
+    train = None
+    if args.guess == "mlp":
+        params, train = train_guess([wl])
+    g = K.Hydro(tile=args.tile, precision=args.precision, stream=stream,
+                guess=K.KTMI_GUESS_MLP if args.guess == "mlp" else K.KTMI_GUESS_PREV, **p)
     g.set_eos(wl.eos)
+    if args.guess == "mlp":
+        g.set_mlp(params, K.KTMI_MLP_BF16)
     if args.quiet_skip:
         g.set_quiet_skip(True)
 
@@ -180,7 +186,8 @@ def main():
                    "eta_over_s": p["etas"], "ic": wl.note or "200 Gaussian hotspots, seed 1",
                    "eos": "1555-row synthetic crossover table",
                    "path": ("plain FP64" if args.precision == 0 else "mixed FP32/FP64") +
-                           (", quiet tiles skipped" if args.quiet_skip else "")},
+                           (", quiet tiles skipped" if args.quiet_skip else "") +
+                           (", learned guess (BF16 forward)" if args.guess == "mlp" else "")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic(wl.name, dom) if args.precision == 0 else None),
@@ -197,7 +204,9 @@ def main():
                     "paper_hardware": "AMD FirePro S9150, 385x385x115 cells"},
     }
     out["graph"] = bool(args.graph)
-    if args.precision == 0 and not args.no_paths:
+    if train:
+        out["training"] = train
+    if args.precision == 0 and not args.no_paths and args.guess == "prev" and not args.quiet_skip:
         del g
         torch.cuda.synchronize()
         out["paths"] = {"mixed_fp32_fp64": mixed_path(wl, args)}
@@ -264,7 +273,8 @@ def train_guess(wls, steps_at=(0, 5, 10), train_steps=1500):
     tr.train(train_steps, batch=4096)
     dt = time.perf_counter() - t0
     return tr.params, {"samples": int(E.size), "adam_steps": train_steps, "loss_initial": loss0,
-                       "loss_final": tr.loss(), "train_s": dt}
+                       "loss_final": tr.loss(), "train_s": dt,
+                       "harvested_from": [f"{w.name} at steps {list(steps_at)}" for w in wls]}
 
 
 def bench_batch(args, precision=None, learned=False, steps=None, warmup=None):
