@@ -92,6 +92,64 @@ def gubser_ideal(g: Grid, tau: float, q: float = 1.0, T_peak: float = 0.4):
 
 
 # --------------------------------------------------------------------------
+# Gubser flow of second-order viscous hydrodynamics, Sec. V.C.
+# --------------------------------------------------------------------------
+def gubser_viscous_taupi_coef(lambda1_hat: float) -> float:
+    """tau_pi coefficient b (tau_pi = b (eta/s) hbarc / T) that meets the solution's
+    condition eta^ lambda1^2 = 3 tau_pi^ for the conformal gas: there
+    eta^ = (4/3)(eta/s) hbarc c_SB^(1/4) and tau_pi^ = b (eta/s) hbarc c_SB^(1/4),
+    so b = 4 lambda1_hat^2 / 9, whatever eta/s and c_SB are."""
+    return 4.0 * lambda1_hat * lambda1_hat / 9.0
+
+
+def gubser_viscous_profile(x, y, tau, L, lambda1_hat, eps_hat0):
+    """Closed form at proper time tau (conformal EoS; L in fm).
+
+    In the de Sitter frame the solution is eps^ = eps_hat0 cosh(rho)^-k with
+    k = 8/3 - 2/lambda1_hat, u^ = (1, 0, 0, 0) and pi^^{eta eta} = C = (2/lambda1_hat) eps^,
+    A = B = -C/2.  Mapped back (eps = eps^/tau^4, pi_{mu nu} = tau^-2 dx^/dx dx^/dx pi^),
+    with Q = L^4 + 2 L^2 (tau^2 + r^2) + (tau^2 - r^2)^2 = (2 L tau cosh rho)^2:
+      pi~^{tau tau} = 4 A r^2 / (tau^2 Q),  pi~^{tau i} = 2 A x_i (L^2 + tau^2 + r^2) / (tau^3 Q),
+      pi~^{ij} = A delta_ij / tau^4 + 4 A x_i x_j / (tau^2 Q),  pi~^{eta eta} = -2 A / tau^4,
+    the other components zero; the velocity is the ideal one,
+    v_r = 2 tau r / (L^2 + tau^2 + r^2).  eps_hat0 carries units GeV fm.
+    Returns (eps, u~x, u~y, pi10) in the pi~ order of this module."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    r2 = x * x + y * y
+    Q = L ** 4 + 2.0 * L * L * (tau * tau + r2) + (tau * tau - r2) ** 2
+    cosh_rho = np.sqrt(Q) / (2.0 * L * tau)
+    k = 8.0 / 3.0 - 2.0 / lambda1_hat
+    eps_hat = eps_hat0 * cosh_rho ** (-k)
+    eps = eps_hat / tau ** 4
+    A = -eps_hat / lambda1_hat  # A = -C/2, C = 2 eps^/lambda1_hat
+    S = L * L + tau * tau + r2
+    vx = 2.0 * tau * x / S
+    vy = 2.0 * tau * y / S
+    ut = 1.0 / np.sqrt(1.0 - vx * vx - vy * vy)
+    pi = np.zeros((10,) + np.shape(eps), dtype=np.float64)
+    pi[0] = 4.0 * A * r2 / (tau * tau * Q)
+    pi[1] = 2.0 * A * x * S / (tau ** 3 * Q)
+    pi[2] = 2.0 * A * y * S / (tau ** 3 * Q)
+    pi[4] = A / tau ** 4 + 4.0 * A * x * x / (tau * tau * Q)
+    pi[5] = 4.0 * A * x * y / (tau * tau * Q)
+    pi[7] = A / tau ** 4 + 4.0 * A * y * y / (tau * tau * Q)
+    pi[9] = -2.0 * A / tau ** 4
+    return eps, ut * vx, ut * vy, pi
+
+
+def gubser_viscous(g: Grid, tau: float, L: float = 2.0, lambda1_hat: float = -10.0,
+                   T_peak: float = 0.4):
+    """Viscous Gubser state on grid g at proper time tau, normalised so that the
+    temperature at r = 0 is T_peak at tau = 1 fm (conformal EoS)."""
+    X, Y, _ = g.mesh()
+    e1, _, _, _ = gubser_viscous_profile(0.0, 0.0, 1.0, L, lambda1_hat, 1.0)
+    eps_hat0 = C_SB * T_peak ** 4 / float(e1)
+    eps, ux, uy, pi = gubser_viscous_profile(X, Y, tau, L, lambda1_hat, eps_hat0)
+    return dict(eps=eps, ux=ux, uy=uy, ue=_zeros(g), pi=pi)
+
+
+# --------------------------------------------------------------------------
 # Bjorken flow, Sec. V.B: uniform in (x, y, eta_s), u~ = (1, 0, 0, 0).
 # --------------------------------------------------------------------------
 def bjorken(g: Grid, eps0: float, phi0: float = 0.0):

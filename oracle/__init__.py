@@ -27,7 +27,8 @@ class _Params(C.Structure):
                 ("tau0", C.c_double), ("h", C.c_double), ("etas", C.c_double),
                 ("viscous", C.c_int), ("cartesian", C.c_int),
                 ("eps_cut", C.c_double), ("theta", C.c_double), ("newton_tol", C.c_double),
-                ("newton_maxit", C.c_int), ("pi_reg", C.c_double)]
+                ("newton_maxit", C.c_int), ("pi_reg", C.c_double),
+                ("taupi_coef", C.c_double), ("lambda1_hat", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -119,11 +120,14 @@ class Params:
     newton_tol: float = 1e-12
     newton_maxit: int = 100
     pi_reg: float = 1.0
+    taupi_coef: float = 5.0
+    lambda1_hat: float = 0.0
 
     def c(self):
         return _Params(self.nx, self.ny, self.ne, self.dx, self.dy, self.de, self.tau0, self.h,
                        self.etas, int(self.viscous), int(self.cartesian), self.eps_cut,
-                       self.theta, self.newton_tol, self.newton_maxit, self.pi_reg)
+                       self.theta, self.newton_tol, self.newton_maxit, self.pi_reg,
+                       self.taupi_coef, self.lambda1_hat)
 
 
 class Oracle:

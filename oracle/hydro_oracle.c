@@ -35,7 +35,10 @@
  *  - the first step estimates u*1 by one ideal forward-Euler step and sets
  *    u~^{-1} = 2 u~^0 - u*1;
  *  - cells whose T^{tau tau}-part falls below the cutoff become vacuum
- *    (e = 0, u~ = 0, and pi~ = 0 at the end of the step).
+ *    (e = 0, u~ = 0, and pi~ = 0 at the end of the step);
+ *  - the second-order coefficient lambda_1 of eqn. pimn is lambda1_hat / e, the
+ *    scaling of Sec. V.C (lambda1_hat = 0 gives the equations of Sec. II), and
+ *    tau_pi = taupi_coef (eta/s) hbarc / T with taupi_coef = 5 in Sec. II.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -65,6 +68,8 @@ typedef struct orc_params {
     double eps_cut, theta, newton_tol;
     int newton_maxit;
     double pi_reg; /* cap on sqrt(|pi:pi|)/(e+P); <= 0 disables the regulator */
+    double taupi_coef;  /* tau_pi = taupi_coef (eta/s) hbarc / T; 5 in Sec. II */
+    double lambda1_hat; /* lambda_1 = lambda1_hat / e (Sec. V.C scaling); 0 in Sec. II */
 } orc_params;
 
 typedef struct orc_diag {
@@ -526,9 +531,42 @@ static void shear_parts(const orc *S, double *const u[3], double *const uE[3],
     *theta_out = theta;
 }
 
+/* Second-order term of eqn. pimn: Y^{mu nu} = pi^{<mu}_lambda pi^{nu>lambda}, the
+ * tensor X^{ab} = pi~^{a l} g~_{l l} pi~^{b l} projected with the double projector of
+ * eqn. projector, Delta^{mu nu}_{a b} = 1/2 (Delta^mu_a Delta^nu_b + Delta^mu_b
+ * Delta^nu_a) - 1/3 Delta^{mu nu} Delta_{a b}, Delta^{mu nu} = g~^{mu nu} - u~^mu u~^nu.
+ * Written from the definition term by term (no use of pi's transversality). */
+static void pipi_projected(const double uc[4], double pc[4][4], double Y[4][4]) {
+    double X[4][4], Dm[4][4], Dup[4][4], Dlo[4][4], ul[4];
+    for (int a = 0; a < 4; ++a) ul[a] = GT[a] * uc[a];
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            double x = 0.0;
+            for (int l = 0; l < 4; ++l) x += pc[a][l] * (MUT(20) ? 1.0 : GT[l]) * pc[b][l];
+            X[a][b] = x;
+            Dm[a][b] = (a == b ? 1.0 : 0.0) - uc[a] * ul[b];          /* Delta^a_b   */
+            Dup[a][b] = (a == b ? GT[a] : 0.0) - uc[a] * uc[b];       /* Delta^{ab}  */
+            Dlo[a][b] = (a == b ? GT[a] : 0.0) - ul[a] * ul[b];       /* Delta_{ab}  */
+        }
+    double tr = 0.0; /* Delta_{ab} X^{ab} */
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) tr += Dlo[a][b] * X[a][b];
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu) {
+            double y = 0.0;
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    y += 0.5 * (Dm[mu][a] * Dm[nu][b] + Dm[mu][b] * Dm[nu][a]) * X[a][b];
+            Y[mu][nu] = y - (MUT(18) ? 0.0 : Dup[mu][nu] * tr / 3.0);
+        }
+}
+
 /* Israel-Stewart source S_pi (Sec. II, eqn. pitilde and eqn. Ipi; eqn. pimn with
- * lambda_i = 0; tau_pi = 5 eta_v/(T s), Sec. II).  uE / uL are the earlier and
- * later time levels for d_tau u~; u is the stage's velocity field. */
+ * lambda_2 = lambda_3 = 0).  tau_pi = taupi_coef (eta/s) hbarc / T (5 in Sec. II);
+ * the lambda_1 term enters as -(lambda_1 / tau_pi) pi^{<mu}_lambda pi^{nu>lambda}
+ * with lambda_1 = lambda1_hat / e (lambda1_hat = lambda_1 e is the dimensionless
+ * coefficient of Sec. V.C).  uE / uL are the earlier and later time levels for
+ * d_tau u~; u is the stage's velocity field. */
 static void pi_source(const orc *S, double *const e, double *const u[3],
                       double *const pi[10], double *const uE[3], double *const uL[3],
                       double tau, double *Rpi[10]) {
@@ -547,7 +585,8 @@ static void pi_source(const orc *S, double *const e, double *const u[3],
                 double P, T, cs2, dP;
                 eos_eval(&S->eos, e[id], &P, &T, &cs2, &dP);
                 double etav = S->p.etas * (e[id] + P) * HBARC / T;
-                double taupi = (MUT(15) ? 3.0 : 5.0) * S->p.etas * HBARC / T;
+                double coef = MUT(19) ? 5.0 : S->p.taupi_coef;
+                double taupi = (MUT(15) ? 0.6 : 1.0) * coef * S->p.etas * HBARC / T;
                 double pc[4][4];
                 for (int mu = 0; mu < 4; ++mu)
                     for (int nu = 0; nu < 4; ++nu) pc[mu][nu] = pi[SYM(mu, nu)][id];
@@ -568,9 +607,16 @@ static void pi_source(const orc *S, double *const e, double *const u[3],
                     I[3][2] = I[2][3] = ue * pc[0][2] / tau;
                     I[3][3] = 2.0 * ue * pc[0][3] / tau;
                 }
+                double Y[4][4], lam1 = 0.0;
+                memset(Y, 0, sizeof(Y));
+                if (S->p.lambda1_hat != 0.0) {
+                    pipi_projected(uc, pc, Y);
+                    lam1 = S->p.lambda1_hat / e[id];
+                }
                 for (int mu = 0; mu < 4; ++mu)
                     for (int nu = mu; nu < 4; ++nu) {
                         double s = -(pc[mu][nu] - etav * sg[mu][nu]) / taupi -
+                                   (MUT(17) ? -1.0 : 1.0) * lam1 * Y[mu][nu] / taupi -
                                    pc[mu][nu] * theta / 3.0 -
                                    (MUT(6) ? -1.0 : 1.0) * (uc[mu] * b[nu] + uc[nu] * b[mu]);
                         if (!cart) s += (MUT(2) ? 1.0 : -1.0) * pc[mu][nu] * uc[0] / tau -
@@ -702,6 +748,8 @@ orc *orc_create(const orc_params *p) {
         !(p->de > 0) || !(p->tau0 > 0))
         return NULL;
     if (p->viscous && !(p->etas > 0)) return NULL;
+    if (p->viscous && !(p->taupi_coef > 0)) return NULL;
+    if (!isfinite(p->lambda1_hat)) return NULL;
     orc *S = (orc *)calloc(1, sizeof(orc));
     S->p = *p;
     S->NX = p->nx + 2 * NG;

@@ -166,3 +166,57 @@ def covariant_shear_milne(u_tilde_fn, X):
     order = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]
     return (np.array([float(sig_t[m, n]) for m, n in order]), float(theta),
             a_t.detach().numpy().copy())
+
+
+# ---------------------------------------------------------------------------
+# Viscous Gubser flow (Sec. V.C) mapped back by automatic differentiation.
+# ---------------------------------------------------------------------------
+
+
+def gubser_viscous_by_weyl(X, L, lambda1_hat, eps_hat0):
+    """(eps, u~x, u~y, pi~[10]) at Milne point X = (tau, x, y, eta), x or y != 0.
+
+    Evaluates the de Sitter-frame solution (eps^ = eps_hat0 cosh(rho)^(2/lambda1_hat - 8/3),
+    u^ = (1, 0, 0, 0), pi^^{eta eta} = C = 2 eps^/lambda1_hat, pi^^{theta theta} cosh^2 rho =
+    pi^^{phi phi} cosh^2 rho sin^2 theta = -C/2) and maps it back by the rules of Sec. V.C:
+    eps = eps^/tau^4, u_mu = tau d rho/dx^mu, pi_{mu nu} = tau^-2 (dx^a/dx^mu)(dx^b/dx^nu) pi^_{ab},
+    with the Jacobian of (rho, theta, phi, eta)(tau, x, y, eta) from automatic
+    differentiation and indices raised with the Milne metric diag(1, -1, -1, -tau^2).
+    """
+    import torch
+
+    X = torch.tensor(X, dtype=torch.float64)
+
+    def hat(Y):
+        tau, x, y, eta = Y[0], Y[1], Y[2], Y[3]
+        r = torch.sqrt(x * x + y * y)
+        rho = torch.asinh(-(L * L - tau * tau + r * r) / (2.0 * L * tau))
+        th = torch.atan2(2.0 * L * r, L * L + tau * tau - r * r)
+        phi = torch.atan2(y, x)
+        return torch.stack([rho, th, phi, eta])
+
+    xh = hat(X)
+    J = torch.autograd.functional.jacobian(hat, X)  # J[a, m] = d xhat^a / d x^m
+    rho, th = xh[0], xh[1]
+    ch = torch.cosh(rho)
+    eps_h = eps_hat0 * ch ** (2.0 / lambda1_hat - 8.0 / 3.0)
+    C = 2.0 * eps_h / lambda1_hat
+    A = -0.5 * C
+    # lower-index hat components: g^_thth = -cosh^2, g^_phph = -cosh^2 sin^2 theta, g^_etaeta = -1
+    pih_low = torch.zeros((4, 4), dtype=torch.float64)
+    pih_low[1, 1] = A * ch ** 2            # (A / cosh^2) * cosh^4
+    pih_low[2, 2] = A * ch ** 2 * torch.sin(th) ** 2
+    pih_low[3, 3] = C
+    tau = X[0]
+    pi_low = torch.einsum("am,bn,ab->mn", J, J, pih_low) / tau ** 2
+    ginv = torch.diag(torch.stack([torch.ones((), dtype=torch.float64),
+                                   -torch.ones((), dtype=torch.float64),
+                                   -torch.ones((), dtype=torch.float64), -1.0 / tau ** 2]))
+    pi_up = ginv @ pi_low @ ginv
+    u_low = tau * J[0]
+    u_up = ginv @ u_low
+    scale = torch.tensor([1.0, 1.0, 1.0, float(tau)], dtype=torch.float64)
+    pit = pi_up * scale[:, None] * scale[None, :]
+    order = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]
+    return (float(eps_h / tau ** 4), float(u_up[1]), float(u_up[2]),
+            np.array([float(pit[m, n]) for m, n in order]), u_up.detach().numpy().copy())

@@ -22,7 +22,8 @@ def oracle_params(p: dict, **kw) -> O.Params:
                     h=q["h"], etas=q["etas"], viscous=bool(q["viscous"]),
                     cartesian=bool(q["cartesian"]), **{k: q[k] for k in
                                                       ("eps_cut", "theta", "newton_tol",
-                                                       "newton_maxit", "pi_reg") if k in q})
+                                                       "newton_maxit", "pi_reg", "taupi_coef",
+                                                       "lambda1_hat") if k in q})
 
 
 def run_oracle(wl, steps, threads=None, **kw):

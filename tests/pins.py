@@ -489,6 +489,85 @@ def pin_first_step():
     return ok, dict(errs=errs)
 
 
+def pin_lambda1_static():
+    """Second-order term (eqn. pimn, lambda_1 = lambda1_hat / e): a uniform fluid at
+    rest in Cartesian mode with pi~ = a (I - 3 n n^T) on the spatial block (n a unit
+    vector off every axis, so all six spatial components are nonzero).  Then
+    sigma = theta = D u = 0, the fluxes cancel, and the projected pi pi equals a pi,
+    so the 3D step must be Heun's method for da/dt = -(a + lambda_1 a^2)/tau_pi (to
+    roundoff), whose exact solution is a0 e^{-t/tau_pi} / (1 + lambda_1 a0 (1 - e^{-t/tau_pi}));
+    the error against it must fall 4x when h halves, and e, u~ must not move."""
+    etas, eps0, a0, lam_hat, coef = 0.1, 10.0, 0.3, -10.0, 5.0
+    n = np.array([1.0, 2.0, 2.0]) / 3.0
+    shape = np.eye(3) - 3.0 * np.outer(n, n)
+    T = (eps0 / E.C_SB) ** 0.25
+    tpi = coef * etas * E.HBARC / T
+    lam1 = lam_hat / eps0
+    g = ics.Grid(3, 3, 3, 0.2, 0.2, 0.2)
+    t_end = 0.3
+    errs, heun_dev, still = [], 0.0, 0.0
+    for h in (0.01, 0.005):
+        nstep = int(round(t_end / h))
+        pi = ics.empty_pi(g)
+        for m, (a, b) in enumerate([(1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]):
+            pi[[4, 5, 6, 7, 8, 9][m]] = a0 * shape[a - 1, b - 1]
+        z = np.zeros(g.shape)
+        ic = dict(eps=np.full(g.shape, eps0), ux=z, uy=z, ue=z, pi=pi)
+        o = _orc(*g.shape, g.dx, g.dy, g.de, 1.0, h, etas=etas, viscous=True, cartesian=True,
+                 taupi_coef=coef, lambda1_hat=lam_hat)
+        o.set_initial(ic)
+        o.step(nstep)
+        f = lambda a: -(a + lam1 * a * a) / tpi
+        a = a0
+        for _ in range(nstep):
+            a1 = a + h * f(a)
+            a = a + 0.5 * h * (f(a) + f(a1))
+        for m, (i, j) in enumerate([(1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]):
+            got = o.read(f"pi{[4, 5, 6, 7, 8, 9][m]}")
+            heun_dev = max(heun_dev, float(np.max(np.abs(got - a * shape[i - 1, j - 1]))) / a0)
+        still = max(still, float(np.max(np.abs(o.read("eps") / eps0 - 1.0))),
+                    max(float(np.max(np.abs(o.read(k)))) for k in ("ux", "uy", "ue", "pi0", "pi1",
+                                                                     "pi2", "pi3")))
+        ex = np.exp(-nstep * h / tpi)
+        a_exact = a0 * ex / (1.0 + lam1 * a0 * (1.0 - ex))
+        errs.append(abs(o.read("pi4")[1, 1, 1] / shape[0, 0] - a_exact))
+    ratio = errs[0] / errs[1]
+    ok = heun_dev < 1e-13 and still < 1e-13 and 3.6 < ratio < 4.4
+    return ok, dict(heun_dev=heun_dev, still=still, ratio=ratio, errs=errs)
+
+
+def pin_gubser_viscous():
+    """Gubser flow of second-order viscous hydrodynamics (Sec. V.C): L = 2 fm,
+    eta/s = 0.2, lambda1_hat = -10, tau_pi from eta^ lambda1^2 = 3 tau_pi^, conformal
+    EoS, started from the closed form at tau = 1 fm.  At tau = 2 fm the interior
+    (r <= 3 fm) L1 errors of e, u~x and the pi~ components must fall >= 2.5x from
+    41^2 cells (dx 0.3) to 81^2 (dx 0.15) (measured 3.6, 2.9, 3.2: the limiter
+    clips slopes near the peak), and the fine grid must be within 0.5% (measured
+    0.11%, 0.04%, 0.13%).  A flipped lambda_1 term, a dropped trace in the
+    projection or the Sec. II tau_pi leave ratios near 1 and errors of 4-200%."""
+    L, etas, lam = 2.0, 0.2, -10.0
+    coef = ics.gubser_viscous_taupi_coef(lam)
+    out = []
+    for n, dx, h in ((41, 0.3, 0.02), (81, 0.15, 0.01)):
+        g = ics.Grid(n, n, 1, dx, dx, 0.3)
+        o = _orc(n, n, 1, dx, dx, 0.3, 1.0, h, etas=etas, viscous=True, taupi_coef=coef,
+                 lambda1_hat=lam)
+        o.set_initial(ics.gubser_viscous(g, 1.0, L=L, lambda1_hat=lam))
+        o.step(int(round(1.0 / h)))
+        ex = ics.gubser_viscous(g, 2.0, L=L, lambda1_hat=lam)
+        X, Y, _ = g.mesh()
+        m = (X ** 2 + Y ** 2) <= 9.0
+        emax = ex["eps"][m].max()
+        e_err = np.abs(o.read("eps") - ex["eps"])[m].mean() / emax
+        u_err = np.abs(o.read("ux") - ex["ux"])[m].mean()
+        pscale = np.abs(ex["pi"][9][m]).max()
+        p_err = max(np.abs(o.read(f"pi{c}") - ex["pi"][c])[m].mean() for c in range(10)) / pscale
+        out.append((e_err, u_err, p_err))
+    r = [out[0][k] / out[1][k] for k in range(3)]
+    ok = min(r) >= 2.5 and max(out[1]) < 0.005
+    return ok, dict(ratios=r, errs=out)
+
+
 ALL_PINS = {
     "eos": pin_eos,
     "con2prim": pin_con2prim,
@@ -504,4 +583,6 @@ ALL_PINS = {
     "symmetry": pin_symmetry,
     "shear": pin_shear,
     "transversality": pin_transversality,
+    "lambda1_static": pin_lambda1_static,
+    "gubser_viscous": pin_gubser_viscous,
 }

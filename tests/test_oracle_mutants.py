@@ -8,7 +8,10 @@ Mutants (see MUT(k) in oracle/hydro_oracle.c):
  without the sound speed, 9 sign of the right-state reconstruction,
  10 transposed gradient in D~u~, 11 wrong velocity normalisation in the root
  solve, 12 EoS T interpolation off by one node, 13 no ideal first-step
- estimate, 14 stage-2 T flux with pi' instead of pi^{n+1}, 15 tau_pi = 3 eta/(sT).
+ estimate, 14 stage-2 T flux with pi' instead of pi^{n+1}, 15 tau_pi = 3 eta/(sT),
+ 17 sign of the lambda_1 term, 18 projected pi pi without its trace part,
+ 19 tau_pi coefficient fixed at 5 (ignoring the configured one), 20 pi pi
+ contracted without the metric.
 Mutant 16 (u* = u^n instead of 2u^n - u^{n-1}) alters only the predicted pi'
 at O(h) and the step at O(h^2), the scheme's own order, so no pin is expected
 to separate it; the GPU-oracle parity tests cover that code path.
@@ -22,7 +25,7 @@ import oracle as O
 
 from . import pins
 
-CAUGHT = list(range(1, 16))
+CAUGHT = list(range(1, 16)) + [17, 18, 19, 20]
 
 
 @pytest.mark.parametrize("k", CAUGHT)
