@@ -211,6 +211,9 @@ def main():
         torch.cuda.synchronize()
         out["paths"] = {"mixed_fp32_fp64": mixed_path(wl, args)}
         out["paths"]["fp64_quiet_skip"] = mixed_path(wl, args, precision=0, quiet=True)
+        out["paths"]["fp64_lambda1"] = mixed_path(wl, args, precision=0, lambda1_hat=-10.0)
+        out["paths"]["fp64_lambda1"]["note"] = ("second-order lambda_1 term on, lambda1_hat = -10, "
+                                                "tau_pi = 5 eta/(sT)")
         b = bench_batch(args, precision=1, learned=True, steps=10, warmup=2)
         out["paths"]["batch64_mixed_learned"] = {
             k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "newton_mean", "training")}
@@ -220,16 +223,19 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def mixed_path(wl, args, precision=1, quiet=False):
+def mixed_path(wl, args, precision=1, quiet=False, **extra):
     """The same workload with FP32 reconstruction, fluxes and relaxation source
     (FP64 root solve, geometric source and state; errors against the FP64
     oracle are bounded by the GPU tests, <= 1e-6 in e and u~), or (precision 0,
     quiet) in FP64 with quiet tiles skipped (fields and diagnostics identical to
-    the full computation bit for bit, tested)."""
+    the full computation bit for bit, tested).  `extra` overrides descriptor
+    fields (the second-order path sets lambda1_hat)."""
     import torch
 
     import paper_1802_04449_amd as K
-    g = K.Hydro(precision=precision, **wl.params)
+    d = dict(wl.params)
+    d.update(extra)
+    g = K.Hydro(precision=precision, **d)
     g.set_eos(wl.eos)
     if quiet:
         g.set_quiet_skip(True)

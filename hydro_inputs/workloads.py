@@ -47,6 +47,18 @@ def gubser_ideal_33(steps: int = 50) -> Workload:
     return Workload("gubser_ideal_33x33x17", p, "conformal", steps, ic=ics.gubser_ideal(g, 1.0))
 
 
+def gubser_viscous(n=41, ne=5, dx=0.3, de=0.3, h=0.02, steps=50, L=2.0, etas=0.2,
+                   lambda1_hat=-10.0) -> Workload:
+    """Second-order viscous conformal hydro started from the Sec. V.C Gubser
+    solution at tau0 = 1 fm (L = 2 fm, eta/s = 0.2, lambda1_hat = -10, tau_pi
+    coefficient from the solution's condition), boost invariant on ne cells."""
+    p = _params(n, n, ne, dx, dx, de, 1.0, h, etas=etas, viscous=True)
+    p.update(taupi_coef=ics.gubser_viscous_taupi_coef(lambda1_hat), lambda1_hat=lambda1_hat)
+    g = ics.Grid(n, n, ne, dx, dx, de)
+    return Workload(f"gubser_viscous_{n}x{n}x{ne}", p, "conformal", steps,
+                    ic=ics.gubser_viscous(g, 1.0, L=L, lambda1_hat=lambda1_hat))
+
+
 def hotspots_viscous(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps=200, seed=1,
                      etas=0.08) -> Workload:
     """Viscous hydro, eta/s = 0.08, tau0 = 0.6 fm, h = 0.01 fm, 200 Gaussian hotspots

@@ -78,6 +78,12 @@ typedef struct ktmi_desc {
                             source, state and accumulators */
     int guess;           /* KTMI_GUESS_* */
     int tile;            /* workgroup tile shape index (ktmi_tile_shape); -1 = automatic */
+    double taupi_coef;   /* tau_pi = taupi_coef (eta/s) hbarc / T; 5 in Sec. II.  Must be > 0
+                            when viscous.  The Sec. V.C viscous Gubser solution needs
+                            4 lambda1_hat^2 / 9 (its condition eta^ lambda1^2 = 3 tau_pi^) */
+    double lambda1_hat;  /* second-order term of eqn. pimn, -(lambda_1/tau_pi) pi^<mu_l pi^nu>l,
+                            with lambda_1 = lambda1_hat / e (the dimensionless lambda1_hat = lambda_1 e
+                            of Sec. V.C); 0 = the equations of Sec. II.  Must be finite */
 } ktmi_desc;
 
 typedef struct ktmi_diagnostics {
@@ -95,12 +101,13 @@ typedef struct ktmi_diagnostics {
 typedef struct ktmi_handle ktmi_handle;
 
 /* Fills d with the defaults: cutoff 1e-7, theta 1.8, tolerance 1e-12, 100
- * iterations, regulator 1.0, FP64, previous-stage guess, automatic tile.  Sizes
- * are zero. */
+ * iterations, regulator 1.0, FP64, previous-stage guess, automatic tile,
+ * taupi_coef 5, lambda1_hat 0.  Sizes are zero. */
 void ktmi_desc_default(ktmi_desc *d);
 
 /* Validates d and creates a handle (host memory only).  KTMI_EINVAL if a size
- * is < 1, a spacing, tau0 or h is not > 0, or viscous with etas <= 0. */
+ * is < 1, a spacing, tau0 or h is not > 0, viscous with etas <= 0 or
+ * taupi_coef <= 0, or lambda1_hat is not finite. */
 int ktmi_create(const ktmi_desc *d, ktmi_handle **out);
 
 /* Bytes of device workspace the handle needs (0 if d is invalid). */

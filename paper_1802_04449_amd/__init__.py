@@ -33,7 +33,8 @@ class ktmi_desc(C.Structure):
                 ("viscous", C.c_int), ("cartesian", C.c_int),
                 ("eps_cut", C.c_double), ("theta", C.c_double), ("newton_tol", C.c_double),
                 ("newton_maxit", C.c_int), ("pi_reg", C.c_double), ("precision", C.c_int),
-                ("guess", C.c_int), ("tile", C.c_int)]
+                ("guess", C.c_int), ("tile", C.c_int), ("taupi_coef", C.c_double),
+                ("lambda1_hat", C.c_double)]
 
 
 class ktmi_diagnostics(C.Structure):

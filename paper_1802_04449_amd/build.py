@@ -23,7 +23,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
-NUM_PASSES = 6  # first estimate, stage1 (viscous, ideal), stage2 pi, stage2 T (viscous, ideal)
+NUM_PASSES = 8  # first estimate, stage1 (viscous, ideal), stage2 pi, stage2 T (viscous, ideal),
+#                 stage1 viscous and stage2 pi with the lambda_1 term
 
 
 def _jobs():

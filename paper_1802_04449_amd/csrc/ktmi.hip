@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -250,6 +251,14 @@ static bool desc_ok(const ktmi_desc* d, std::string* why) {
     *why = "viscous mode needs etas > 0";
     return false;
   }
+  if (d->viscous && !(d->taupi_coef > 0)) {
+    *why = "viscous mode needs taupi_coef > 0";
+    return false;
+  }
+  if (!std::isfinite(d->lambda1_hat)) {
+    *why = "lambda1_hat must be finite";
+    return false;
+  }
   if (!(d->theta >= 1.0 && d->theta <= 2.0)) {
     *why = "theta must lie in [1, 2]";
     return false;
@@ -338,7 +347,10 @@ static StepParams step_params(const ktmi_handle* h) {
   p.h = h->d.h;
   p.inv_h = 1.0 / h->d.h;
   p.etas = h->d.etas;
-  p.inv_taupi_coef = h->d.etas > 0 ? 1.0 / (5.0 * h->d.etas * kHbarc) : 0.0;
+  const bool visc_ok = h->d.etas > 0 && h->d.taupi_coef > 0;
+  p.inv_taupi_coef = visc_ok ? 1.0 / (h->d.taupi_coef * h->d.etas * kHbarc) : 0.0;
+  p.eta_taupi = visc_ok ? 1.0 / h->d.taupi_coef : 0.0;
+  p.lambda1_hat = h->d.lambda1_hat;
   p.c_vac = sqrt(h->cs2_vac);
   p.eps_cut = h->d.eps_cut;
   p.theta = h->d.theta;
@@ -395,7 +407,8 @@ static Geo geo(const ktmi_handle* h, double tau, double tau1) {
 static const PassLauncher kPassLaunch[PASS_COUNT][2] = {
     {launch_pass0_f64, launch_pass0_f32}, {launch_pass1_f64, launch_pass1_f32},
     {launch_pass2_f64, launch_pass2_f32}, {launch_pass3_f64, launch_pass3_f32},
-    {launch_pass4_f64, launch_pass4_f32}, {launch_pass5_f64, launch_pass5_f32}};
+    {launch_pass4_f64, launch_pass4_f32}, {launch_pass5_f64, launch_pass5_f32},
+    {launch_pass6_f64, launch_pass6_f32}, {launch_pass7_f64, launch_pass7_f32}};
 
 static void launch_class(int pass, hipStream_t s, int tile, int precision, bool net,
                          const EventDesc* evs, const GroupTable& gt) {
@@ -440,15 +453,16 @@ static int upload_event(ktmi_handle* h) {
 }
 
 // The kernels of one step for the events of one class (same tile, precision, mode).
-static int enqueue_class_step(ktmi_handle* h, hipStream_t s, int tile, int precision, int viscous,
+// mode: 0 ideal, 1 viscous (Sec. II), 2 viscous with the lambda_1 term.
+static int enqueue_class_step(ktmi_handle* h, hipStream_t s, int tile, int precision, int mode,
                               bool net, const EventDesc* evs, const GroupTable& gt) {
   int rc;
-  if (viscous) {
-    rc = launch(h, K_STAGE1,
-                [&] { launch_class(PASS_STAGE1_V, s, tile, precision, net, evs, gt); });
+  if (mode) {
+    const int p1 = mode == 2 ? PASS_STAGE1_V_L1 : PASS_STAGE1_V;
+    const int p2 = mode == 2 ? PASS_STAGE2_PI_L1 : PASS_STAGE2_PI;
+    rc = launch(h, K_STAGE1, [&] { launch_class(p1, s, tile, precision, net, evs, gt); });
     if (rc) return rc;
-    rc = launch(h, K_STAGE2PI,
-                [&] { launch_class(PASS_STAGE2_PI, s, tile, precision, false, evs, gt); });
+    rc = launch(h, K_STAGE2PI, [&] { launch_class(p2, s, tile, precision, false, evs, gt); });
     if (rc) return rc;
     return launch(h, K_STAGE2T,
                   [&] { launch_class(PASS_STAGE2_T_V, s, tile, precision, net, evs, gt); });
@@ -462,9 +476,14 @@ static int enqueue_class_step(ktmi_handle* h, hipStream_t s, int tile, int preci
 
 static bool uses_net(const ktmi_handle* h) { return h->d.guess == KTMI_GUESS_MLP; }
 
+// 0 ideal, 1 viscous, 2 viscous with the lambda_1 term
+static int step_mode(const ktmi_handle* h) {
+  return !h->d.viscous ? 0 : (h->d.lambda1_hat != 0.0 ? 2 : 1);
+}
+
 static int enqueue_step(ktmi_handle* h) {
   const GroupTable gt = single_table(h);
-  int rc = enqueue_class_step(h, h->stream, h->tile, h->d.precision, h->d.viscous, uses_net(h),
+  int rc = enqueue_class_step(h, h->stream, h->tile, h->d.precision, step_mode(h), uses_net(h),
                               h->dev_ev, gt);
   if (rc) return rc;
   return launch(h, K_REDUCE, [&] {
@@ -523,7 +542,7 @@ struct ktmi_group {
   std::vector<ktmi_handle*> hs;  // in class order
   hipStream_t stream = nullptr;
   struct Class {
-    int tile, precision, viscous;
+    int tile, precision, mode;  // mode: step_mode() of its events
     bool net;   // learned root-solve guess
     int first;  // index of the class's first event in the device table
     GroupTable gt;
@@ -545,7 +564,7 @@ static int group_fail(ktmi_group* g, int code, const std::string& msg) {
 static int enqueue_group_step(ktmi_group* g) {
   ktmi_handle* h = &g->timing_stub;
   for (const auto& c : g->classes) {
-    int rc = enqueue_class_step(h, g->stream, c.tile, c.precision, c.viscous, c.net, g->dev + c.first,
+    int rc = enqueue_class_step(h, g->stream, c.tile, c.precision, c.mode, c.net, g->dev + c.first,
                                 c.gt);
     if (rc) return group_fail(g, rc, h->err);
   }
@@ -568,6 +587,8 @@ void ktmi_desc_default(ktmi_desc* d) {
   d->precision = KTMI_FP64;
   d->guess = KTMI_GUESS_PREV;
   d->tile = -1;
+  d->taupi_coef = 5.0;
+  d->lambda1_hat = 0.0;
 }
 
 size_t ktmi_workspace_bytes(const ktmi_desc* d) {
@@ -1022,13 +1043,13 @@ int ktmi_group_create(ktmi_handle* const* hs, int nev, void* ws, size_t bytes, k
     int c = -1;
     for (size_t k = 0; k < g->classes.size(); ++k)
       if (g->classes[k].tile == h->tile && g->classes[k].precision == h->d.precision &&
-          g->classes[k].viscous == h->d.viscous && g->classes[k].net == uses_net(h))
+          g->classes[k].mode == step_mode(h) && g->classes[k].net == uses_net(h))
         c = (int)k;
     if (c < 0) {
       ktmi_group::Class cl{};
       cl.tile = h->tile;
       cl.precision = h->d.precision;
-      cl.viscous = h->d.viscous;
+      cl.mode = step_mode(h);
       cl.net = uses_net(h);
       g->classes.push_back(cl);
       members.emplace_back();

@@ -16,7 +16,9 @@ struct StepParams {
   double inv_dx, inv_dy, inv_de;  // reciprocals of the spacings
   double h, inv_h;
   double etas;
-  double inv_taupi_coef;  // 1 / (5 eta/s hbarc): 1/tau_pi = T * inv_taupi_coef
+  double inv_taupi_coef;  // 1 / (b eta/s hbarc): 1/tau_pi = T * inv_taupi_coef (b = 5, Sec. II)
+  double eta_taupi;       // 1 / b: eta_v / tau_pi = (e + P) / b
+  double lambda1_hat;     // lambda_1 = lambda1_hat / e (0: no second-order term)
   double eps_cut, theta, newton_tol, pi_reg;
   double c_vac;  // local speed of a vacuum state, sqrt(cs2(0))
   int newton_maxit;

@@ -632,10 +632,11 @@ constexpr int lds_doubles() {
 // Waves per SIMD asked of stage2_pi: 3 where the tile's LDS leaves room for
 // three workgroups per CU (160 KB), else no bound.  Capping its registers for
 // a third wave is a net gain for this pass (10-16% on the 201x201x105 grids);
-// stage1 and stage2_T lose from the same cap (spills), so they have none.
-template <typename RT, int TX, int TY, int TZ>
+// stage1 and stage2_T lose from the same cap (spills), so they have none, nor
+// has the lambda_1 variant of stage2_pi (it would spill under the cap).
+template <typename RT, int TX, int TY, int TZ, bool L1>
 constexpr int pi_waves() {
-  return 163840 / (int)(lds_doubles<TX, TY, TZ>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
+  return !L1 && 163840 / (int)(lds_doubles<TX, TY, TZ>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
 }
 
 // u~^tau of spatial components.
@@ -643,13 +644,17 @@ __device__ __forceinline__ double utau(double a, double b, double c) {
   return sqrt(1.0 + a * a + b * b + c * c);
 }
 
-// Israel-Stewart source (Sec. II, eqns. pitilde, Ipi; eqn. pimn with lambda_i = 0,
-// tau_pi = 5 eta_v/(T s)):
-// S = -(pi - eta sigma)/tau_pi - pi theta/3 - (u b + b u) - pi u~^tau/tau - I,
+// Israel-Stewart source (Sec. II, eqns. pitilde, Ipi; eqn. pimn with lambda_2 = lambda_3 = 0):
+// S = -(pi - eta sigma)/tau_pi - pi theta/3 - (u b + b u) - pi u~^tau/tau - I
+//     - (lambda_1/tau_pi) pi^<mu_l pi^nu>l,
 // sigma~, theta, D~u~ from nabla~_mu u~^nu (eq. dtuz), b^nu = pi^{nu beta} g_{beta beta} a^beta.
 // uE/uL: time levels for d_tau u~.  With eta = (eta/s)(e+P) hbarc/T and
-// tau_pi = 5 (eta/s) hbarc/T, eta/tau_pi = (e+P)/5.
-template <typename R>
+// tau_pi = b (eta/s) hbarc/T (b = 5 in Sec. II), eta/tau_pi = (e+P)/b.  lambda_1 =
+// lambda1_hat / e (Sec. V.C scaling); the bracket <> is the double projector of
+// eqn. projector applied to X^{ab} = pi^{a l} g_{l l} pi^{b l}, expanded as
+// X - u w - w u + u u (u.w) - (1/3)(g - u u)(g:X - u.w) with w^b = u_a X^{ab}
+// (an identity for any symmetric X; pi's transversality is not assumed).
+template <typename R, bool L1>
 __device__ __forceinline__ void pi_source(const double* const* u, const double* const* uE,
                                           const double* const* uL, const StepParams& p,
                                           const EosDev& eos, const Geo& g, const Pos& q,
@@ -707,7 +712,7 @@ __device__ __forceinline__ void pi_source(const double* const* u, const double* 
   R P, T;
   eos_p_t_r<R>(eos, ec, P, T);
   const R inv_taupi = T * (R)p.inv_taupi_coef;
-  const R eta_over_taupi = R(0.2) * (ec + P);
+  const R eta_over_taupi = (R)p.eta_taupi * (ec + P);
   const R ue = uc[3];
   const R third = R(1) / R(3);
 #pragma unroll
@@ -731,6 +736,33 @@ __device__ __forceinline__ void pi_source(const double* const* u, const double* 
         s += -(pc[m] * uc[0] + I) * inv_tau;
       }
       S_d[m] = (double)s;
+    }
+  }
+  if constexpr (L1) {
+    R X[10];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = a; b < 4; ++b)
+        X[sym(a, b)] = pc[sym(a, 0)] * pc[sym(b, 0)] - pc[sym(a, 1)] * pc[sym(b, 1)] -
+                       pc[sym(a, 2)] * pc[sym(b, 2)] - pc[sym(a, 3)] * pc[sym(b, 3)];
+    R w[4];  // w^b = u_a X^{ab}, u_a = g_a u~^a
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      w[b] = uc[0] * X[sym(0, b)] - uc[1] * X[sym(1, b)] - uc[2] * X[sym(2, b)] -
+             uc[3] * X[sym(3, b)];
+    const R uw = uc[0] * w[0] - uc[1] * w[1] - uc[2] * w[2] - uc[3] * w[3];
+    const R tr = X[0] - X[4] - X[7] - X[9] - uw;  // Delta_{ab} X^{ab}
+    const R c1 = (R)p.lambda1_hat / ec * inv_taupi;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+      for (int nu = mu; nu < 4; ++nu) {
+        const int m = sym(mu, nu);
+        const R dmn = ((mu == nu) ? gt[mu] : R(0)) - uc[mu] * uc[nu];
+        const R Y = X[m] - uc[mu] * w[nu] - uc[nu] * w[mu] + uc[mu] * uc[nu] * uw - third * dmn * tr;
+        S_d[m] -= (double)(c1 * Y);
+      }
     }
   }
 }
@@ -875,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(const EventDesc* __re
 }
 
 // Stage 1 at tau_n (predictor) for the ideal (VISC = false) or viscous path.
-template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET>
+template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool L1>
 __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__ evs,
                                                     GroupTable gt) {
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
@@ -919,7 +951,7 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
     if (VISC) {
       if (e >= p.eps_cut) {
         double S[10];
-        pi_source<RT>(f.u, f.up, f.u, p, eos, g, q, e, pc, S);
+        pi_source<RT, L1>(f.u, f.up, f.u, p, eos, g, q, e, pc, S);
 #pragma unroll
         for (int m = 0; m < 10; ++m) R[4 + m] += S[m];
       }
@@ -961,9 +993,9 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
 }
 
 // Stage 2, part 1 (tau_{n+1}): pi^{n+1} = [ (u^n pi^n + u* pi')/2 + h/2 R_pi(e', u', pi') ] / u'^tau.
-template <typename RT, int TX, int TY, int TZ>
+template <typename RT, int TX, int TY, int TZ, bool L1>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ>()))) void k_stage2_pi(
+__attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, L1>()))) void k_stage2_pi(
     const EventDesc* __restrict__ evs, GroupTable gt) {
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 1);
@@ -985,7 +1017,7 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ>()))) void k_stage2_p
     for (int m = 0; m < 10; ++m) pc[m] = f.pi1[m][c];
     if (e1 >= p.eps_cut) {
       double S[10];
-      pi_source<RT>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
+      pi_source<RT, L1>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
 #pragma unroll
       for (int m = 0; m < 10; ++m) R[4 + m] += S[m];
     }
@@ -1113,10 +1145,12 @@ constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 // Launchers of the stencil passes, one per (pass, arithmetic type), each
 // defined in its own object (ktmi_stencil.hip built per pass and type).  `net`
-// selects the instances whose root solves take the network's guess.
+// selects the instances whose root solves take the network's guess.  The
+// passes that evaluate S_pi come twice: without and with the lambda_1 term
+// (a compile-time choice, so the first-order kernels keep their registers).
 enum Pass : int {
   PASS_FIRST = 0, PASS_STAGE1_V, PASS_STAGE1_I, PASS_STAGE2_PI, PASS_STAGE2_T_V, PASS_STAGE2_T_I,
-  PASS_COUNT
+  PASS_STAGE1_V_L1, PASS_STAGE2_PI_L1, PASS_COUNT
 };
 typedef void (*PassLauncher)(hipStream_t s, int tile, bool net, const EventDesc* evs,
                              const GroupTable& gt);
@@ -1129,6 +1163,8 @@ KTMI_DECLARE_PASS(2)
 KTMI_DECLARE_PASS(3)
 KTMI_DECLARE_PASS(4)
 KTMI_DECLARE_PASS(5)
+KTMI_DECLARE_PASS(6)
+KTMI_DECLARE_PASS(7)
 #undef KTMI_DECLARE_PASS
 
 }  // namespace ktmi

@@ -1,9 +1,10 @@
 // ktmi_stencil.hip -- instances of one stencil pass of the RK2 step for one
 // arithmetic type, and the launcher the host code calls for them.  The build
-// compiles this file once per (pass, type) with -DKTMI_PASS=<0..5>
+// compiles this file once per (pass, type) with -DKTMI_PASS=<0..7>
 // -DKTMI_RT=<double|float> -DKTMI_LAUNCH_FN=launch_pass<P>_<f64|f32>, so the
 // instances compile in parallel.  Passes: 0 first-step estimate, 1 / 2 stage 1
-// (viscous / ideal), 3 stage 2 pi, 4 / 5 stage 2 T (viscous / ideal).
+// (viscous / ideal), 3 stage 2 pi, 4 / 5 stage 2 T (viscous / ideal), 6 / 7
+// stage 1 viscous / stage 2 pi with the second-order lambda_1 term.
 #include "ktmi_kernels.hpp"
 
 #if !defined(KTMI_PASS) || !defined(KTMI_RT) || !defined(KTMI_LAUNCH_FN)
@@ -18,22 +19,26 @@ void launch_tile(dim3 g, dim3 b, hipStream_t s, const EventDesc* evs, const Grou
 #if KTMI_PASS == 0
   hipLaunchKernelGGL((k_first_estimate<KTMI_RT, X, Y, Z>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 1
-  hipLaunchKernelGGL((k_stage1<KTMI_RT, X, Y, Z, true, N>), g, b, 0, s, evs, gt);
+  hipLaunchKernelGGL((k_stage1<KTMI_RT, X, Y, Z, true, N, false>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 2
-  hipLaunchKernelGGL((k_stage1<KTMI_RT, X, Y, Z, false, N>), g, b, 0, s, evs, gt);
+  hipLaunchKernelGGL((k_stage1<KTMI_RT, X, Y, Z, false, N, false>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 3
-  hipLaunchKernelGGL((k_stage2_pi<KTMI_RT, X, Y, Z>), g, b, 0, s, evs, gt);
+  hipLaunchKernelGGL((k_stage2_pi<KTMI_RT, X, Y, Z, false>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 4
   hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, true, N>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 5
   hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, false, N>), g, b, 0, s, evs, gt);
+#elif KTMI_PASS == 6
+  hipLaunchKernelGGL((k_stage1<KTMI_RT, X, Y, Z, true, N, true>), g, b, 0, s, evs, gt);
+#elif KTMI_PASS == 7
+  hipLaunchKernelGGL((k_stage2_pi<KTMI_RT, X, Y, Z, true>), g, b, 0, s, evs, gt);
 #else
 #error "KTMI_PASS out of range"
 #endif
 }
 
 // passes without a root solve have no network instances
-constexpr bool kHasNet = KTMI_PASS != 0 && KTMI_PASS != 3;
+constexpr bool kHasNet = KTMI_PASS != 0 && KTMI_PASS != 3 && KTMI_PASS != 7;
 
 }  // namespace
 

@@ -48,11 +48,14 @@ def test_defaults_follow_the_paper():
     d = K.ktmi_desc_default()
     assert d.eps_cut == 1e-7  # energy-density cutoff of Sec. V.A
     assert d.newton_tol == 1e-12 and d.precision == K.KTMI_FP64
+    assert d.taupi_coef == 5.0 and d.lambda1_hat == 0.0  # tau_pi = 5 eta/(sT), Sec. II
 
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ne=-1), dict(dx=0.0), dict(h=-0.01),
                                  dict(tau0=0.0), dict(viscous=1, etas=0.0), dict(theta=2.5),
-                                 dict(newton_maxit=0), dict(precision=7), dict(guess=9)])
+                                 dict(newton_maxit=0), dict(precision=7), dict(guess=9),
+                                 dict(viscous=1, etas=0.1, taupi_coef=0.0),
+                                 dict(lambda1_hat=float("nan")), dict(lambda1_hat=float("inf"))])
 def test_invalid_descriptors_rejected(bad):
     import paper_1802_04449_amd as K
     d = _desc(**bad)

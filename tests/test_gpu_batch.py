@@ -73,6 +73,31 @@ def test_group_matches_single_events():
     G.assert_parity(grouped[2].fields(), of, 1e-12, "grouped event vs oracle")
 
 
+def test_group_with_second_order_events():
+    """A group mixing first-order events with lambda_1 events (different kernel
+    classes in one step) gives the single-run fields bit for bit."""
+    import torch
+    print("[gpu-case] grouped lambda_1 events", flush=True)
+    import paper_1802_04449_amd as K
+    evs = W.event_batch(nev=3, seed0=80, steps=5, sizes=[(29, 7, 0.08), (25, 5, 0.16), (31, 9, 0.08)])
+    for wl in evs:
+        wl.params.update(dx=0.45, dy=0.45, de=0.45)
+    evs[0].params.update(lambda1_hat=-8.0, taupi_coef=6.0)
+    evs[2].params.update(lambda1_hat=-12.0)
+    st = torch.cuda.Stream()
+    solo = [_make(wl, st) for wl in evs]
+    grouped = [_make(wl, st) for wl in evs]
+    for h in solo:
+        h.step(5)
+    grp = K.Group(grouped)
+    assert grp.classes >= 2
+    grp.step(5)
+    for e, (x, y) in enumerate(zip(solo, grouped)):
+        _same(x, y, f"event {e}")
+    of = G.run_oracle(evs[0], 5).fields()
+    G.assert_parity(grouped[0].fields(), of, 1e-12, "grouped lambda_1 event vs oracle")
+
+
 def test_autotuner_selects_a_tile_and_results_do_not_change():
     """The autotuner times every tile shape on the event and keeps the fastest;
     the state it then produces equals an untuned run's (any tile gives the same

@@ -54,6 +54,11 @@ def test_mixed_viscous_hotspots():
     _check(W.hotspots_viscous(nx=45, ny=39, ne=13, dx=0.35, dy=0.35, de=0.4, steps=20, seed=5), 20)
 
 
+def test_mixed_viscous_gubser_second_order():
+    """The lambda_1 term in FP32 (Sec. V.C viscous Gubser flow, 41x41x5, 50 steps)."""
+    _check(W.gubser_viscous(steps=50), 50)
+
+
 def test_mixed_viscous_fine_grid():
     _check(W.hotspots_viscous(nx=65, ny=65, ne=17, dx=0.16, dy=0.16, de=0.3, steps=60, seed=5), 60)
 
