@@ -9,6 +9,20 @@ namespace ktmi {
 
 constexpr double kHbarc = 0.1973269804;  // GeV fm
 
+// Device memory seen through the global address space.  Plain pointers read
+// from a table in memory are generic to the compiler, which then emits FLAT
+// loads and stores; on CDNA those also count against the LDS / scalar-memory
+// wait counter, so every LDS wait would also wait for outstanding HBM loads.
+// Pointers of these types compile to global_load / global_store.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) int gint;
+
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gl(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 // Parameters copied by value into every launch (kernel argument segment).
 struct StepParams {
   int nx, ny, ne, ncell;
@@ -80,14 +94,14 @@ __device__ __forceinline__ void eos_p_cs2(const EosDev& q, double e, double& P, 
   EosSeg s = eos_seg(q, e);
   const int n = q.n;
   if (s.beyond) {
-    const double slope = (q.P[n - 1] - q.P[n - 2]) * q.inv_de;
+    const double slope = (gl(q.P)[n - 1] - gl(q.P)[n - 2]) * q.inv_de;
     const double elast = q.e0 + (double)(n - 1) * q.de;
-    P = q.P[n - 1] + (e - elast) * slope;
-    cs2 = q.cs2[n - 1];
+    P = gl(q.P)[n - 1] + (e - elast) * slope;
+    cs2 = gl(q.cs2)[n - 1];
     return;
   }
-  const double p0 = q.P[s.i], p1 = q.P[s.i + 1];
-  const double c0 = q.cs2[s.i], c1 = q.cs2[s.i + 1];
+  const double p0 = gl(q.P)[s.i], p1 = gl(q.P)[s.i + 1];
+  const double c0 = gl(q.cs2)[s.i], c1 = gl(q.cs2)[s.i + 1];
   P = p0 + s.f * (p1 - p0);
   cs2 = c0 + s.f * (c1 - c0);
 }
@@ -103,12 +117,12 @@ __device__ __forceinline__ void eos_p_dp(const EosDev& q, double e, double& P, d
   EosSeg s = eos_seg(q, e);
   const int n = q.n;
   if (s.beyond) {
-    dP = (q.P[n - 1] - q.P[n - 2]) * q.inv_de;
+    dP = (gl(q.P)[n - 1] - gl(q.P)[n - 2]) * q.inv_de;
     const double elast = q.e0 + (double)(n - 1) * q.de;
-    P = q.P[n - 1] + (e - elast) * dP;
+    P = gl(q.P)[n - 1] + (e - elast) * dP;
     return;
   }
-  const double p0 = q.P[s.i], p1 = q.P[s.i + 1];
+  const double p0 = gl(q.P)[s.i], p1 = gl(q.P)[s.i + 1];
   P = p0 + s.f * (p1 - p0);
   dP = (p1 - p0) * q.inv_de;
 }
@@ -124,14 +138,14 @@ __device__ __forceinline__ void eos_p_t(const EosDev& q, double e, double& P, do
   EosSeg s = eos_seg(q, e);
   const int n = q.n;
   if (s.beyond) {
-    const double slope = (q.P[n - 1] - q.P[n - 2]) * q.inv_de;
+    const double slope = (gl(q.P)[n - 1] - gl(q.P)[n - 2]) * q.inv_de;
     const double elast = q.e0 + (double)(n - 1) * q.de;
-    P = q.P[n - 1] + (e - elast) * slope;
-    T = q.T[n - 1] * sqrt(sqrt((e + P) / (elast + q.P[n - 1])));
+    P = gl(q.P)[n - 1] + (e - elast) * slope;
+    T = gl(q.T)[n - 1] * sqrt(sqrt((e + P) / (elast + gl(q.P)[n - 1])));
     return;
   }
-  const double p0 = q.P[s.i], p1 = q.P[s.i + 1];
-  const double t0 = q.T[s.i], t1 = q.T[s.i + 1];
+  const double p0 = gl(q.P)[s.i], p1 = gl(q.P)[s.i + 1];
+  const double t0 = gl(q.T)[s.i], t1 = gl(q.T)[s.i + 1];
   P = p0 + s.f * (p1 - p0);
   T = t0 + s.f * (t1 - t0);
 }
@@ -295,16 +309,16 @@ __device__ __forceinline__ void eos_p_cs2_r<float>(const EosDev& q, float e, flo
   float x = (e - q.e0_f) * q.inv_de_f;
   x = x >= 0.0f ? x : 0.0f;
   if (x >= (float)(n - 1)) {
-    const float slope = (q.Pf[n - 1] - q.Pf[n - 2]) * q.inv_de_f;
-    P = q.Pf[n - 1] + (e - (q.e0_f + (float)(n - 1) * q.de_f)) * slope;
-    cs2 = q.cs2f[n - 1];
+    const float slope = (gl(q.Pf)[n - 1] - gl(q.Pf)[n - 2]) * q.inv_de_f;
+    P = gl(q.Pf)[n - 1] + (e - (q.e0_f + (float)(n - 1) * q.de_f)) * slope;
+    cs2 = gl(q.cs2f)[n - 1];
     return;
   }
   int i = (int)floorf(x);
   i = i > n - 2 ? n - 2 : (i < 0 ? 0 : i);
   const float f = x - (float)i;
-  P = q.Pf[i] + f * (q.Pf[i + 1] - q.Pf[i]);
-  cs2 = q.cs2f[i] + f * (q.cs2f[i + 1] - q.cs2f[i]);
+  P = gl(q.Pf)[i] + f * (gl(q.Pf)[i + 1] - gl(q.Pf)[i]);
+  cs2 = gl(q.cs2f)[i] + f * (gl(q.cs2f)[i + 1] - gl(q.cs2f)[i]);
 }
 
 template <typename R>
@@ -327,17 +341,17 @@ __device__ __forceinline__ void eos_p_t_r<float>(const EosDev& q, float e, float
   float x = (e - q.e0_f) * q.inv_de_f;
   x = x >= 0.0f ? x : 0.0f;
   if (x >= (float)(n - 1)) {
-    const float slope = (q.Pf[n - 1] - q.Pf[n - 2]) * q.inv_de_f;
+    const float slope = (gl(q.Pf)[n - 1] - gl(q.Pf)[n - 2]) * q.inv_de_f;
     const float elast = q.e0_f + (float)(n - 1) * q.de_f;
-    P = q.Pf[n - 1] + (e - elast) * slope;
-    T = q.Tf[n - 1] * sqrtf(sqrtf((e + P) / (elast + q.Pf[n - 1])));
+    P = gl(q.Pf)[n - 1] + (e - elast) * slope;
+    T = gl(q.Tf)[n - 1] * sqrtf(sqrtf((e + P) / (elast + gl(q.Pf)[n - 1])));
     return;
   }
   int i = (int)floorf(x);
   i = i > n - 2 ? n - 2 : (i < 0 ? 0 : i);
   const float f = x - (float)i;
-  P = q.Pf[i] + f * (q.Pf[i + 1] - q.Pf[i]);
-  T = q.Tf[i] + f * (q.Tf[i + 1] - q.Tf[i]);
+  P = gl(q.Pf)[i] + f * (gl(q.Pf)[i + 1] - gl(q.Pf)[i]);
+  T = gl(q.Tf)[i] + f * (gl(q.Tf)[i + 1] - gl(q.Tf)[i]);
 }
 
 template <typename R>

@@ -44,20 +44,49 @@ __host__ __device__ constexpr bool is_max_slot(int s) {
   return s == P_CFL || s == P_ITMAX || s == P_EMAX;
 }
 
-struct Fields {
-  double* e;       // e^n, overwritten by e^{n+1} in stage2T
-  double* u[3];    // u~^n
-  double* up[3];   // u~^{n-1}; stage2T writes u~^{n+1} here
-  double* pi[10];  // pi~^n, overwritten by pi~^{n+1} in stage2pi
-  double* T[4];    // T~^{tau mu, n}, overwritten by T^{n+1} in stage2T
-  double* e1;      // stage-1 prediction
-  double* u1[3];
-  double* pi1[10];
-  double* T1[4];
-  double* partial;  // [2][kNP][nblk]: stage1 then stage2T, slot-major
-  double* acc;      // [16] accumulated diagnostics
-  int* quiet;       // [3][ntiles]: quiet flags by clock parity (2), stage-2pi part (1)
+template <typename D, typename I>
+struct FieldsT {
+  D* e;       // e^n, overwritten by e^{n+1} in stage2T
+  D* u[3];    // u~^n
+  D* up[3];   // u~^{n-1}; stage2T writes u~^{n+1} here
+  D* pi[10];  // pi~^n, overwritten by pi~^{n+1} in stage2pi
+  D* T[4];    // T~^{tau mu, n}, overwritten by T^{n+1} in stage2T
+  D* e1;      // stage-1 prediction
+  D* u1[3];
+  D* pi1[10];
+  D* T1[4];
+  D* partial;  // [2][kNP][nblk]: stage1 then stage2T, slot-major
+  D* acc;      // [16] accumulated diagnostics
+  I* quiet;    // [3][ntiles]: quiet flags by clock parity (2), stage-2pi part (1)
 };
+using Fields = FieldsT<double, int>;     // as the host fills it
+using DFields = FieldsT<gdouble, gint>;  // the same pointers, global address space
+
+__device__ __forceinline__ DFields dfields(const Fields& f) {
+  DFields d;
+  d.e = (gdouble*)f.e;
+  d.e1 = (gdouble*)f.e1;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    d.u[m] = (gdouble*)f.u[m];
+    d.up[m] = (gdouble*)f.up[m];
+    d.u1[m] = (gdouble*)f.u1[m];
+  }
+#pragma unroll
+  for (int m = 0; m < 10; ++m) {
+    d.pi[m] = (gdouble*)f.pi[m];
+    d.pi1[m] = (gdouble*)f.pi1[m];
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    d.T[m] = (gdouble*)f.T[m];
+    d.T1[m] = (gdouble*)f.T1[m];
+  }
+  d.partial = (gdouble*)f.partial;
+  d.acc = (gdouble*)f.acc;
+  d.quiet = (gint*)f.quiet;
+  return d;
+}
 
 struct Geo {
   double tau;   // stage time in the Milne factors (1 in Cartesian mode)
@@ -94,15 +123,15 @@ struct GroupTable {
 // Per-block view of its event.  stage2 = 0: tau = tau_n, tau1 = tau_n + h;
 // stage2 = 1: tau = tau1 = tau_n + h.
 struct Ctx {
-  Fields f;
+  DFields f;
   StepParams p;
   EosDev eos;
   TileGrid tg;
   Geo g;
   int tile;  // tile index inside the event
-  const int* qcur;  // quiet flags after the previous step
-  int* qnext;       // quiet flags after this step
-  int* qpi;         // this step's stage-2pi part of the flags
+  const gint* qcur;  // quiet flags after the previous step
+  gint* qnext;       // quiet flags after this step
+  gint* qpi;         // this step's stage-2pi part of the flags
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -169,7 +198,7 @@ __device__ __forceinline__ Ctx load_ctx(const EventDesc* __restrict__ evs, const
   while (e + 1 < gt.nev && t >= gt.start[e + 1]) ++e;
   const EventDesc& E = evs[e];
   Ctx c;
-  c.f = E.f;
+  c.f = dfields(E.f);
   c.p = E.p;
   c.eos = E.eos;
   c.tg = E.tg;
@@ -177,17 +206,17 @@ __device__ __forceinline__ Ctx load_ctx(const EventDesc* __restrict__ evs, const
   const bool odd = E.clock[2] != 0.0;
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    c.f.u[m] = odd ? E.f.up[m] : E.f.u[m];
-    c.f.up[m] = odd ? E.f.u[m] : E.f.up[m];
+    c.f.u[m] = (gdouble*)(odd ? E.f.up[m] : E.f.u[m]);
+    c.f.up[m] = (gdouble*)(odd ? E.f.u[m] : E.f.up[m]);
   }
   c.g.cart = E.cart;
   c.g.tau1 = tau + E.p.h;
   c.g.tau = stage2 ? c.g.tau1 : tau;
   c.tile = t - gt.start[e];
   const int nt = E.tg.ntiles;
-  c.qcur = E.f.quiet + (odd ? nt : 0);
-  c.qnext = E.f.quiet + (odd ? 0 : nt);
-  c.qpi = E.f.quiet + 2 * nt;
+  c.qcur = c.f.quiet + (odd ? nt : 0);
+  c.qnext = c.f.quiet + (odd ? 0 : nt);
+  c.qpi = c.f.quiet + 2 * nt;
   return c;
 }
 
@@ -221,7 +250,7 @@ __device__ __forceinline__ Pos cell_pos(const StepParams& p, const TileGrid& tg,
 // the values its buffers hold.  Returns the block-uniform decision.
 template <int TX, int TY, int TZ>
 __device__ __forceinline__ bool tile_asleep(const StepParams& p, const TileGrid& tg,
-                                            const int* __restrict__ qcur, int tile) {
+                                            const gint* __restrict__ qcur, int tile) {
   if (p.quiet_r[0] <= 0) return false;
   const int tk = tile % tg.ntz, r = tile / tg.ntz;
   const int tj = r % tg.nty, ti = r / tg.nty;
@@ -249,7 +278,7 @@ __device__ __forceinline__ double vacuum_cfl(const StepParams& p, double tauf) {
 
 // pi~ at a cell: PI_SRC 0 -> 0, 1 -> zero where e == 0 (vacuum), 2 -> as stored.
 template <int PI_SRC>
-__device__ __forceinline__ double ld_pi(const double* const* pi, int m, int idx, double e) {
+__device__ __forceinline__ double ld_pi(const gdouble* const* pi, int m, int idx, double e) {
   if (PI_SRC == 0) return 0.0;
   const double v = pi[m][idx];
   if (PI_SRC == 1) return e == 0.0 ? 0.0 : v;
@@ -271,8 +300,8 @@ __device__ __forceinline__ double ld_pi(const double* const* pi, int m, int idx,
 // and F), then T~'s flux.  The arithmetic of every component is that of
 // tau (w u u - P g + pi) and u pi as written, in that order.
 template <typename R, bool DO_T, bool DO_PI, int PI_SRC>
-__device__ __forceinline__ R face_flux_stream(const double* __restrict__ e, const double* const* u,
-                                       const double* const* pi, int base, int a, int n,
+__device__ __forceinline__ R face_flux_stream(const gdouble* __restrict__ e, const gdouble* const* u,
+                                       const gdouble* const* pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
                                        const EosDev& eos, R* out, int F) {
   int idx[4];
@@ -387,8 +416,8 @@ __device__ __forceinline__ R face_flux_stream(const double* __restrict__ e, cons
 // vacuum (all primitives zero) has H = 0 and c = c_vac, so it skips the arithmetic.
 // R is the arithmetic type (double, or float on the mixed-precision path).
 template <typename R, bool DO_T, bool DO_PI, int PI_SRC>
-__device__ __forceinline__ R face_flux_all(const double* __restrict__ e, const double* const* u,
-                                       const double* const* pi, int base, int a, int n,
+__device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const gdouble* const* u,
+                                       const gdouble* const* pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
                                        const EosDev& eos, R* out, int F) {
   int idx[4];
@@ -505,8 +534,8 @@ __device__ __forceinline__ R face_flux_all(const double* __restrict__ e, const d
 // computed once by one thread and staged in LDS (component-major).  Returns
 // max over the computed faces of c / Delta (for the CFL diagnostic).
 template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC>
-__device__ __forceinline__ double tile_divergence(const double* __restrict__ e,
-                                                  const double* const* u, const double* const* pi,
+__device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
+                                                  const gdouble* const* u, const gdouble* const* pi,
                                                   const StepParams& p, const EosDev& eos,
                                                   double tauf, const Pos& q, double R[14],
                                                   RT* lds) {
@@ -655,8 +684,8 @@ __device__ __forceinline__ double utau(double a, double b, double c) {
 // X - u w - w u + u u (u.w) - (1/3)(g - u u)(g:X - u.w) with w^b = u_a X^{ab}
 // (an identity for any symmetric X; pi's transversality is not assumed).
 template <typename R, bool L1>
-__device__ __forceinline__ void pi_source(const double* const* u, const double* const* uE,
-                                          const double* const* uL, const StepParams& p,
+__device__ __forceinline__ void pi_source(const gdouble* const* u, const gdouble* const* uE,
+                                          const gdouble* const* uL, const StepParams& p,
                                           const EosDev& eos, const Geo& g, const Pos& q,
                                           double ec_d, const double pc_d[10], double S_d[10]) {
   const R ec = (R)ec_d;
@@ -794,7 +823,7 @@ __device__ __forceinline__ void regulate(const EosDev& eos, const StepParams& p,
 // ---------------------------------------------------------------------------
 // Workgroup reduction of the diagnostic partials (wave64 shuffles, then LDS).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void block_partials(double v[kNP], double* out, int ntiles, int tile) {
+__device__ __forceinline__ void block_partials(double v[kNP], gdouble* out, int ntiles, int tile) {
   __shared__ double red[kBlock / 64][kNP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -867,7 +896,7 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(const EventDesc* __re
                                                             GroupTable gt) {
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 0);
-  const Fields& f = cx.f;
+  const DFields& f = cx.f;
   const StepParams& p = cx.p;
   const EosDev& eos = cx.eos;
   const Geo& g = cx.g;
@@ -912,7 +941,7 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
                                                     GroupTable gt) {
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 0);
-  const Fields& f = cx.f;
+  const DFields& f = cx.f;
   const StepParams& p = cx.p;
   const EosDev& eos = cx.eos;
   const Geo& g = cx.g;
@@ -999,7 +1028,7 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, L1>()))) void k_stag
     const EventDesc* __restrict__ evs, GroupTable gt) {
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 1);
-  const Fields& f = cx.f;
+  const DFields& f = cx.f;
   const StepParams& p = cx.p;
   const EosDev& eos = cx.eos;
   const Geo& g = cx.g;
@@ -1052,7 +1081,7 @@ __global__ __launch_bounds__(kBlock) void k_stage2_T(const EventDesc* __restrict
                                                      GroupTable gt) {
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 1);
-  const Fields& f = cx.f;
+  const DFields& f = cx.f;
   const StepParams& p = cx.p;
   const EosDev& eos = cx.eos;
   const Geo& g = cx.g;
