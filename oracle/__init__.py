@@ -73,6 +73,10 @@ def load():
     lib.orc_mlp_loss_grad.argtypes = [P, C.c_int, P, P, P, P, P]
     lib.orc_mlp_adam.argtypes = [P, P, P, P, C.c_int, C.c_double, C.c_double, C.c_double,
                                  C.c_double]
+    lib.orc_surface.restype = C.c_long
+    lib.orc_surface.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                P, C.c_double, P, C.c_double, C.c_int, C.c_double, C.c_int, P,
+                                C.c_long]
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_max_threads.restype = C.c_int
     _lib = lib
@@ -259,3 +263,26 @@ def mlp_loss_grad(params, E, M, eps):
 def mlp_adam(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, epsilon=1e-8):
     """In-place Adam step on float64 arrays params, m, v."""
     load().orc_mlp_adam(_p(params), _p(_c(grad)), _p(m), _p(v), int(t), lr, b1, b2, epsilon)
+
+
+SURF_REC = 24
+
+
+def surface(shape, spacing, A, tauA, B, tauB, eps_f, cartesian=False):
+    """Freeze-out surface elements between slices A (tau_A) and B (tau_B) of shape
+    (nf, nx, ny, ne), nf = 4 (e, u~x, u~y, u~eta) or 14 (+ pi~): an (n, 24) array in
+    hypercube order (record layout in surface_oracle.c)."""
+    lib = load()
+    nx, ny, ne = shape
+    A = _c(A)
+    B = _c(B)
+    nf = A.shape[0]
+    assert A.shape == B.shape == (nf, nx, ny, ne)
+    n = lib.orc_surface(nx, ny, ne, *spacing, _p(A), tauA, _p(B), tauB, nf, eps_f, int(cartesian),
+                        None, 0)
+    if n < 0:
+        raise ValueError("orc_surface rejected its arguments")
+    out = np.zeros((max(n, 1), SURF_REC))
+    lib.orc_surface(nx, ny, ne, *spacing, _p(A), tauA, _p(B), tauB, nf, eps_f, int(cartesian),
+                    _p(out), n)
+    return out[:n]

@@ -56,6 +56,7 @@
 static int orc_mutant = 0;
 #define MUT(k) (orc_mutant == (k))
 void orc_set_mutant(int k) { orc_mutant = k; }
+int orc_get_mutant(void) { return orc_mutant; }
 #define NG 2 /* ghost layers per face: the KT stencil reaches i-2 .. i+2 */
 
 /* ------------------------------------------------------------------------ */

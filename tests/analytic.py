@@ -220,3 +220,59 @@ def gubser_viscous_by_weyl(X, L, lambda1_hat, eps_hat0):
     order = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]
     return (float(eps_h / tau ** 4), float(u_up[1]), float(u_up[2]),
             np.array([float(pit[m, n]) for m, n in order]), u_up.detach().numpy().copy())
+
+
+# ---------------------------------------------------------------------------
+# Volumes cut from boxes and simplices by a plane or a linear function.
+# ---------------------------------------------------------------------------
+
+
+def cube_plane_hot_fraction(w):
+    """Fraction of the unit 3-cube where the linear function with corner values
+    w[4 b0 + 2 b1 + b2] is > 0, by inclusion-exclusion over the corners:
+    vol{g0 + sum_i g_i x_i > 0} = sum_v (-1)^(3-|v|) max(0, g(v))^3 / (6 g1 g2 g3),
+    valid for g1 g2 g3 != 0 (the box-spline form of the cut volume).  The
+    alternating sum cancels heavily, so it is evaluated with 60 significant
+    digits (the corner values themselves are taken as exact)."""
+    import mpmath
+    with mpmath.workdps(60):
+        wm = [mpmath.mpf(float(x)) for x in w]
+        g0 = wm[0]
+        g = (wm[4] - wm[0], wm[2] - wm[0], wm[1] - wm[0])
+        assert all(x != 0 for x in g)
+        s = mpmath.mpf(0)
+        for b in range(8):
+            v = ((b >> 2) & 1, (b >> 1) & 1, b & 1)
+            val = g0 + sum(gi * vi for gi, vi in zip(g, v))
+            s += (-1) ** (3 - sum(v)) * max(mpmath.mpf(0), val) ** 3
+        return float(s / (6 * g[0] * g[1] * g[2]))
+
+
+def tet_hot_fraction_dd(v):
+    """Hot fraction of a tetrahedron with a linear function of vertex values v
+    (pairwise distinct), as the divided difference of x_+^3:
+    sum over v_i > 0 of v_i^3 / prod_{j != i} (v_i - v_j)."""
+    s = 0.0
+    for i, vi in enumerate(v):
+        if vi > 0:
+            den = 1.0
+            for j, vj in enumerate(v):
+                if j != i:
+                    den *= vi - vj
+            s += vi ** 3 / den
+    return s
+
+
+def cube_hot_fraction_dd(w):
+    """Mean over the six Kuhn tetrahedra 000 -> +e_p -> +e_q -> 111 of the
+    divided-difference hot fraction (w indexed 4 b0 + 2 b1 + b2)."""
+    import itertools
+    s = 0.0
+    for perm in itertools.permutations(range(3)):
+        b = 0
+        v = [w[0]]
+        for ax in perm:
+            b |= 4 >> ax
+            v.append(w[b])
+        s += tet_hot_fraction_dd(v)
+    return s / 6.0

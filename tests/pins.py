@@ -568,6 +568,173 @@ def pin_gubser_viscous():
     return ok, dict(ratios=r, errs=out)
 
 
+# ---------------------------------------------------------------------------
+# Freeze-out surface finder (Sec. IV surface of constant e_f; surface_oracle.c)
+# ---------------------------------------------------------------------------
+def _slices(fn, shape, spacing, tau, nf=4):
+    """Slice (nf, nx, ny, ne) at time tau with e = fn(tau, X, Y, Eta), zero flow."""
+    g = ics.Grid(*shape, *spacing)
+    X, Y, Et = g.mesh()
+    out = np.zeros((nf,) + tuple(shape))
+    out[0] = fn(tau, X, Y, Et)
+    return out
+
+
+def pin_surface_bjorken():
+    """Ideal Bjorken slices (uniform e = e0 (tau0/tau)^(4/3)) bracketing tau_f: every
+    hypercube gives one element with dSigma = (tau_c V, 0, 0, 0) exactly, tau_c the
+    linear-interpolation crossing, e = e_f at the centre; |tau_c - tau_f| stays
+    within the interpolation bound (e''/2|e'|) h^2/4 ~ 0.3 h^2/tau_f."""
+    e0, tau0, ef = 30.0, 0.6, 0.5
+    tau_f = tau0 * (e0 / ef) ** 0.75
+    shape, sp = (3, 4, 5), (0.3, 0.25, 0.2)
+    fn = lambda t, X, Y, E: A.bjorken_ideal_exact(e0, tau0, t) + 0 * X
+    dev, errs = 0.0, []
+    for h in (0.04, 0.02):
+        tA = tau0 + math.floor((tau_f - tau0) / h) * h
+        tB = tA + h
+        el = O.surface(shape, sp, _slices(fn, shape, sp, tA), tA, _slices(fn, shape, sp, tB), tB, ef)
+        if len(el) != 2 * 3 * 4:
+            return False, dict(n=len(el))
+        pa, pb = fn(tA, 0, 0, 0) - ef, fn(tB, 0, 0, 0) - ef
+        tc = tA + h * (pa / (pa - pb))
+        V = sp[0] * sp[1] * sp[2]
+        dev = max(dev, float(np.max(np.abs(el[:, 1] - tc))), float(np.max(np.abs(el[:, 5] - tc * V))),
+                  float(np.max(np.abs(el[:, 6:9]))), float(np.max(np.abs(el[:, 22] - ef))))
+        errs.append(abs(tc - tau_f) / (h * h))
+    ok = dev < 1e-13 and max(errs) < 0.3 / tau_f
+    return ok, dict(dev=dev, err_over_h2=errs)
+
+
+def pin_surface_plane():
+    """Tilted hyperplanes e = e_f + a.(x - x0) (seeded, Cartesian measure): the PL
+    interpolant is exact, so each element's S_mu must equal V_mu (f_lo - f_hi) with
+    the face fractions from the inclusion-exclusion formula for a cube cut by a
+    plane (to 1e-12 of the face volume: the corner values carry FP64 rounding),
+    point against the gradient (out of the hot side), and the centre must lie on
+    the plane."""
+    rng = np.random.default_rng(7)
+    shape, sp = (6, 5, 4), (0.3, 0.25, 0.2)
+    tA, tB = 1.0, 1.15
+    ext = (tB - tA,) + sp
+    worst, n_el = 0.0, 0
+    for trial in range(4):
+        a = rng.normal(size=4) * np.array([4.0, 1.0, 1.0, 1.0])
+        x0 = np.array([tA + 0.07, 0.05, -0.1, 0.03]) + rng.normal(size=4) * 0.1
+        fn = lambda t, X, Y, E: 1.0 + a[0] * (t - x0[0]) + a[1] * (X - x0[1]) + a[2] * (Y - x0[2]) + a[3] * (E - x0[3])
+        SA, SB = _slices(fn, shape, sp, tA), _slices(fn, shape, sp, tB)
+        el = O.surface(shape, sp, SA, tA, SB, tB, 1.0, cartesian=True)
+        n_el += len(el)
+        cy, cz = shape[1] - 1, shape[2] - 1
+        for r in el:
+            cid = int(r[0])
+            i, j, k = cid // (cy * cz), (cid // cz) % cy, cid % cz
+            phi = np.zeros(16)
+            for c in range(16):
+                S = SB if c & 8 else SA
+                phi[c] = S[0, i + ((c >> 2) & 1), j + ((c >> 1) & 1), k + (c & 1)] - 1.0
+            S_ref = np.zeros(4)
+            for mu in range(4):
+                others = [ax for ax in range(4) if ax != mu]
+                f = []
+                for side in (0, 1):
+                    w = np.zeros(8)
+                    for b in range(8):
+                        bits = {mu: side, others[0]: (b >> 2) & 1, others[1]: (b >> 1) & 1, others[2]: b & 1}
+                        w[b] = phi[sum(bits[ax] << (3 - ax) for ax in range(4))]
+                    f.append(A.cube_plane_hot_fraction(w))
+                V = np.prod([ext[ax] for ax in others])
+                S_ref[mu] = V * (f[0] - f[1])
+            S = r[5:9]
+            scale = max(np.prod(ext) / e for e in ext)  # largest face volume V_mu
+            worst = max(worst, float(np.abs(S - S_ref).max() / scale), abs(r[22] - 1.0))
+            if not (np.dot(S, a) < 0):
+                return False, dict(bad_orientation=r[:9].tolist())
+    ok = worst < 1e-11 and n_el > 100
+    return ok, dict(worst=worst, elements=n_el)
+
+
+def pin_surface_gubser():
+    """Ideal Gubser flow (closed form, q = 1/fm): the isotherm e = e_f found between
+    slices h apart.  Element centres must lie on the exact isotherm (max
+    |e_exact(centre)/e_f - 1|) and S must be parallel to -grad e (1 - cos of the
+    angle), both falling >= 3x from (dx, h) = (0.2, 0.04) to (0.1, 0.02) (measured
+    3.7x and 3.8x) and below 1% on the finer grid (0.42% and 0.41%)."""
+    eps_peak = E.C_SB * 0.4 ** 4
+    ef = 0.15 * eps_peak
+
+    def ex(t, X, Y):
+        e, _, _ = ics.gubser_profile(X, Y, t, q=1.0, eps_peak_tau1=eps_peak)
+        return e
+
+    res = []
+    for n, dx, h in ((41, 0.2, 0.04), (81, 0.1, 0.02)):
+        shape, sp = (n, n, 1), (dx, dx, 0.3)
+        fn = lambda t, X, Y, E: ex(t, X, Y)
+        worst_e, worst_n, cnt = 0.0, 0.0, 0
+        taus = [1.0 + m * h for m in range(int(round(0.8 / h)) + 1)]
+        for tA, tB in zip(taus[:-1], taus[1:]):
+            el = O.surface(shape, sp, _slices(fn, shape, sp, tA), tA, _slices(fn, shape, sp, tB), tB, ef,
+                           cartesian=True)
+            for r in el:
+                t, x, y = r[1], r[2], r[3]
+                if x * x + y * y > 3.0 ** 2:
+                    continue
+                cnt += 1
+                worst_e = max(worst_e, abs(float(ex(t, x, y)) / ef - 1.0))
+                d = 1e-6
+                gr = np.array([(ex(t + d, x, y) - ex(t - d, x, y)) / (2 * d),
+                               (ex(t, x + d, y) - ex(t, x - d, y)) / (2 * d),
+                               (ex(t, x, y + d) - ex(t, x, y - d)) / (2 * d)])
+                S = r[5:8]
+                cos = -np.dot(S, gr) / (np.linalg.norm(S) * np.linalg.norm(gr))
+                worst_n = max(worst_n, 1.0 - cos)
+        res.append((worst_e, worst_n, cnt))
+    r_e, r_n = res[0][0] / res[1][0], res[0][1] / res[1][1]
+    ok = r_e >= 3.0 and r_n >= 3.0 and max(res[1][:2]) < 1e-2 and res[1][2] > 100
+    return ok, dict(r_e=r_e, r_n=r_n, res=res)
+
+
+def pin_surface_closure():
+    """Discrete Gauss theorem: for a lumpy hot region that stays inside the grid,
+    the elements' S summed over all hypercubes equals (hot volume of slice A - hot
+    volume of slice B) e_tau, each slice's hot volume from the Kuhn tetrahedra
+    with the divided-difference formula (independent of the oracle's fractions)."""
+    rng = np.random.default_rng(11)
+    shape, sp = (13, 12, 11), (0.25, 0.25, 0.25)
+    cen = rng.uniform(-0.3, 0.3, size=(4, 3))
+    amp = rng.uniform(0.8, 1.6, size=4)
+
+    def fn(t, X, Y, E):
+        out = 0.0 * X
+        for (cx, cy, ce), a in zip(cen, amp):
+            out = out + a * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2 + (E - ce) ** 2) / (2 * 0.35 ** 2)) / t
+        return out
+
+    tA, tB, ef = 1.0, 1.3, 0.5
+    SA, SB = _slices(fn, shape, sp, tA), _slices(fn, shape, sp, tB)
+    el = O.surface(shape, sp, SA, tA, SB, tB, ef, cartesian=True)
+    tot = el[:, 5:9].sum(axis=0)
+    Vt = sp[0] * sp[1] * sp[2]
+
+    def hot_volume(Sl):
+        v = 0.0
+        nx, ny, ne = shape
+        for i in range(nx - 1):
+            for j in range(ny - 1):
+                for k in range(ne - 1):
+                    w = [Sl[0, i + ((b >> 2) & 1), j + ((b >> 1) & 1), k + (b & 1)] - ef for b in range(8)]
+                    v += A.cube_hot_fraction_dd(w)
+        return v * Vt
+
+    edge = max(float(np.abs(SA[0][[0, -1]]).max()), float(np.abs(SA[0][:, [0, -1]]).max()),
+               float(np.abs(SA[0][:, :, [0, -1]]).max()))
+    ref = np.array([hot_volume(SA) - hot_volume(SB), 0.0, 0.0, 0.0])
+    dev = float(np.abs(tot - ref).max() / abs(ref[0]))
+    ok = edge < ef and dev < 1e-10 and len(el) > 50
+    return ok, dict(dev=dev, tot=tot.tolist(), ref=ref.tolist(), n=len(el))
+
+
 ALL_PINS = {
     "eos": pin_eos,
     "con2prim": pin_con2prim,
@@ -585,4 +752,8 @@ ALL_PINS = {
     "transversality": pin_transversality,
     "lambda1_static": pin_lambda1_static,
     "gubser_viscous": pin_gubser_viscous,
+    "surface_bjorken": pin_surface_bjorken,
+    "surface_plane": pin_surface_plane,
+    "surface_gubser": pin_surface_gubser,
+    "surface_closure": pin_surface_closure,
 }
