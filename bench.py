@@ -211,6 +211,7 @@ def main():
         torch.cuda.synchronize()
         out["paths"] = {"mixed_fp32_fp64": mixed_path(wl, args)}
         out["paths"]["fp64_quiet_skip"] = mixed_path(wl, args, precision=0, quiet=True)
+        out["paths"]["freezeout_surface"] = surface_path(wl)
         out["paths"]["fp64_lambda1"] = mixed_path(wl, args, precision=0, lambda1_hat=-10.0)
         out["paths"]["fp64_lambda1"]["note"] = ("second-order lambda_1 term on, lambda1_hat = -10, "
                                                 "tau_pi = 5 eta/(sT)")
@@ -254,6 +255,58 @@ def mixed_path(wl, args, precision=1, quiet=False, **extra):
     if quiet:
         out["quiet_tiles"], out["tiles"] = K.ktmi_quiet_tiles(g.h)
     return out
+
+
+SURF_BYTES_PER_CELL = 16      # e of both slices
+SURF_BYTES_PER_ELEMENT = 400  # its 192-byte record + 13 other fields x 2 slices of one corner cell
+
+
+def surface_path(wl, warm_steps=10, reps=20, eps_f=0.3):
+    """The freeze-out surface finder on two slices (with pi~) of the workload one
+    step apart, after warm_steps steps; reps timed launches (HIP events on the
+    library's stream).  Algorithmic bytes per launch: 16 B per cell (e of both
+    slices) plus 400 B per element (its record and the other 13 fields of one
+    corner cell in both slices)."""
+    import torch
+
+    import paper_1802_04449_amd as K
+    g = K.Hydro(**wl.params)
+    g.set_eos(wl.eos)
+    if wl.T4 is not None:
+        g.set_initial_conserved(wl.T4)
+    else:
+        g.set_initial(wl.ic)
+    g.step(warm_steps)
+    tA = g.diag()["tau"]
+    A = g.snapshot(True)
+    g.step(1)
+    tB = g.diag()["tau"]
+    B = g.snapshot(True)
+    el = g.surface(A, tA, B, tB, eps_f)
+    n_el = int(el.shape[0])
+    cap = max(n_el, 1)
+    out = torch.empty((cap, K.KTMI_SURF_REC), dtype=torch.float64, device=g.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=g.device)
+    names = K.ktmi_kernel_names()
+    ks = names.index("surface")
+    torch.cuda.synchronize()
+    K.ktmi_set_timing(g.h, True)
+    for _ in range(reps):
+        K.ktmi_surface(g.h, A.data_ptr(), tA, B.data_ptr(), tB, True, eps_f, out.data_ptr(), cap,
+                       cnt.data_ptr())
+    torch.cuda.synchronize()
+    tot, launches = K.ktmi_timing(g.h, ks)
+    K.ktmi_set_timing(g.h, False)
+    avg_ms = tot / launches
+    cubes = (wl.params["nx"] - 1) * (wl.params["ny"] - 1) * (wl.params["ne"] - 1)
+    alg = SURF_BYTES_PER_CELL * wl.ncell + SURF_BYTES_PER_ELEMENT * n_el
+    ach = alg / (avg_ms * 1e-3) / 1e9
+    return {"value": cubes / (avg_ms * 1e-3), "unit": "hypercubes/s", "avg_launch_ms": avg_ms,
+            "launches": launches, "elements": n_el, "eps_f": eps_f,
+            "slices": f"steps {warm_steps} and {warm_steps + 1}, e, u~ and pi~",
+            "roofline": {"bound": "hbm", "kernel": "surface", "achieved": ach,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                         "algorithmic_bytes": alg}}
 
 
 def train_guess(wls, steps_at=(0, 5, 10), train_steps=1500):

@@ -261,6 +261,52 @@ int ktmi_mlp_grad(const float *params, int n, const double *E, const double *M, 
 int ktmi_mlp_adam(float *params, const float *grad, float *m, float *v, int t, float lr, float b1,
                   float b2, float epsilon, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* End of the evolution and the freeze-out surface (Sec. IV; App. A.2).      */
+/* ------------------------------------------------------------------------ */
+
+/* Steps h in chunks of check_every steps until the maximum energy density after
+ * a chunk falls below eps_stop (the freeze-out energy density: App. A.2 stops the
+ * evolution there), or max_steps steps are taken; *taken receives the number of
+ * steps taken (>= 1 when max_steps >= 1).  Reads one diagnostics record per chunk
+ * (a stream synchronisation).  KTMI_EINVAL if max_steps < 0, check_every < 1 or
+ * taken is NULL. */
+int ktmi_step_until(ktmi_handle *h, double eps_stop, int max_steps, int check_every, int *taken);
+
+/* A time slice of h's state for the surface finder: with_pi = 0 gives 4 fields
+ * (e, u~x, u~y, u~eta), 1 gives 14 (then pi~ in the order of KTMI_F_PI, zero in
+ * vacuum), each nx*ny*ne doubles in the cell order of ktmi_read, field after
+ * field.  ktmi_snapshot_doubles returns the size; ktmi_snapshot writes it to the
+ * caller's device buffer dst (async on h's stream). */
+size_t ktmi_snapshot_doubles(const ktmi_handle *h, int with_pi);
+int ktmi_snapshot(ktmi_handle *h, double *dst, int with_pi);
+
+#define KTMI_SURF_REC 24 /* doubles per surface element */
+
+/* Freeze-out surface of constant energy density eps_f between two slices of h's
+ * grid (device buffers from ktmi_snapshot with the same with_pi): A at tau_A and
+ * B at tau_B > tau_A.  Every hypercube of 2x2x2x2 grid points (an axis with one
+ * cell spans its width) whose corners straddle eps_f gives one element: the zero
+ * set of the piecewise-linear interpolant of e - eps_f on the Kuhn triangulation
+ * of the hypercube, with the covector dSigma_mu = sqrt(-g) S_mu pointing out of
+ * the region e > eps_f, S_mu = V_mu (f_lo - f_hi) from the hot volume fractions of
+ * the hypercube's faces normal to mu (divergence theorem; sums over hypercubes
+ * telescope exactly), sqrt(-g) = tau at the element's centre (1 in Cartesian
+ * mode).  Record (KTMI_SURF_REC doubles): [0] hypercube index (i cy + j) cz + k
+ * with cy, cz the hypercube counts along y and eta, [1..4] centre (tau, x, y,
+ * eta_s; the mean of the sign changes along the 32 edges), [5..8] dSigma_mu in
+ * the coordinates (tau, x, y, eta_s), [9..11] u~ and [12..21] pi~ at the centre
+ * (multilinear in the corners; pi~ zero for 4-field slices), [22] e at the
+ * centre, [23] zero.  Records are in increasing hypercube order and reproducible
+ * bit for bit.  The first capacity records go to out (device); *count (device, 8
+ * bytes) receives the number of elements, which may exceed capacity (then call
+ * again with a larger buffer).  Uses scratch in h's workspace (calls on one
+ * handle must not overlap).  Async on h's stream.  KTMI_EINVAL on bad arguments,
+ * KTMI_ESTATE without a bound workspace. */
+int ktmi_surface(ktmi_handle *h, const double *A, double tau_A, const double *B, double tau_B,
+                 int with_pi, double eps_f, double *out, long capacity,
+                 unsigned long long *count);
+
 /* Message of the last error on h (or of the last failed ktmi_create if h is
  * NULL).  Valid until the next call on h. */
 const char *ktmi_last_error(const ktmi_handle *h);

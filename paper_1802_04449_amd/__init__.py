@@ -94,6 +94,11 @@ def _load():
         "ktmi_mlp_grad": (C.c_int, [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, vp, vp, sz,
                                     vp]),
         "ktmi_mlp_adam": (C.c_int, [vp, vp, vp, vp, C.c_int, f, f, f, f, vp]),
+        "ktmi_step_until": (C.c_int, [vp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int)]),
+        "ktmi_snapshot_doubles": (sz, [vp, C.c_int]),
+        "ktmi_snapshot": (C.c_int, [vp, vp, C.c_int]),
+        "ktmi_surface": (C.c_int, [vp, vp, C.c_double, vp, C.c_double, C.c_int, C.c_double, vp,
+                                   C.c_long, vp]),
         "ktmi_last_error": (C.c_char_p, [vp]),
         "ktmi_destroy": (None, [vp]),
     }
@@ -267,6 +272,31 @@ def ktmi_quiet_tiles(h):
     return q.value, t.value
 
 
+KTMI_SURF_REC = 24
+
+
+def ktmi_step_until(h, eps_stop: float, max_steps: int, check_every: int = 1) -> int:
+    taken = C.c_int()
+    _check(lib.ktmi_step_until(h, float(eps_stop), int(max_steps), int(check_every),
+                               C.byref(taken)), h)
+    return taken.value
+
+
+def ktmi_snapshot_doubles(h, with_pi: bool) -> int:
+    return int(lib.ktmi_snapshot_doubles(h, int(bool(with_pi))))
+
+
+def ktmi_snapshot(h, dst_ptr: int, with_pi: bool):
+    _check(lib.ktmi_snapshot(h, C.c_void_p(dst_ptr), int(bool(with_pi))), h)
+
+
+def ktmi_surface(h, A_ptr: int, tau_A: float, B_ptr: int, tau_B: float, with_pi: bool,
+                 eps_f: float, out_ptr: int, capacity: int, count_ptr: int):
+    _check(lib.ktmi_surface(h, C.c_void_p(A_ptr), float(tau_A), C.c_void_p(B_ptr), float(tau_B),
+                            int(bool(with_pi)), float(eps_f), C.c_void_p(out_ptr), int(capacity),
+                            C.c_void_p(count_ptr)), h)
+
+
 def ktmi_harvest(h, E_ptr: int, M_ptr: int, eps_ptr: int):
     _check(lib.ktmi_harvest(h, C.c_void_p(E_ptr), C.c_void_p(M_ptr), C.c_void_p(eps_ptr)), h)
 
@@ -395,6 +425,39 @@ class Hydro:
 
     def set_quiet_skip(self, on=True):
         ktmi_set_quiet_skip(self.h, on)
+
+    def step_until(self, eps_stop, max_steps, check_every=1):
+        """Steps until the maximum energy density falls below eps_stop (checked
+        every check_every steps) or max_steps are taken; returns the steps taken."""
+        return ktmi_step_until(self.h, eps_stop, max_steps, check_every)
+
+    def snapshot(self, with_pi=False):
+        """The current (e, u~[, pi~]) slice as a device tensor (nf, nx, ny, ne)."""
+        t = self.torch
+        nf = 14 if with_pi else 4
+        out = t.empty((nf,) + self.shape, dtype=t.float64, device=self.device)
+        ktmi_snapshot(self.h, out.data_ptr(), with_pi)
+        return out
+
+    def surface(self, A, tau_A, B, tau_B, eps_f, capacity=None):
+        """Freeze-out elements between slices A (tau_A) and B (tau_B): a device
+        tensor (n, KTMI_SURF_REC) in hypercube order (grown once if the first
+        buffer was too small)."""
+        t = self.torch
+        with_pi = A.shape[0] == 14
+        assert A.shape == B.shape and A.is_contiguous() and B.is_contiguous()
+        cap = capacity if capacity is not None else max(1024, self.ncell // 8)
+        count = t.zeros(1, dtype=t.int64, device=self.device)
+        for _ in range(2):
+            out = t.empty((cap, KTMI_SURF_REC), dtype=t.float64, device=self.device)
+            ktmi_surface(self.h, A.data_ptr(), tau_A, B.data_ptr(), tau_B, with_pi, eps_f,
+                         out.data_ptr(), cap, count.data_ptr())
+            self.stream.synchronize()
+            n = int(count.item())
+            if n <= cap:
+                return out[:n]
+            cap = n
+        raise KtmiError("surface element count changed between calls")
 
     def harvest(self):
         """(E, M, eps) of every cell of the current state, device tensors."""

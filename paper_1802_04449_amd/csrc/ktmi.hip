@@ -17,6 +17,7 @@
 
 #include "../../include/ktmi.h"
 #include "ktmi_kernels.hpp"
+#include "ktmi_surface.hpp"
 
 namespace ktmi {
 
@@ -165,13 +166,14 @@ __global__ void k_zero(double* p, int n) {
 // ===========================================================================
 using namespace ktmi;
 
-enum { K_INIT = 0, K_FIRST, K_STAGE1, K_STAGE2PI, K_STAGE2T, K_REDUCE, K_COUNT };
+enum { K_INIT = 0, K_FIRST, K_STAGE1, K_STAGE2PI, K_STAGE2T, K_REDUCE, K_SURFACE, K_COUNT };
 static const char* kKernelNames[K_COUNT] = {"init", "first_estimate", "stage1", "stage2_pi",
-                                            "stage2_T", "reduce"};
+                                            "stage2_T", "reduce", "surface"};
 
 struct ktmi_handle {
   ktmi_desc d;
   std::string err;
+  unsigned long long* surf_blocks = nullptr;  // workspace scratch of the surface finder
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
@@ -604,6 +606,7 @@ size_t ktmi_workspace_bytes(const ktmi_desc* d) {
   bytes += 3 * (size_t)kEosMaxRows * sizeof(float);           // its FP32 copy
   bytes += 4096 + 512;                                         // event table, clock
   bytes += (kMlpDevBytes + 255) / 256 * 256;                   // network parameters
+  bytes += (surface_scratch_words(d->nx, d->ny, d->ne) * 8 + 255) / 256 * 256;  // surface finder
   return bytes;
 }
 
@@ -668,6 +671,7 @@ int ktmi_bind(ktmi_handle* h, void* ws, size_t bytes, void* stream) {
   h->dev_ev = (EventDesc*)rest;
   h->clock = rest + 4096 / 8;
   h->mlp_dev = (float*)(rest + (4096 + 512) / 8);
+  h->surf_blocks = (unsigned long long*)((char*)h->mlp_dev + (kMlpDevBytes + 255) / 256 * 256);
   static_assert(sizeof(EventDesc) <= 4096, "event table slot");
   h->ev_dirty = true;
   h->bound = true;
@@ -907,6 +911,69 @@ int ktmi_read(ktmi_handle* h, int field, double* dst) {
     return fail(h, KTMI_EINVAL, "unknown field id");
   HIP_TRY(h, hipMemcpyAsync(dst, src, nb, hipMemcpyDeviceToDevice, s));
   return KTMI_OK;
+}
+
+int ktmi_step_until(ktmi_handle* h, double eps_stop, int max_steps, int check_every, int* taken) {
+  if (!h) return KTMI_EINVAL;
+  if (!taken || max_steps < 0 || check_every < 1)
+    return fail(h, KTMI_EINVAL, "need taken != NULL, max_steps >= 0, check_every >= 1");
+  *taken = 0;
+  while (*taken < max_steps) {
+    const int n = std::min(check_every, max_steps - *taken);
+    if (int rc = ktmi_step(h, n)) return rc;
+    *taken += n;
+    ktmi_diagnostics d;
+    if (int rc = ktmi_diag(h, &d)) return rc;
+    if (d.eps_max < eps_stop) break;
+  }
+  return KTMI_OK;
+}
+
+size_t ktmi_snapshot_doubles(const ktmi_handle* h, int with_pi) {
+  if (!h) return 0;
+  return (size_t)(with_pi ? 14 : 4) * h->d.nx * h->d.ny * h->d.ne;
+}
+
+int ktmi_snapshot(ktmi_handle* h, double* dst, int with_pi) {
+  if (!h) return KTMI_EINVAL;
+  if (!dst) return fail(h, KTMI_EINVAL, "null destination");
+  const size_t n = (size_t)h->d.nx * h->d.ny * h->d.ne;
+  const int nf = with_pi ? 14 : 4;
+  for (int f = 0; f < nf; ++f) {
+    const int field = f == 0 ? KTMI_F_EPS : (f < 4 ? KTMI_F_UX + f - 1 : KTMI_F_PI + f - 4);
+    if (int rc = ktmi_read(h, field, dst + f * n)) return rc;
+  }
+  return KTMI_OK;
+}
+
+int ktmi_surface(ktmi_handle* h, const double* A, double tau_A, const double* B, double tau_B,
+                 int with_pi, double eps_f, double* out, long capacity,
+                 unsigned long long* count) {
+  if (!h) return KTMI_EINVAL;
+  if (!A || !B || !count || capacity < 0 || (capacity > 0 && !out))
+    return fail(h, KTMI_EINVAL, "null slice, count or output buffer, or capacity < 0");
+  if (!(tau_B > tau_A) || !std::isfinite(eps_f))
+    return fail(h, KTMI_EINVAL, "need tau_B > tau_A and a finite eps_f");
+  if (!h->bound) return fail(h, KTMI_ESTATE, "bind a workspace first");
+  SurfaceArgs a;
+  a.nx = h->d.nx;
+  a.ny = h->d.ny;
+  a.ne = h->d.ne;
+  a.dx = h->d.dx;
+  a.dy = h->d.dy;
+  a.de = h->d.de;
+  a.A = A;
+  a.B = B;
+  a.tauA = tau_A;
+  a.tauB = tau_B;
+  a.nf = with_pi ? 14 : 4;
+  a.eps_f = eps_f;
+  a.cart = h->d.cartesian;
+  a.out = out;
+  a.capacity = capacity;
+  a.count = count;
+  a.blocks = h->surf_blocks;
+  return launch(h, K_SURFACE, [&] { (void)launch_surface(a, h->stream); });
 }
 
 int ktmi_diag(ktmi_handle* h, ktmi_diagnostics* out) {

@@ -17,6 +17,7 @@ constexpr double kHbarc = 0.1973269804;  // GeV fm
 typedef __attribute__((address_space(1))) double gdouble;
 typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) int gint;
+typedef __attribute__((address_space(1))) unsigned long long gullong;
 
 template <typename T>
 __device__ __forceinline__ const __attribute__((address_space(1))) T* gl(const T* p) {
