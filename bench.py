@@ -94,6 +94,8 @@ def main():
                          "the 64-event batch with mixed precision and the learned guess")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (counter calibration)")
+    ap.add_argument("--only-surface", action="store_true",
+                    help="only measure the freeze-out surface finder on the workload (profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -114,6 +116,9 @@ def main():
         return
     wl = {"hotspots": W.hotspots_viscous, "gubser_dense": W.gubser_dense_viscous,
           "large": W.large_event}[args.workload](steps=args.steps)
+    if args.only_surface:
+        print(json.dumps({"workload": wl.name, "freezeout_surface": surface_path(wl)}), flush=True)
+        return
     p = wl.params
     stream = torch.cuda.Stream() if args.graph else None
     train = None
