@@ -77,6 +77,8 @@ def load():
     lib.orc_surface.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                 P, C.c_double, P, C.c_double, C.c_int, C.c_double, C.c_int, P,
                                 C.c_long]
+    lib.orc_spectra.argtypes = [P, C.c_long, C.c_double, C.c_double, C.c_int, P, P,
+                                C.POINTER(C.c_int), P, C.c_int, P, C.c_int, P, C.c_int, P, P]
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_max_threads.restype = C.c_int
     _lib = lib
@@ -286,3 +288,23 @@ def surface(shape, spacing, A, tauA, B, tauB, eps_f, cartesian=False):
     lib.orc_surface(nx, ny, ne, *spacing, _p(A), tauA, _p(B), tauB, nf, eps_f, int(cartesian),
                     _p(out), n)
     return out[:n]
+
+
+def spectra(elements, T, eps_plus_P, species, Y, pt, phi):
+    """Smooth Cooper-Frye spectra dN/(dY pT dpT dphi) (GeV^-2) of the surface elements
+    (n, 24) for species = (mass, dof, stat, mu) arrays: shape (ns, nY, npt, nphi).
+    eps_plus_P = 0 leaves out delta f (formulas in spectra_oracle.c)."""
+    lib = load()
+    el = _c(np.asarray(elements).reshape(-1, SURF_REC))
+    mass, dof, stat, mu = species
+    mass, dof, mu = _c(mass), _c(dof), _c(mu)
+    stat = np.ascontiguousarray(stat, dtype=np.int32)
+    Y, pt, phi = _c(Y), _c(pt), _c(phi)
+    ns = mass.size
+    out = np.zeros((ns, Y.size, pt.size, phi.size))
+    rc = lib.orc_spectra(_p(el), el.shape[0], T, eps_plus_P, ns, _p(mass), _p(dof),
+                         stat.ctypes.data_as(C.POINTER(C.c_int)), _p(mu), Y.size, _p(Y), pt.size,
+                         _p(pt), phi.size, _p(phi), _p(out))
+    if rc != 0:
+        raise ValueError("orc_spectra rejected its arguments")
+    return out

@@ -5,7 +5,7 @@ import os
 import subprocess
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["hydro_oracle.c", "mlp_oracle.c", "surface_oracle.c"]
+SOURCES = ["hydro_oracle.c", "mlp_oracle.c", "surface_oracle.c", "spectra_oracle.c"]
 
 
 def build(verbose: bool = False) -> str:

@@ -735,6 +735,129 @@ def pin_surface_closure():
     return ok, dict(dev=dev, tot=tot.tolist(), ref=ref.tolist(), n=len(el))
 
 
+# ---------------------------------------------------------------------------
+# Smooth Cooper-Frye spectra (Sec. IV, eq. cooper_frye, eqn. feq; spectra_oracle.c)
+# ---------------------------------------------------------------------------
+_PREF = 1.0 / (2.0 * math.pi * E.HBARC) ** 3
+_SPECIES = (np.array([0.14, 0.938, 0.5]), np.array([1.0, 2.0, 3.0]), np.array([-1, 1, 0]),
+            np.zeros(3))
+_Y, _PT, _PHI = np.array([0.0, 0.7]), np.array([0.2, 1.0, 2.5]), np.array([0.0, 1.3, 2.9])
+
+
+def _bjorken_elements(tau, deta, etamax, dS=None, u=(0.0, 0.0, 0.0), pi=None):
+    """One element per eta cell on a constant-tau surface of unit transverse area:
+    dSigma = (tau deta, 0, 0, 0) unless dS (per unit deta) is given."""
+    etas = np.arange(-etamax + 0.5 * deta, etamax, deta)
+    el = np.zeros((etas.size, 24))
+    el[:, 1] = tau
+    el[:, 4] = etas
+    el[:, 5:9] = (np.array([tau, 0, 0, 0]) if dS is None else np.asarray(dS)) * deta
+    el[:, 9:12] = u
+    if pi is not None:
+        el[:, 12:22] = pi
+    return el
+
+
+def _series(stat, fn, nmax=60):
+    """sum_{n>=1} (-stat)^(n-1) fn(n) (one term for Boltzmann statistics)."""
+    if stat == 0:
+        return fn(1)
+    return sum((-stat) ** (n - 1) * fn(n) for n in range(1, nmax + 1))
+
+
+def pin_spectra_bjorken():
+    """Boost-invariant constant-tau surface at rest, no shear: dN/(dY d2pT) =
+    g tau/(2 pi hbarc)^3 sum_n (-sigma)^(n-1) 2 m_T K1(n m_T/T) (Bose, Fermi and
+    Boltzmann species), independent of Y and phi."""
+    from scipy.special import kv
+    T, tau = 0.15, 5.0
+    el = _bjorken_elements(tau, 0.01, 12.0)
+    sp = O.spectra(el, T, 0.0, _SPECIES, _Y, _PT, _PHI)
+    worst = 0.0
+    for s, (m, g, st) in enumerate(zip(*_SPECIES[:3])):
+        for ip, pt in enumerate(_PT):
+            mT = math.hypot(m, pt)
+            ref = g * tau * _PREF * _series(int(st), lambda n: 2 * mT * kv(1, n * mT / T))
+            worst = max(worst, float(np.max(np.abs(sp[s, :, ip, :] / ref - 1.0))))
+    return worst < 1e-9, dict(worst=worst)
+
+
+def pin_spectra_deltaf():
+    """Bjorken shear pi~^xx = pi~^yy = Phi/2, pi~^etaeta = -Phi: the delta f term adds
+    Phi/(2 T^2 (e+P)) sum_n (-sigma)^(n-1) n [pT^2 m_T K1(n z) - 2 m_T^2 T K2(n z)/n], z = m_T/T
+    (f(1 - sigma f) = sum_n (-sigma)^(n-1) n e^{-n x})."""
+    from scipy.special import kv
+    T, tau, Phi, wP = 0.15, 5.0, 0.05, 0.6
+    pi = np.zeros(10)
+    pi[4] = pi[7] = 0.5 * Phi
+    pi[9] = -Phi
+    el = _bjorken_elements(tau, 0.01, 12.0, pi=pi)
+    sp = O.spectra(el, T, wP, _SPECIES, _Y, _PT, _PHI)
+    worst = 0.0
+    for s, (m, g, st) in enumerate(zip(*_SPECIES[:3])):
+        for ip, pt in enumerate(_PT):
+            mT = math.hypot(m, pt)
+            z = mT / T
+            ideal = _series(int(st), lambda n: 2 * mT * kv(1, n * z))
+            corr = _series(int(st), lambda n: n * (pt * pt * mT * kv(1, n * z) -
+                                                   2 * mT * mT * T * kv(2, n * z) / n))
+            ref = g * tau * _PREF * (ideal + Phi / (2 * T * T * wP) * corr)
+            worst = max(worst, float(np.max(np.abs(sp[s, :, ip, :] / ref - 1.0))))
+    return worst < 1e-9, dict(worst=worst)
+
+
+def pin_spectra_flow():
+    """Uniform transverse flow u~ = (gamma v, 0, 0) on the constant-tau surface
+    (Boltzmann): p.u = gamma m_T cosh(Y - eta) - gamma v pT cos phi, so the spectrum is
+    g tau/(2 pi hbarc)^3 2 m_T K1(gamma m_T/T) exp(gamma v pT cos phi / T)."""
+    from scipy.special import kv
+    T, tau, v = 0.15, 5.0, 0.4
+    gam = 1.0 / math.sqrt(1 - v * v)
+    el = _bjorken_elements(tau, 0.01, 12.0, u=(gam * v, 0.0, 0.0))
+    spc = (np.array([0.3]), np.array([1.0]), np.array([0]), np.zeros(1))
+    sp = O.spectra(el, T, 0.0, spc, _Y, _PT, _PHI)
+    worst = 0.0
+    for ip, pt in enumerate(_PT):
+        mT = math.hypot(0.3, pt)
+        for iq, ph in enumerate(_PHI):
+            ref = tau * _PREF * 2 * mT * kv(1, gam * mT / T) * math.exp(gam * v * pt * math.cos(ph) / T)
+            worst = max(worst, float(np.max(np.abs(sp[0, :, ip, iq] / ref - 1.0))))
+    return worst < 1e-9, dict(worst=worst)
+
+
+def pin_spectra_spacelike():
+    """Space-like elements at rest (Boltzmann): dSigma = (0, D, 0, 0) per unit eta gives
+    2 pT cos phi K0(m_T/T) D; dSigma = (0, 0, 0, D) on eta in [a, b] at tau = 3 gives
+    (D / tau)(exp(-z cosh(Y - b)) - exp(-z cosh(Y - a))) T (times g/(2 pi hbarc)^3)."""
+    from scipy.special import kv
+    T, D = 0.15, 0.7
+    spc = (np.array([0.3]), np.array([1.0]), np.array([0]), np.zeros(1))
+    el = _bjorken_elements(2.0, 0.01, 12.0, dS=(0.0, D, 0.0, 0.0))
+    sp = O.spectra(el, T, 0.0, spc, _Y, _PT, _PHI)
+    worst = 0.0
+    for ip, pt in enumerate(_PT):
+        mT = math.hypot(0.3, pt)
+        for iq, ph in enumerate(_PHI):
+            ref = _PREF * 2 * pt * math.cos(ph) * kv(0, mT / T) * D
+            worst = max(worst, float(np.max(np.abs(sp[0, :, ip, iq] - ref)) / (_PREF * D * kv(0, 0.3 / T))))
+    tau, a, b, deta = 3.0, -1.0, 2.0, 0.0005
+    etas = np.arange(a + 0.5 * deta, b, deta)
+    el = np.zeros((etas.size, 24))
+    el[:, 1] = tau
+    el[:, 4] = etas
+    el[:, 8] = D * deta
+    sp = O.spectra(el, T, 0.0, spc, _Y, _PT, _PHI)
+    worst2 = 0.0
+    for iy, Yv in enumerate(_Y):
+        for ip, pt in enumerate(_PT):
+            z = math.hypot(0.3, pt) / T
+            ref = _PREF * (D / tau) * T * (math.exp(-z * math.cosh(Yv - b)) - math.exp(-z * math.cosh(Yv - a)))
+            scale = _PREF * (D / tau) * T * math.exp(-z)
+            worst2 = max(worst2, float(np.max(np.abs(sp[0, iy, ip, :] - ref))) / scale)
+    ok = worst < 1e-9 and worst2 < 1e-6
+    return ok, dict(worst_x=worst, worst_eta=worst2)
+
+
 ALL_PINS = {
     "eos": pin_eos,
     "con2prim": pin_con2prim,
@@ -756,4 +879,8 @@ ALL_PINS = {
     "surface_plane": pin_surface_plane,
     "surface_gubser": pin_surface_gubser,
     "surface_closure": pin_surface_closure,
+    "spectra_bjorken": pin_spectra_bjorken,
+    "spectra_deltaf": pin_spectra_deltaf,
+    "spectra_flow": pin_spectra_flow,
+    "spectra_spacelike": pin_spectra_spacelike,
 }

@@ -14,7 +14,9 @@ Mutants (see MUT(k) in oracle/hydro_oracle.c):
  contracted without the metric; freeze-out surface: 21 flipped face difference
  (S pointing into the hot region), 22 a dropped term of the two-hot-vertex
  tetrahedron fraction, 23 edge crossings measured from the wrong end, 24 the
- one-hot-vertex fraction missing a factor.
+ one-hot-vertex fraction missing a factor; spectra: 25 delta f with (1 + sigma f)
+ instead of (1 - sigma f), 26 p^eta dSigma_eta without the 1/tau of the tilde
+ component, 27 the sign of p^x u^x in p.u.
 Mutant 16 (u* = u^n instead of 2u^n - u^{n-1}) alters only the predicted pi'
 at O(h) and the step at O(h^2), the scheme's own order, so no pin is expected
 to separate it; the GPU-oracle parity tests cover that code path.
@@ -28,7 +30,7 @@ import oracle as O
 
 from . import pins
 
-CAUGHT = list(range(1, 16)) + list(range(17, 25))
+CAUGHT = list(range(1, 16)) + list(range(17, 28))
 
 
 @pytest.mark.parametrize("k", CAUGHT)
