@@ -96,6 +96,8 @@ def main():
                     help="only run a plain device copy of 1 GiB five times (counter calibration)")
     ap.add_argument("--only-surface", action="store_true",
                     help="only measure the freeze-out surface finder on the workload (profiling)")
+    ap.add_argument("--only-spectra", action="store_true",
+                    help="only measure the Cooper-Frye spectra on the workload's surface (profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -118,6 +120,9 @@ def main():
           "large": W.large_event}[args.workload](steps=args.steps)
     if args.only_surface:
         print(json.dumps({"workload": wl.name, "freezeout_surface": surface_path(wl)}), flush=True)
+        return
+    if args.only_spectra:
+        print(json.dumps({"workload": wl.name, "cooper_frye_spectra": spectra_path(wl)}), flush=True)
         return
     p = wl.params
     stream = torch.cuda.Stream() if args.graph else None
@@ -217,6 +222,7 @@ def main():
         out["paths"] = {"mixed_fp32_fp64": mixed_path(wl, args)}
         out["paths"]["fp64_quiet_skip"] = mixed_path(wl, args, precision=0, quiet=True)
         out["paths"]["freezeout_surface"] = surface_path(wl)
+        out["paths"]["cooper_frye_spectra"] = spectra_path(wl)
         out["paths"]["fp64_lambda1"] = mixed_path(wl, args, precision=0, lambda1_hat=-10.0)
         out["paths"]["fp64_lambda1"]["note"] = ("second-order lambda_1 term on, lambda1_hat = -10, "
                                                 "tau_pi = 5 eta/(sT)")
@@ -312,6 +318,56 @@ def surface_path(wl, warm_steps=10, reps=20, eps_f=0.3):
             "roofline": {"bound": "hbm", "kernel": "surface", "achieved": ach,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                          "algorithmic_bytes": alg}}
+
+
+SPECTRA_FLOPS = 52  # FP64 operations per (element, bin) with delta f; exp and 1/x count as one
+
+
+def spectra_path(wl, reps=3, eps_f=0.3, T=0.137):
+    """Smooth Cooper-Frye spectra of the freeze-out surface between steps 10 and 11 on
+    the paper's 41 x 15 x 48 (Y, pT, phi) bins for 8 species (light mesons and
+    baryons), delta f on; reps timed calls (torch events on the call's stream)."""
+    import numpy as np
+    import torch
+
+    import paper_1802_04449_amd as K
+    g = K.Hydro(**wl.params)
+    g.set_eos(wl.eos)
+    if wl.T4 is not None:
+        g.set_initial_conserved(wl.T4)
+    else:
+        g.set_initial(wl.ic)
+    g.step(10)
+    tA = g.diag()["tau"]
+    A = g.snapshot(True)
+    g.step(1)
+    tB = g.diag()["tau"]
+    B = g.snapshot(True)
+    el = g.surface(A, tA, B, tB, eps_f)
+    species = ([0.13957, 0.13498, 0.49368, 0.49761, 0.93827, 0.93957, 1.11568, 1.18937],
+               [1.0, 1.0, 1.0, 1.0, 2.0, 2.0, 2.0, 2.0], [-1, -1, -1, -1, 1, 1, 1, 1], [0.0] * 8)
+    Y = np.linspace(-4.0, 4.0, 41)
+    x, _ = np.polynomial.laguerre.laggauss(15)
+    pt = 0.35 * x
+    u, _ = np.polynomial.legendre.leggauss(48)
+    phi = np.pi * (u + 1.0)
+    wP = eps_f + 0.1  # e + P at the freeze-out density (GeV/fm^3)
+    K.spectra(el, T, wP, species, Y, pt, phi)  # warm-up
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        K.spectra(el, T, wP, species, Y, pt, phi)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    evals = int(el.shape[0]) * 8 * 41 * 15 * 48
+    tfl = evals * SPECTRA_FLOPS / (ms * 1e-3) / 1e12
+    return {"value": evals / (ms * 1e-3), "unit": "element-bin evaluations/s", "ms_per_call": ms,
+            "elements": int(el.shape[0]), "species": 8, "bins": [41, 15, 48],
+            "roofline": {"bound": "alu", "achieved": tfl, "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": tfl / 78.6, "flops_per_evaluation": SPECTRA_FLOPS}}
 
 
 def train_guess(wls, steps_at=(0, 5, 10), train_steps=1500):

@@ -307,6 +307,27 @@ int ktmi_surface(ktmi_handle *h, const double *A, double tau_A, const double *B,
                  int with_pi, double eps_f, double *out, long capacity,
                  unsigned long long *count);
 
+/* Smooth Cooper-Frye spectra (Sec. IV, eq. cooper_frye with f_eq and delta f of
+ * eqn. feq; App. A.2) of n surface records (device, as written by ktmi_surface)
+ * for ns species (host arrays: mass in GeV, degeneracy dof, stat = +1
+ * Fermi-Dirac, -1 Bose-Einstein, 0 Boltzmann, chemical potential mu in GeV) on
+ * the bins Y[nY] x pt[npt] (GeV) x phi[nphi] (host arrays):
+ *   out[((s nY + iy) npt + ip) nphi + iphi] = dN/(dY pT dpT dphi) in GeV^-2
+ *   = dof / (2 pi hbarc)^3 sum_elements p^mu dSigma_mu f (1 + df),
+ * p~ = (m_T cosh(Y - eta_s), pT cos phi, pT sin phi, m_T sinh(Y - eta_s)) at the element's
+ * centre, p^mu dSigma_mu = p~^tau dS_tau + p~^x dS_x + p~^y dS_y + (p~^eta/tau) dS_eta,
+ * f = 1/(exp((p.u - mu)/T) + stat), df = (1 - stat f) p~_a p~_b pi~^{ab} / (2 T^2 e_plus_P)
+ * (eps_plus_P = e + P at freeze-out in GeV/fm^3; 0 leaves delta f out).  out is
+ * device memory; ws is caller-owned device scratch of ktmi_spectra_workspace_bytes
+ * bytes.  The result does not depend on scheduling (fixed summation order).
+ * Synchronises stream once (upload of the small tables), then runs async on it.
+ * KTMI_EINVAL on bad arguments or a short workspace. */
+size_t ktmi_spectra_workspace_bytes(long n, int ns, int nY, int npt, int nphi);
+int ktmi_spectra(const double *elements, long n, double T, double eps_plus_P, int ns,
+                 const double *mass, const double *dof, const int *stat, const double *mu, int nY,
+                 const double *Y, int npt, const double *pt, int nphi, const double *phi,
+                 double *out, void *ws, size_t ws_bytes, void *stream);
+
 /* Message of the last error on h (or of the last failed ktmi_create if h is
  * NULL).  Valid until the next call on h. */
 const char *ktmi_last_error(const ktmi_handle *h);

@@ -99,6 +99,10 @@ def _load():
         "ktmi_snapshot": (C.c_int, [vp, vp, C.c_int]),
         "ktmi_surface": (C.c_int, [vp, vp, C.c_double, vp, C.c_double, C.c_int, C.c_double, vp,
                                    C.c_long, vp]),
+        "ktmi_spectra_workspace_bytes": (sz, [C.c_long, C.c_int, C.c_int, C.c_int, C.c_int]),
+        "ktmi_spectra": (C.c_int, [vp, C.c_long, C.c_double, C.c_double, C.c_int, dp, dp,
+                                   C.POINTER(C.c_int), dp, C.c_int, dp, C.c_int, dp, C.c_int, dp,
+                                   vp, vp, sz, vp]),
         "ktmi_last_error": (C.c_char_p, [vp]),
         "ktmi_destroy": (None, [vp]),
     }
@@ -295,6 +299,47 @@ def ktmi_surface(h, A_ptr: int, tau_A: float, B_ptr: int, tau_B: float, with_pi:
     _check(lib.ktmi_surface(h, C.c_void_p(A_ptr), float(tau_A), C.c_void_p(B_ptr), float(tau_B),
                             int(bool(with_pi)), float(eps_f), C.c_void_p(out_ptr), int(capacity),
                             C.c_void_p(count_ptr)), h)
+
+
+def ktmi_spectra_workspace_bytes(n: int, ns: int, nY: int, npt: int, nphi: int) -> int:
+    return int(lib.ktmi_spectra_workspace_bytes(int(n), int(ns), int(nY), int(npt), int(nphi)))
+
+
+def ktmi_spectra(el_ptr: int, n: int, T: float, eps_plus_P: float, mass, dof, stat, mu, Y, pt, phi,
+                 out_ptr: int, ws_ptr: int, ws_bytes: int, stream_ptr: int):
+    """Pointer-level call: device records, output and workspace; host numpy arrays for
+    the species (mass, dof, stat as int32, mu) and the bins (Y, pt, phi)."""
+    import numpy as np
+    mass, dof, mu, Y, pt, phi = (np.ascontiguousarray(x, dtype=np.float64)
+                                 for x in (mass, dof, mu, Y, pt, phi))
+    stat = np.ascontiguousarray(stat, dtype=np.int32)
+    P = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    rc = lib.ktmi_spectra(C.c_void_p(el_ptr), int(n), float(T), float(eps_plus_P), mass.size,
+                          P(mass), P(dof), stat.ctypes.data_as(C.POINTER(C.c_int)), P(mu), Y.size,
+                          P(Y), pt.size, P(pt), phi.size, P(phi), C.c_void_p(out_ptr),
+                          C.c_void_p(ws_ptr), int(ws_bytes), C.c_void_p(stream_ptr))
+    if rc != 0:
+        raise KtmiError(f"ktmi_spectra failed ({rc})")
+
+
+def spectra(elements, T, eps_plus_P, species, Y, pt, phi, stream=None):
+    """Smooth Cooper-Frye spectra of device surface records (torch tensor (n, 24)):
+    a device tensor (ns, nY, npt, nphi) of dN/(dY pT dpT dphi) in GeV^-2.
+    species = (mass, dof, stat, mu) sequences; Y, pt, phi sequences (host)."""
+    import numpy as np
+    import torch
+    mass, dof, stat, mu = species
+    ns, nY, npt, nphi = len(mass), len(Y), len(pt), len(phi)
+    el = elements.contiguous()
+    n = int(el.shape[0])
+    dev = el.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    nb = ktmi_spectra_workspace_bytes(n, ns, nY, npt, nphi)
+    ws = torch.empty(nb // 8 + 1, dtype=torch.float64, device=dev)
+    out = torch.empty((ns, nY, npt, nphi), dtype=torch.float64, device=dev)
+    ktmi_spectra(el.data_ptr() if n else 0, n, T, eps_plus_P, mass, dof, stat, mu, Y, pt, phi,
+                 out.data_ptr(), ws.data_ptr(), nb, st.cuda_stream)
+    return out
 
 
 def ktmi_harvest(h, E_ptr: int, M_ptr: int, eps_ptr: int):

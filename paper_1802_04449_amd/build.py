@@ -2,7 +2,8 @@
 
 The stencil passes are compiled per (pass, arithmetic type) from
 csrc/ktmi_stencil.hip, in parallel with the host file, the network kernels and
-the freeze-out surface finder, then linked into one shared library.  Objects go to _build/ next to this file.
+the freeze-out surface finder, and the spectra kernels, then linked into one shared library.  Objects go to
+_build/ next to this file.
 """
 from __future__ import annotations
 
@@ -30,7 +31,8 @@ NUM_PASSES = 8  # first estimate, stage1 (viscous, ideal), stage2 pi, stage2 T (
 def _jobs():
     jobs = [("ktmi", os.path.join(CSRC, "ktmi.hip"), []),
             ("ktmi_mlp", os.path.join(CSRC, "ktmi_mlp.hip"), []),
-            ("ktmi_surface", os.path.join(CSRC, "ktmi_surface.hip"), [])]
+            ("ktmi_surface", os.path.join(CSRC, "ktmi_surface.hip"), []),
+            ("ktmi_spectra", os.path.join(CSRC, "ktmi_spectra.hip"), [])]
     for p in range(NUM_PASSES):
         for rt, tag in (("double", "f64"), ("float", "f32")):
             jobs.append((f"stencil_p{p}_{tag}", os.path.join(CSRC, "ktmi_stencil.hip"),
