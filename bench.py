@@ -35,13 +35,16 @@ BYTES_PER_CELL_IDEAL = {"stage1": (8 + 5) * 8, "stage2_T": (8 + 4) * 8}
 
 
 def source_sha256() -> str:
-    """Hash of the kernel sources: counter-derived traffic recorded under
-    profiles/ is used only while it matches the code being timed."""
-    import glob
+    """Hash of everything the step's stencil kernels are compiled from (their
+    sources, the headers they include and the build flags): counter-derived
+    traffic recorded under profiles/ is used only while it matches the code
+    being timed."""
     import hashlib
-    csrc = os.path.join(ROOT, "paper_1802_04449_amd", "csrc")
-    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp")))
-    files.append(os.path.join(ROOT, "include", "ktmi.h"))
+    pkg = os.path.join(ROOT, "paper_1802_04449_amd")
+    csrc = os.path.join(pkg, "csrc")
+    files = [os.path.join(csrc, f) for f in ("ktmi_stencil.hip", "ktmi_kernels.hpp",
+                                             "ktmi_device.hpp", "ktmi_mlp.hpp")]
+    files += [os.path.join(ROOT, "include", "ktmi.h"), os.path.join(pkg, "build.py")]
     h = hashlib.sha256()
     for f in files:
         h.update(os.path.basename(f).encode())

@@ -29,7 +29,12 @@ namespace ktmi {
 namespace {
 
 constexpr int kSpecBlock = 256;
-constexpr int kPhi = 8;     // phi bins per thread
+#ifndef KTMI_SPEC_PHI
+#define KTMI_SPEC_PHI 16
+#endif
+// phi bins per thread; on the 201x201x105 benchmark surface (41660 elements, 8
+// species, 41 x 15 x 48 bins): 4 -> 30.0 ms, 8 -> 24.4 ms, 16 -> 23.7 ms
+constexpr int kPhi = KTMI_SPEC_PHI;
 constexpr int kChunk = 128; // elements per LDS chunk
 constexpr int kElemVals = 20;
 
