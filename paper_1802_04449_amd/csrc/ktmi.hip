@@ -54,18 +54,21 @@ __global__ __launch_bounds__(kBlock) void k_init_primitive(Fields f, StepParams 
 }
 
 // Folds the partials of stage1 and stage2T into the accumulated diagnostics.
-// One workgroup per slot; each folds the slot's partials in a fixed order.
+// One workgroup of kRedBlock threads per slot; each folds the slot's partials
+// in a fixed order (thread t takes tiles t, t + kRedBlock, ...; then the waves
+// and the workgroup in order).
 // acc: 0 geo_src, 1 max_cfl, 2 solves, 3 iter_sum, 4 iter_max, 5 fallbacks,
 //      6 nonconv, 7 nans, 8 clamps, 9 eps_max, 10 sum_Ttt, 11 vacuum.
-__global__ __launch_bounds__(kBlock) void k_reduce(const EventDesc* __restrict__ evs) {
-  __shared__ double sh[2][kBlock / 64];
+constexpr int kRedBlock = 1024;
+__global__ __launch_bounds__(kRedBlock) void k_reduce(const EventDesc* __restrict__ evs) {
+  __shared__ double sh[2][kRedBlock / 64];
   const int e = blockIdx.x / kNP, s = blockIdx.x % kNP;
   const EventDesc& E = evs[e];
   const int nblk = E.tg.ntiles;
-  const double* part = E.f.partial;
+  const gdouble* part = (const gdouble*)E.f.partial;
   const bool mx = is_max_slot(s);
   double x = 0.0, y = 0.0;  // stage1, stage2T
-  for (int b = threadIdx.x; b < nblk; b += kBlock) {
+  for (int b = threadIdx.x; b < nblk; b += kRedBlock) {
     const double a = part[(size_t)s * nblk + b];
     const double c = part[(size_t)(kNP + s) * nblk + b];
     x = mx ? fmax(x, a) : x + a;
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const EventDesc* __restrict__
   if (threadIdx.x != 0) return;
   x = sh[0][0];
   y = sh[1][0];
-  for (int w = 1; w < kBlock / 64; ++w) {
+  for (int w = 1; w < kRedBlock / 64; ++w) {
     x = mx ? fmax(x, sh[0][w]) : x + sh[0][w];
     y = mx ? fmax(y, sh[1][w]) : y + sh[1][w];
   }
@@ -489,7 +492,7 @@ static int enqueue_step(ktmi_handle* h) {
                               h->dev_ev, gt);
   if (rc) return rc;
   return launch(h, K_REDUCE, [&] {
-    hipLaunchKernelGGL(k_reduce, dim3(kNP), dim3(kBlock), 0, h->stream, h->dev_ev);
+    hipLaunchKernelGGL(k_reduce, dim3(kNP), dim3(kRedBlock), 0, h->stream, h->dev_ev);
   });
 }
 
@@ -571,7 +574,7 @@ static int enqueue_group_step(ktmi_group* g) {
     if (rc) return group_fail(g, rc, h->err);
   }
   const int nev = (int)g->hs.size();
-  hipLaunchKernelGGL(k_reduce, dim3(kNP * nev), dim3(kBlock), 0, g->stream, g->dev);
+  hipLaunchKernelGGL(k_reduce, dim3(kNP * nev), dim3(kRedBlock), 0, g->stream, g->dev);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return group_fail(g, KTMI_EHIP, hipGetErrorString(e));
   return KTMI_OK;
