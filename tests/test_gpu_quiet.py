@@ -50,6 +50,17 @@ def test_quiet_skip_matches_full_computation(viscous, cartesian):
     assert 0 < q < n, (q, n)
 
 
+@pytest.mark.parametrize("kw", [dict(lambda1_hat=-10.0, taupi_coef=7.5), dict(precision=1)])
+def test_quiet_skip_second_order_and_mixed(kw):
+    """Skipping with the lambda_1 kernels and with the mixed-precision kernels:
+    bitwise equal to the same variant without skipping."""
+    print(f"[gpu-case] quiet skip {kw}", flush=True)
+    wl = W.hotspots_viscous(nx=61, ny=61, ne=9, dx=0.35, dy=0.35, de=0.5, steps=100, seed=33)
+    a = _run(wl, 100, False, **kw)
+    b = _run(wl, 100, True, **kw)
+    _same(a, b, f"quiet skip {kw}")
+
+
 def test_quiet_skip_grouped_graph():
     """Three events (one ideal) stepped as a group replayed from a graph, with
     skipping on, against plain single runs without it."""
