@@ -141,3 +141,52 @@ def test_learned_guess_argument_checks():
             K.ktmi_harvest(h, 8, 8, 8)
     finally:
         K.ktmi_destroy(h)
+
+
+def test_freezeout_and_spectra_argument_checks():
+    """Surface, stop and spectra entry points reject bad arguments before touching
+    a device (a handle without a workspace, short workspaces, bad statistics)."""
+    import ctypes as C
+
+    import numpy as np
+
+    import paper_1802_04449_amd as K
+    lib = K.lib
+    h = K.ktmi_create(_desc())
+    try:
+        assert K.ktmi_snapshot_doubles(h, False) == 4 * 8 * 8 * 4
+        assert K.ktmi_snapshot_doubles(h, True) == 14 * 8 * 8 * 4
+        taken = C.c_int()
+        assert lib.ktmi_step_until(h, 1.0, -1, 1, C.byref(taken)) == K.KTMI_EINVAL
+        assert lib.ktmi_step_until(h, 1.0, 5, 0, C.byref(taken)) == K.KTMI_EINVAL
+        assert lib.ktmi_step_until(h, 1.0, 5, 1, None) == K.KTMI_EINVAL
+        # no slices, reversed times, a non-finite threshold, then no workspace
+        assert lib.ktmi_surface(h, None, 1.0, 8, 2.0, 0, 0.3, 8, 4, 8) == K.KTMI_EINVAL
+        assert lib.ktmi_surface(h, 8, 2.0, 8, 1.0, 0, 0.3, 8, 4, 8) == K.KTMI_EINVAL
+        assert lib.ktmi_surface(h, 8, 1.0, 8, 2.0, 0, float("nan"), 8, 4, 8) == K.KTMI_EINVAL
+        assert lib.ktmi_surface(h, 8, 1.0, 8, 2.0, 0, 0.3, None, 4, 8) == K.KTMI_EINVAL
+        assert lib.ktmi_surface(h, 8, 1.0, 8, 2.0, 0, 0.3, 8, 4, 8) == K.KTMI_ESTATE
+    finally:
+        K.ktmi_destroy(h)
+    assert K.ktmi_spectra_workspace_bytes(-1, 1, 1, 1, 1) == 0
+    assert K.ktmi_spectra_workspace_bytes(100, 0, 1, 1, 1) == 0
+    nb = K.ktmi_spectra_workspace_bytes(1000, 2, 41, 15, 48)
+    assert nb >= 2 * 41 * 15 * 48 * 8
+    args = dict(mass=[0.14, 0.94], dof=[1, 2], stat=[-1, 1], mu=[0, 0], Y=np.zeros(41),
+                pt=np.ones(15), phi=np.ones(48))
+
+    def call(**kw):
+        a = dict(args)
+        a.update(kw)
+        try:
+            K.ktmi_spectra(8, kw.pop("n", 1000), kw.pop("T", 0.15), 0.0, a["mass"], a["dof"],
+                           a["stat"], a["mu"], a["Y"], a["pt"], a["phi"], 8, 8,
+                           kw.pop("ws_bytes", nb), 0)
+        except K.KtmiError as e:
+            return str(e)
+        return "ok?"
+
+    assert "failed" in call(ws_bytes=nb - 8)          # short workspace
+    assert "failed" in call(T=0.0)                    # T must be > 0
+    assert "failed" in call(stat=[-1, 2])             # statistics in {-1, 0, 1}
+    assert "failed" in call(mass=[0.14, -1.0])        # negative mass
