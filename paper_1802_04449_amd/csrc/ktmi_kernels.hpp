@@ -424,6 +424,9 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
                                        const gdouble* const* pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
                                        const EosDev& eos, R* out, int F) {
+  // limiter form: the sign-test one in the T-only pass (its register count sets
+  // its occupancy), the min/max one elsewhere
+  constexpr bool kMinMax = !(DO_T && !DO_PI);
   int idx[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) idx[t] = base + clampi(a - 1 + t, 0, n - 1) * stride;
@@ -482,8 +485,8 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
 #pragma unroll
   for (int v = 0; v < 14; ++v) {
     const R a0 = q4[v][0], a1 = q4[v][1], a2 = q4[v][2], a3 = q4[v][3];
-    qL[v] = a1 + R(0.5) * mm_slope_r<R>(th, a0, a1, a2);
-    qR[v] = a2 - R(0.5) * mm_slope_r<R>(th, a1, a2, a3);
+    qL[v] = a1 + R(0.5) * mm_slope_r<R, kMinMax>(th, a0, a1, a2);
+    qR[v] = a2 - R(0.5) * mm_slope_r<R, kMinMax>(th, a1, a2, a3);
   }
   // Scalars of the two states first (u~^tau, P, c_s^2, e + P, speed), then each
   // flux component from them and the face states, straight to LDS: only the
