@@ -210,9 +210,9 @@ __device__ inline Prim con2prim(const EosDev& q, const StepParams& p, double E, 
     }
     double P, dP;
     eos_p_dp(q, x, P, dP);
-    const double w = E + P;
-    const double f = x - E + M2 / w;
-    const double df = 1.0 - M2 * dP / (w * w);
+    const double r = 1.0 / (E + P);  // one division for f and f'
+    const double f = x - E + M2 * r;
+    const double df = 1.0 - M2 * dP * r * r;
     if (f == 0.0) {
       conv = true;
       break;
@@ -240,9 +240,9 @@ __device__ inline Prim con2prim(const EosDev& q, const StepParams& p, double E, 
   {
     double P, dP;
     eos_p_dp(q, x, P, dP);
-    const double w = E + P;
-    const double f = x - E + M2 / w;
-    const double df = 1.0 - M2 * dP / (w * w);
+    const double r = 1.0 / (E + P);
+    const double f = x - E + M2 * r;
+    const double df = 1.0 - M2 * dP * r * r;
     const double xp = x - f / df;
     if (xp >= lo0 && xp <= hi0) x = xp;
   }
@@ -376,17 +376,18 @@ __device__ __forceinline__ R mm_slope_r(R th, R qm, R q0, R qp) {
   return minmod3_r<R, MINMAX>(th * (q0 - qm), R(0.5) * (qp - qm), th * (qp - q0));
 }
 
+// Largest |eigenvalue| of the ideal flux Jacobian along the face normal,
+// [|v_d|(1 - cs2) + cs sqrt((1 - v^2)(1 - v^2 cs2 - v_d^2 (1 - cs2)))] / (1 - v^2 cs2)
+// with v = u~/u~^tau, multiplied through by (u~^tau)^2 (1 + |u~|^2 = (u~^tau)^2):
+// [|u~_d| (1 - cs2) u~^tau + sqrt(cs2 (1 + u~_perp^2 (1 - cs2)))] / (1 + |u~|^2 (1 - cs2)),
+// one division and a discriminant that cannot go negative.
 template <typename R>
 __device__ __forceinline__ R local_speed_r(R ut, R ux, R uy, R ue, R ud, R cs2) {
-  const R inv = R(1) / ut;
-  const R vd = ud * inv;
-  const R v2 = (ux * ux + uy * uy + ue * ue) * inv * inv;
-  R disc = inv * inv * (R(1) - v2 * cs2 - vd * vd * (R(1) - cs2));
-  disc = disc < R(0) ? R(0) : disc;
-  const R root = sqrt(cs2 * disc);
-  const R inv_den = R(1) / (R(1) - v2 * cs2);
-  const R a = vd * (R(1) - cs2);
-  return (fabs(a) + root) * inv_den;
+  const R w = R(1) - cs2;
+  const R u2 = ux * ux + uy * uy + ue * ue;
+  const R up2 = u2 - ud * ud;  // transverse part (>= 0 up to rounding)
+  const R disc = R(1) + (up2 > R(0) ? up2 : R(0)) * w;
+  return (fabs(ud) * w * ut + sqrt(cs2 * disc)) / (R(1) + u2 * w);
 }
 
 // pi~ component index of the symmetric pair (mu, nu).
