@@ -355,32 +355,20 @@ __device__ __forceinline__ void eos_p_t_r<float>(const EosDev& q, float e, float
   T = gl(q.Tf)[i] + f * (gl(q.Tf)[i + 1] - gl(q.Tf)[i]);
 }
 
-// min of the three if all are positive, max if all are negative, else 0.  Two
-// forms with the same value for finite arguments: MINMAX goes through the min
-// and max of the three (fewer instructions), the other tests each argument's
-// sign (fewer live registers in the pass that is register-bound).
-template <typename R, bool MINMAX>
+// min of the three if all are positive, max if all are negative, else 0,
+// written through the min and max of the three (fewer instructions than a sign
+// test of each argument; the same value for finite arguments).
+template <typename R>
 __device__ __forceinline__ R minmod3_r(R a, R b, R c) {
-  if constexpr (MINMAX) {
-    const R lo = fmin(a, fmin(b, c)), hi = fmax(a, fmax(b, c));
-    return lo > R(0) ? lo : (hi < R(0) ? hi : R(0));
-  } else {
-    if (a > R(0) && b > R(0) && c > R(0)) return fmin(a, fmin(b, c));
-    if (a < R(0) && b < R(0) && c < R(0)) return fmax(a, fmax(b, c));
-    return R(0);
-  }
+  const R lo = fmin(a, fmin(b, c)), hi = fmax(a, fmax(b, c));
+  return lo > R(0) ? lo : (hi < R(0) ? hi : R(0));
 }
 
-template <typename R, bool MINMAX = true>
+template <typename R>
 __device__ __forceinline__ R mm_slope_r(R th, R qm, R q0, R qp) {
-  return minmod3_r<R, MINMAX>(th * (q0 - qm), R(0.5) * (qp - qm), th * (qp - q0));
+  return minmod3_r<R>(th * (q0 - qm), R(0.5) * (qp - qm), th * (qp - q0));
 }
 
-// Largest |eigenvalue| of the ideal flux Jacobian along the face normal,
-// [|v_d|(1 - cs2) + cs sqrt((1 - v^2)(1 - v^2 cs2 - v_d^2 (1 - cs2)))] / (1 - v^2 cs2)
-// with v = u~/u~^tau, multiplied through by (u~^tau)^2 (1 + |u~|^2 = (u~^tau)^2):
-// [|u~_d| (1 - cs2) u~^tau + sqrt(cs2 (1 + u~_perp^2 (1 - cs2)))] / (1 + |u~|^2 (1 - cs2)),
-// one division and a discriminant that cannot go negative.
 template <typename R>
 __device__ __forceinline__ R local_speed_r(R ut, R ux, R uy, R ue, R ud, R cs2) {
   const R w = R(1) - cs2;

@@ -424,9 +424,6 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
                                        const gdouble* const* pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
                                        const EosDev& eos, R* out, int F) {
-  // limiter form: the sign-test one in the T-only pass (its register count sets
-  // its occupancy), the min/max one elsewhere
-  constexpr bool kMinMax = !(DO_T && !DO_PI);
   int idx[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) idx[t] = base + clampi(a - 1 + t, 0, n - 1) * stride;
@@ -485,8 +482,8 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
 #pragma unroll
   for (int v = 0; v < 14; ++v) {
     const R a0 = q4[v][0], a1 = q4[v][1], a2 = q4[v][2], a3 = q4[v][3];
-    qL[v] = a1 + R(0.5) * mm_slope_r<R, kMinMax>(th, a0, a1, a2);
-    qR[v] = a2 - R(0.5) * mm_slope_r<R, kMinMax>(th, a1, a2, a3);
+    qL[v] = a1 + R(0.5) * mm_slope_r<R>(th, a0, a1, a2);
+    qR[v] = a2 - R(0.5) * mm_slope_r<R>(th, a1, a2, a3);
   }
   // Scalars of the two states first (u~^tau, P, c_s^2, e + P, speed), then each
   // flux component from them and the face states, straight to LDS: only the
@@ -669,11 +666,11 @@ constexpr int lds_doubles() {
   return 14 * m;
 }
 
-// Waves per SIMD asked of stage2_pi: 3 where the tile's LDS leaves room for
-// three workgroups per CU (160 KB), else no bound.  Capping its registers for
-// a third wave is a net gain for this pass (10-16% on the 201x201x105 grids);
-// stage1 and stage2_T lose from the same cap (spills), so they have none, nor
-// has the lambda_1 variant of stage2_pi (it would spill under the cap).
+// Waves per SIMD asked of the stage-2 passes: 3 where the tile's LDS leaves
+// room for three workgroups per CU (160 KB), else no bound.  Capping their
+// registers for a third wave is a net gain (stage2_pi 10-16%, stage2_T 1-5% on
+// the 201x201x105 grids, with a few spilled registers); stage1 loses from the
+// same cap, so it has none, nor has the lambda_1 variant of stage2_pi.
 template <typename RT, int TX, int TY, int TZ, bool L1>
 constexpr int pi_waves() {
   return !L1 && 163840 / (int)(lds_doubles<TX, TY, TZ>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
@@ -1088,7 +1085,8 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, L1>()))) void k_stag
 // Stage 2, part 2 (tau_{n+1}): T^{n+1} = T^n + [(T' - T^n) + h R_T(e', u', pi^{n+1})]/2,
 // root solve -> (e, u~)^{n+1} (written over e^n and u~^{n-1}), diagnostics.
 template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET>
-__global__ __launch_bounds__(kBlock) void k_stage2_T(const EventDesc* __restrict__ evs,
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, false>()))) void k_stage2_T(const EventDesc* __restrict__ evs,
                                                      GroupTable gt) {
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 1);
