@@ -356,12 +356,13 @@ __device__ __forceinline__ void eos_p_t_r<float>(const EosDev& q, float e, float
 }
 
 // min of the three if all are positive, max if all are negative, else 0,
-// written through the min and max of the three (fewer instructions than a sign
-// test of each argument; the same value for finite arguments).
+// written as max(lo, 0) + min(hi, 0) with lo, hi the min and max of the three
+// (no compares or selects; the same value for finite arguments, up to the sign
+// of a zero result).
 template <typename R>
 __device__ __forceinline__ R minmod3_r(R a, R b, R c) {
   const R lo = fmin(a, fmin(b, c)), hi = fmax(a, fmax(b, c));
-  return lo > R(0) ? lo : (hi < R(0) ? hi : R(0));
+  return fmax(lo, R(0)) + fmin(hi, R(0));
 }
 
 template <typename R>
