@@ -19,6 +19,7 @@ FIELDS = {"eps": 0, "ux": 1, "uy": 2, "ue": 3}
 FIELDS.update({f"pi{m}": 4 + m for m in range(10)})
 FIELDS.update({f"T{m}": 14 + m for m in range(4)})
 FIELDS.update({"uprev_x": 18, "uprev_y": 19, "uprev_e": 20})
+FIELDS.update({"Pi": 21, "nb": 22})  # bulk pressure, net-baryon density
 
 
 class _Params(C.Structure):
@@ -28,7 +29,8 @@ class _Params(C.Structure):
                 ("viscous", C.c_int), ("cartesian", C.c_int),
                 ("eps_cut", C.c_double), ("theta", C.c_double), ("newton_tol", C.c_double),
                 ("newton_maxit", C.c_int), ("pi_reg", C.c_double),
-                ("taupi_coef", C.c_double), ("lambda1_hat", C.c_double)]
+                ("taupi_coef", C.c_double), ("lambda1_hat", C.c_double),
+                ("zetas", C.c_double), ("taubulk_coef", C.c_double), ("baryon", C.c_int)]
 
 
 class _Diag(C.Structure):
@@ -57,6 +59,7 @@ def load():
     lib.orc_set_eos_conformal.argtypes = [C.c_void_p, C.c_double]
     lib.orc_set_eos_table.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, P, P, P]
     lib.orc_set_initial_primitive.argtypes = [C.c_void_p, P, P, P, P, P]
+    lib.orc_set_initial_primitive_ext.argtypes = [C.c_void_p, P, P, P, P, P, P, P]
     lib.orc_set_initial_conserved.argtypes = [C.c_void_p, P, P]
     lib.orc_step.argtypes = [C.c_void_p, C.c_int]
     lib.orc_read.argtypes = [C.c_void_p, C.c_int, P]
@@ -64,6 +67,8 @@ def load():
     lib.orc_eos_eval.argtypes = [C.c_void_p, C.c_int, P, P, P, P, P]
     lib.orc_con2prim.argtypes = [C.c_void_p, C.c_int, P, P, P, P, C.POINTER(C.c_int),
                                  C.POINTER(C.c_int)]
+    lib.orc_con2prim_bulk.argtypes = [C.c_void_p, C.c_int, P, P, P, P, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]
     lib.orc_prim2K.argtypes = [C.c_void_p, C.c_int, P, P, P]
     lib.orc_local_speed.argtypes = [C.c_int, P, C.c_int, P, P]
     lib.orc_shear_at.argtypes = [C.c_void_p, P, P, P, C.c_double, C.c_int, C.c_int, C.c_int, P]
@@ -128,12 +133,16 @@ class Params:
     pi_reg: float = 1.0
     taupi_coef: float = 5.0
     lambda1_hat: float = 0.0
+    zetas: float = 0.0         # zeta/s of the bulk pressure (0: no bulk)
+    taubulk_coef: float = 5.0  # tau_Pi = taubulk_coef (zeta/s) hbarc / T
+    baryon: bool = False       # transport the net-baryon density
 
     def c(self):
         return _Params(self.nx, self.ny, self.ne, self.dx, self.dy, self.de, self.tau0, self.h,
                        self.etas, int(self.viscous), int(self.cartesian), self.eps_cut,
                        self.theta, self.newton_tol, self.newton_maxit, self.pi_reg,
-                       self.taupi_coef, self.lambda1_hat)
+                       self.taupi_coef, self.lambda1_hat, self.zetas, self.taubulk_coef,
+                       int(self.baryon))
 
 
 class Oracle:
@@ -171,7 +180,9 @@ class Oracle:
         e, ux, uy, ue = (_c(ic[k]).reshape(-1) for k in ("eps", "ux", "uy", "ue"))
         pi = ic.get("pi")
         pi = None if pi is None else _c(pi).reshape(10, -1)
-        rc = self.lib.orc_set_initial_primitive(self.h, _p(e), _p(ux), _p(uy), _p(ue), _p(pi))
+        Pi, nb = (None if ic.get(k) is None else _c(ic[k]).reshape(-1) for k in ("Pi", "nb"))
+        rc = self.lib.orc_set_initial_primitive_ext(self.h, _p(e), _p(ux), _p(uy), _p(ue), _p(pi),
+                                                    _p(Pi), _p(nb))
         assert rc == 0
 
     def set_initial_conserved(self, T4, pi=None):
@@ -214,6 +225,20 @@ class Oracle:
         self.lib.orc_con2prim(self.h, n, _p(K), _p(g), _p(e), _p(u),
                               it.ctypes.data_as(C.POINTER(C.c_int)),
                               fl.ctypes.data_as(C.POINTER(C.c_int)))
+        return e, u, it, fl
+
+    def con2prim_bulk(self, K, Pi):
+        """Root solve of K = (e+P+Pi) u~^tau u~ - (P+Pi) g~^{tau .} for (e, u~)."""
+        K = _c(K).reshape(-1, 4)
+        Pi = _c(Pi).reshape(-1)
+        n = K.shape[0]
+        e = np.empty(n)
+        u = np.empty((n, 3))
+        it = np.empty(n, dtype=np.int32)
+        fl = np.empty(n, dtype=np.int32)
+        self.lib.orc_con2prim_bulk(self.h, n, _p(K), _p(Pi), _p(e), _p(u),
+                                   it.ctypes.data_as(C.POINTER(C.c_int)),
+                                   fl.ctypes.data_as(C.POINTER(C.c_int)))
         return e, u, it, fl
 
     def shear_at(self, uE, uL, u, tau, i, j, k):

@@ -38,7 +38,18 @@
  *    (e = 0, u~ = 0, and pi~ = 0 at the end of the step);
  *  - the second-order coefficient lambda_1 of eqn. pimn is lambda1_hat / e, the
  *    scaling of Sec. V.C (lambda1_hat = 0 gives the equations of Sec. II), and
- *    tau_pi = taupi_coef (eta/s) hbarc / T with taupi_coef = 5 in Sec. II.
+ *    tau_pi = taupi_coef (eta/s) hbarc / T with taupi_coef = 5 in Sec. II;
+ *  - bulk pressure Pi and net-baryon density n (eqns. Pitilde and Ntilde; zero in
+ *    every run of the paper) are transported like the pi~ components,
+ *    d~_tau (u~^tau X) + d~_i (u~^i X) = S_X, as components 10 and 11 of the
+ *    same arrays.  S_Pi = -(Pi + zeta theta)/tau_Pi - Pi theta/3 - Pi u~^tau/tau
+ *    (the Navier-Stokes limit Pi = -zeta theta fixes the sign of zeta theta; the
+ *    u~^tau/tau term is the one pi~ gets, for a scalar), zeta = (zeta/s)(e+P)
+ *    hbarc/T, tau_Pi = taubulk_coef (zeta/s) hbarc / T.  S_n = -n u~^tau/tau is
+ *    d_mu(tau n u^mu) = 0 with the tau of sqrt(-g) taken into the source.  Pi
+ *    adds to P in T^{mu nu} (also in the root solve); n is passive (the EoS
+ *    tables here are those of zero baryon chemical potential).  The regulator
+ *    keeps |Pi| <= P (no cavitation) and sets Pi and n to zero in vacuum.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -58,6 +69,9 @@ static int orc_mutant = 0;
 void orc_set_mutant(int k) { orc_mutant = k; }
 int orc_get_mutant(void) { return orc_mutant; }
 #define NG 2 /* ghost layers per face: the KT stencil reaches i-2 .. i+2 */
+#define NQ 12 /* transported components: 10 pi~, Pi, n */
+#define QB 10 /* index of Pi */
+#define QN 11 /* index of n */
 
 /* ------------------------------------------------------------------------ */
 typedef struct orc_params {
@@ -71,6 +85,9 @@ typedef struct orc_params {
     double pi_reg; /* cap on sqrt(|pi:pi|)/(e+P); <= 0 disables the regulator */
     double taupi_coef;  /* tau_pi = taupi_coef (eta/s) hbarc / T; 5 in Sec. II */
     double lambda1_hat; /* lambda_1 = lambda1_hat / e (Sec. V.C scaling); 0 in Sec. II */
+    double zetas;        /* zeta / s of the bulk pressure Pi; 0: Pi stays 0 */
+    double taubulk_coef; /* tau_Pi = taubulk_coef (zeta/s) hbarc / T */
+    int baryon;          /* 1: transport the net-baryon density n */
 } orc_params;
 
 typedef struct orc_diag {
@@ -95,17 +112,19 @@ typedef struct orc_eos {
 
 typedef struct orc {
     orc_params p;
+    int nq; /* transported components in use: 10 (pi~), or 12 with Pi and n */
     orc_eos eos;
     int NX, NY, NE;       /* padded dims */
     long ncell, npad;
     double tau;
     long step;
     /* state n (padded) */
-    double *e, *u[3], *pi[10], *T[4], *uprev[3];
+    /* pi[0..9] = pi~, pi[10] = Pi, pi[11] = n (the transported set) */
+    double *e, *u[3], *pi[NQ], *T[4], *uprev[3];
     /* stage-1 prediction, stage results */
-    double *e1, *u1[3], *pi1[10], *T1[4];
-    double *RT1[4], *Rpi1[10], *RT2[4], *Rpi2[10];
-    double *piN[10], *zero;
+    double *e1, *u1[3], *pi1[NQ], *T1[4];
+    double *RT1[4], *Rpi1[NQ], *RT2[4], *Rpi2[NQ];
+    double *piN[NQ], *zero;
     /* per-cell root-solve bookkeeping */
     int *it_cell, *flag_cell;
     orc_diag d;
@@ -173,12 +192,13 @@ static double eos_P(const orc_eos *q, double e) {
 /* ------------------------------------------------------------------------ */
 /* Root solve T_ideal -> (e, u~) (Sec. III, RK2 flow chart; App. A.3 notes the
  * variable iteration count).  K^mu = T~^{tau mu}/tau - pi~^{tau mu} equals
- * (e+P) u~^tau u~^mu - P g~^{tau mu}; with E = K^tau, M = |K|,
- * e solves f(e) = e - E + M^2/(E + P(e)) = 0 on [max(0, E - M^2/E), E], where
- * f is increasing.  Safeguarded Newton (bisection when a step leaves the
+ * (e+P+Pi) u~^tau u~^mu - (P+Pi) g~^{tau mu}; with E = K^tau, M = |K|,
+ * e solves f(e) = e - E + M^2/(E + P(e) + Pi) = 0 on [max(0, E - M^2/B), E],
+ * B = E + min(Pi, 0), where f is increasing (M is first capped below B; a state
+ * with B <= 0 has no solution and becomes vacuum).  Safeguarded Newton (bisection when a step leaves the
  * bracket), stop at |de| <= tol e, then one extra Newton step so the result
  * does not depend on the starting guess. */
-static void con2prim(const orc *S, const double Kin[4], double guess, double *e_out,
+static void con2prim(const orc *S, const double Kin[4], double Pi, double guess, double *e_out,
                      double u_out[3], int *iters, int *flags) {
     const orc_eos *q = &S->eos;
     double E = Kin[0], K1 = Kin[1], K2 = Kin[2], K3 = Kin[3];
@@ -196,9 +216,16 @@ static void con2prim(const orc *S, const double Kin[4], double guess, double *e_
         u_out[0] = u_out[1] = u_out[2] = 0.0;
         return;
     }
+    const double B = E + (Pi < 0.0 ? Pi : 0.0);
+    if (!(B > 0.0)) {
+        *flags |= C2P_VAC | C2P_CLAMP;
+        *e_out = 0.0;
+        u_out[0] = u_out[1] = u_out[2] = 0.0;
+        return;
+    }
     double M2 = K1 * K1 + K2 * K2 + K3 * K3;
     double M = sqrt(M2);
-    double Mmax = (1.0 - 1e-10) * E;
+    double Mmax = (1.0 - 1e-10) * B;
     if (M > Mmax) {
         double s = Mmax / M;
         K1 *= s;
@@ -207,7 +234,7 @@ static void con2prim(const orc *S, const double Kin[4], double guess, double *e_
         M2 = K1 * K1 + K2 * K2 + K3 * K3;
         *flags |= C2P_CLAMP;
     }
-    double lo = E - M2 / E;
+    double lo = E - M2 / B;
     if (lo < 0.0) lo = 0.0;
     double hi = E;
     const double lo0 = lo, hi0 = hi;
@@ -225,8 +252,9 @@ static void con2prim(const orc *S, const double Kin[4], double guess, double *e_
         }
         double P, T, c, dP;
         eos_eval(q, x, &P, &T, &c, &dP);
-        double f = x - E + M2 / (E + P);
-        double df = 1.0 - M2 * dP / ((E + P) * (E + P));
+        const double W = MUT(31) ? E + P : E + P + Pi;
+        double f = x - E + M2 / W;
+        double df = 1.0 - M2 * dP / (W * W);
         if (f == 0.0) {
             conv = 1;
             break;
@@ -254,8 +282,9 @@ static void con2prim(const orc *S, const double Kin[4], double guess, double *e_
     {   /* polish */
         double P, T, c, dP;
         eos_eval(q, x, &P, &T, &c, &dP);
-        double f = x - E + M2 / (E + P);
-        double df = 1.0 - M2 * dP / ((E + P) * (E + P));
+        const double W = MUT(31) ? E + P : E + P + Pi;
+        double f = x - E + M2 / W;
+        double df = 1.0 - M2 * dP / (W * W);
         double xp = x - f / df;
         if (xp >= lo0 && xp <= hi0) x = xp;
     }
@@ -266,15 +295,13 @@ static void con2prim(const orc *S, const double Kin[4], double guess, double *e_
         u_out[0] = u_out[1] = u_out[2] = 0.0;
         return;
     }
-    double P = eos_P(q, x);
-    /* 1 - v^2 = (e+P)/(E+P), v = K/(E+P) */
-    double ut = sqrt((E + P) / (x + P));
+    double P = eos_P(q, x) + Pi;
+    /* u~^tau = sqrt((E+P+Pi)/(e+P+Pi)), u~^i = K^i / ((e+P+Pi) u~^tau) */
     double den = MUT(11) ? sqrt(E * (x + P)) : sqrt((E + P) * (x + P));
     *e_out = x;
     u_out[0] = K1 / den;
     u_out[1] = K2 / den;
     u_out[2] = K3 / den;
-    (void)ut;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -307,11 +334,12 @@ static double local_speed(const double uc[4], int d, double cs2) {
 }
 
 /* Conserved densities and fluxes of one side state along axis d.
- * prim = (e, u~x, u~y, u~e); piT is the pi~ entering T, piP the evolved pi~.
- * QT = tau Tc^{tau nu}, FT = tau Tc^{d nu}, Qpi = u~^tau pi~, Fpi = u~^d pi~. */
-static void side_flux(const orc *S, const double prim[4], const double piT[10],
-                      const double piP[10], int d, double tauf, int doT, int doPi,
-                      double QT[4], double FT[4], double Qpi[10], double Fpi[10],
+ * prim = (e, u~x, u~y, u~e); piT is the (pi~, Pi) entering T, piP the evolved
+ * set (pi~, Pi, n).  With P' = P + Pi: QT = tau Tc^{tau nu}, FT = tau Tc^{d nu}
+ * for Tc = (e + P') u~ u~ - P' g~ + pi~; Qpi = u~^tau X, Fpi = u~^d X. */
+static void side_flux(const orc *S, const double prim[4], const double piT[NQ],
+                      const double piP[NQ], int d, double tauf, int doT, int doPi,
+                      double QT[4], double FT[4], double Qpi[NQ], double Fpi[NQ],
                       double *speed) {
     double P, T, cs2, dP;
     eos_eval(&S->eos, prim[0], &P, &T, &cs2, &dP);
@@ -321,6 +349,7 @@ static void side_flux(const orc *S, const double prim[4], const double piT[10],
     uc[3] = prim[3];
     uc[0] = sqrt(1.0 + uc[1] * uc[1] + uc[2] * uc[2] + uc[3] * uc[3]);
     double e = prim[0] > 0.0 ? prim[0] : 0.0;
+    if (S->nq > QB && !MUT(30)) P += piT[QB];
     double w = e + P;
     if (doT) {
         for (int nu = 0; nu < 4; ++nu) {
@@ -331,7 +360,7 @@ static void side_flux(const orc *S, const double prim[4], const double piT[10],
         }
     }
     if (doPi) {
-        for (int m = 0; m < 10; ++m) {
+        for (int m = 0; m < S->nq; ++m) {
             Qpi[m] = uc[0] * piP[m];
             Fpi[m] = uc[d] * piP[m];
         }
@@ -369,8 +398,8 @@ static void fill_ghosts(const orc *S, double *f) {
  * and the face flux H = [F(Q^r) + F(Q^l)]/2 - c (Q^r - Q^l)/2).  Adds -dH/Delta
  * into RT / Rpi for every interior cell; records max c h / Delta in *cfl. */
 static void kt_axis(const orc *S, int d, double *const e, double *const u[3],
-                    double *const piT[10], double *const piP[10], double tau, int doT,
-                    int doPi, double *RT[4], double *Rpi[10], double *cfl) {
+                    double *const piT[NQ], double *const piP[NQ], double tau, int doT,
+                    int doPi, double *RT[4], double *Rpi[NQ], double *cfl) {
     const int n[4] = {0, S->p.nx, S->p.ny, S->p.ne};
     const int nd = n[d];
     const double tauf = S->p.cartesian ? 1.0 : tau;
@@ -378,6 +407,7 @@ static void kt_axis(const orc *S, int d, double *const e, double *const u[3],
     const long stride = (d == 1) ? (long)S->NY * S->NE : (d == 2) ? S->NE : 1;
     int a1 = (d == 1) ? 2 : 1, a2 = (d == 3) ? 2 : 3; /* the two transverse axes */
     const int n1 = n[a1], n2 = n[a2];
+    const int nv = 4 + S->nq; /* reconstructed fields: e, u~ (3), the transported set */
     double cmax = 0.0;
 
 #ifdef _OPENMP
@@ -390,18 +420,18 @@ static void kt_axis(const orc *S, int d, double *const e, double *const u[3],
         ijk[a2] = c2;
         ijk[d] = 0;
         long base = IDX(S, ijk[1], ijk[2], ijk[3]); /* cell 0 of the line */
-        double *H = (double *)malloc(sizeof(double) * 14 * (nd + 1));
+        double *H = (double *)malloc(sizeof(double) * (4 + NQ) * (nd + 1));
         for (int f = -1; f < nd; ++f) { /* face between cells f and f+1 */
-            double qL[14], qR[14];
-            const double *fld[14];
+            double qL[4 + NQ], qR[4 + NQ];
+            const double *fld[4 + NQ];
             fld[0] = e;
             fld[1] = u[0];
             fld[2] = u[1];
             fld[3] = u[2];
-            for (int m = 0; m < 10; ++m) fld[4 + m] = piP[m];
+            for (int m = 0; m < S->nq; ++m) fld[4 + m] = piP[m];
             /* reconstruct the primitives; piT is reconstructed separately */
-            double piTL[10], piTR[10];
-            for (int v = 0; v < 14; ++v) {
+            double piTL[NQ], piTR[NQ];
+            for (int v = 0; v < nv; ++v) {
                 const double *F = fld[v];
                 double qm1 = F[base + (long)(f - 1) * stride], q0 = F[base + (long)f * stride];
                 double q1 = F[base + (long)(f + 1) * stride], q2 = F[base + (long)(f + 2) * stride];
@@ -410,7 +440,7 @@ static void kt_axis(const orc *S, int d, double *const e, double *const u[3],
                 qL[v] = q0 + 0.5 * sL;
                 qR[v] = MUT(9) ? q1 + 0.5 * sR : q1 - 0.5 * sR;
             }
-            for (int m = 0; m < 10; ++m) {
+            for (int m = 0; m < S->nq; ++m) {
                 if (piT == piP) { /* same field: same reconstruction */
                     piTL[m] = qL[4 + m];
                     piTR[m] = qR[4 + m];
@@ -422,36 +452,36 @@ static void kt_axis(const orc *S, int d, double *const e, double *const u[3],
                 piTL[m] = q0 + 0.5 * limited_slope(S->p.theta, qm1, q0, q1);
                 piTR[m] = q1 - 0.5 * limited_slope(S->p.theta, q0, q1, q2);
             }
-            double QTL[4], FTL[4], QpL[10], FpL[10], sl;
-            double QTR[4], FTR[4], QpR[10], FpR[10], sr;
+            double QTL[4], FTL[4], QpL[NQ], FpL[NQ], sl;
+            double QTR[4], FTR[4], QpR[NQ], FpR[NQ], sr;
             side_flux(S, qL, piTL, qL + 4, d, tauf, doT, doPi, QTL, FTL, QpL, FpL, &sl);
             side_flux(S, qR, piTR, qR + 4, d, tauf, doT, doPi, QTR, FTR, QpR, FpR, &sr);
             double c = fmax(sl, sr);
             double ch = c * S->p.h / Delta;
             if (ch > cmax) cmax = ch;
-            double *Hf = H + 14 * (f + 1);
+            double *Hf = H + (4 + NQ) * (f + 1);
             for (int nu = 0; nu < 4; ++nu)
                 Hf[nu] = doT ? 0.5 * (FTL[nu] + FTR[nu]) - 0.5 * c * (QTR[nu] - QTL[nu]) : 0.0;
-            for (int m = 0; m < 10; ++m)
+            for (int m = 0; m < S->nq; ++m)
                 Hf[4 + m] = doPi ? 0.5 * (FpL[m] + FpR[m]) - 0.5 * c * (QpR[m] - QpL[m]) : 0.0;
         }
         for (int cidx = 0; cidx < nd; ++cidx) {
             long id = base + (long)cidx * stride;
-            const double *Hm = H + 14 * cidx, *Hp = H + 14 * (cidx + 1);
+            const double *Hm = H + (4 + NQ) * cidx, *Hp = H + (4 + NQ) * (cidx + 1);
             if (doT)
                 for (int nu = 0; nu < 4; ++nu) RT[nu][id] -= (Hp[nu] - Hm[nu]) / Delta;
             if (doPi)
-                for (int m = 0; m < 10; ++m) Rpi[m][id] -= (Hp[4 + m] - Hm[4 + m]) / Delta;
+                for (int m = 0; m < S->nq; ++m) Rpi[m][id] -= (Hp[4 + m] - Hm[4 + m]) / Delta;
         }
         free(H);
     }
     if (cmax > *cfl) *cfl = cmax;
 }
 
-/* Geometric source of T~ (Sec. II, eqn. Ttilde): S_T = (-Tc^{ee}, 0, 0, -Tc^{te}).
- * Adds it to RT; returns the interior sum of S_T^tau. */
+/* Geometric source of T~ (Sec. II, eqn. Ttilde): S_T = (-Tc^{ee}, 0, 0, -Tc^{te}),
+ * with P + Pi in Tc.  Adds it to RT; returns the interior sum of S_T^tau. */
 static double geometric_source(const orc *S, double *const e, double *const u[3],
-                               double *const piT[10], double *RT[4]) {
+                               double *const piT[NQ], double *RT[4]) {
     if (S->p.cartesian) return 0.0;
     int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
     double *st = (double *)malloc(sizeof(double) * (size_t)nx * ny * ne);
@@ -465,6 +495,7 @@ static double geometric_source(const orc *S, double *const e, double *const u[3]
                 double P, T, cs2, dP;
                 eos_eval(&S->eos, e[id], &P, &T, &cs2, &dP);
                 double ee = e[id] > 0.0 ? e[id] : 0.0;
+                if (S->nq > QB) P += piT[QB][id];
                 double ux = u[0][id], uy = u[1][id], ue = u[2][id];
                 double ut = sqrt(1.0 + ux * ux + uy * uy + ue * ue);
                 double w = ee + P;
@@ -569,8 +600,8 @@ static void pipi_projected(const double uc[4], double pc[4][4], double Y[4][4]) 
  * coefficient of Sec. V.C).  uE / uL are the earlier and later time levels for
  * d_tau u~; u is the stage's velocity field. */
 static void pi_source(const orc *S, double *const e, double *const u[3],
-                      double *const pi[10], double *const uE[3], double *const uL[3],
-                      double tau, double *Rpi[10]) {
+                      double *const pi[NQ], double *const uE[3], double *const uL[3],
+                      double tau, double *Rpi[NQ]) {
     int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
     const int cart = S->p.cartesian;
 #ifdef _OPENMP
@@ -624,20 +655,35 @@ static void pi_source(const orc *S, double *const e, double *const u[3],
                                         (MUT(3) ? -1.0 : 1.0) * I[mu][nu];
                         Rpi[SYM(mu, nu)][id] += s;
                     }
+                /* bulk pressure and net-baryon density (eqns. Pitilde, Ntilde) */
+                if (S->p.zetas > 0.0) {
+                    double Pi = pi[QB][id];
+                    double zeta = S->p.zetas * (e[id] + P) * HBARC / T;
+                    double tauPi = S->p.taubulk_coef * S->p.zetas * HBARC / T;
+                    double s = -(Pi + (MUT(28) ? -zeta : zeta) * theta) / tauPi - Pi * theta / 3.0;
+                    if (!cart && !MUT(29)) s -= Pi * uc[0] / tau;
+                    Rpi[QB][id] += s;
+                }
+                if (S->p.baryon && !cart && !MUT(32)) Rpi[QN][id] += -pi[QN][id] * uc[0] / tau;
             }
 }
 
 /* Shear-stress regulator (the paper states none; see the readings above):
  * where sqrt(|pi~ : pi~|) exceeds rho_max (e + P), pi~ is scaled down to that
- * size; in vacuum (e + P = 0) pi~ is set to zero.  pi~ : pi~ =
- * pi~^{mu nu} pi~^{ab} g~_{mu a} g~_{nu b}, an invariant of the local frame. */
-static void regulate_pi(const orc *S, double e, double pi10[10]) {
+ * size; in vacuum (e + P = 0) pi~ (and Pi, n) is set to zero.  pi~ : pi~ =
+ * pi~^{mu nu} pi~^{ab} g~_{mu a} g~_{nu b}, an invariant of the local frame.
+ * Pi is clipped to [-P, P]. */
+static void regulate_pi(const orc *S, double e, double pi10[NQ]) {
     double P, T, cs2, dP;
     eos_eval(&S->eos, e, &P, &T, &cs2, &dP);
     double w = (e > 0.0 ? e : 0.0) + P;
     if (!(w > 0.0)) {
-        for (int m = 0; m < 10; ++m) pi10[m] = 0.0;
+        for (int m = 0; m < S->nq; ++m) pi10[m] = 0.0;
         return;
+    }
+    if (S->nq > QB) {
+        if (pi10[QB] > P) pi10[QB] = P;
+        if (pi10[QB] < -P) pi10[QB] = -P;
     }
     double pp = 0.0;
     for (int mu = 0; mu < 4; ++mu)
@@ -654,13 +700,13 @@ static void regulate_pi(const orc *S, double e, double pi10[10]) {
 
 /* Full right-hand side: R_T = S_KT + S_T (if doT), R_pi = S_KT + S_pi (if doPi).
  * Ghosts of every field read must be filled by the caller. */
-static double rhs(orc *S, double *const e, double *const u[3], double *const piT[10],
-                  double *const piP[10], double *const uE[3], double *const uL[3],
-                  double tau, int doT, int doPi, double *RT[4], double *Rpi[10],
+static double rhs(orc *S, double *const e, double *const u[3], double *const piT[NQ],
+                  double *const piP[NQ], double *const uE[3], double *const uL[3],
+                  double tau, int doT, int doPi, double *RT[4], double *Rpi[NQ],
                   double *cfl) {
     for (int nu = 0; nu < 4; ++nu)
         if (doT) memset(RT[nu], 0, sizeof(double) * S->npad);
-    for (int m = 0; m < 10; ++m)
+    for (int m = 0; m < S->nq; ++m)
         if (doPi) memset(Rpi[m], 0, sizeof(double) * S->npad);
     for (int d = 1; d <= 3; ++d) kt_axis(S, d, e, u, piT, piP, tau, doT, doPi, RT, Rpi, cfl);
     double st = 0.0;
@@ -676,7 +722,7 @@ static double *alloc_field(const orc *S) {
 
 static int it_cell_zero(int it) { return it == 0; }
 
-static void cells_con2prim(orc *S, double *const T[4], double *const piq[10], double tau,
+static void cells_con2prim(orc *S, double *const T[4], double *const piq[NQ], double tau,
                            double *const guess, double *e_out, double *u_out[3]) {
     int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
     const double tauf = S->p.cartesian ? 1.0 : tau;
@@ -691,7 +737,8 @@ static void cells_con2prim(orc *S, double *const T[4], double *const piq[10], do
                 for (int nu = 0; nu < 4; ++nu)
                     K[nu] = T[nu][id] / tauf - (piq ? piq[SYM(0, nu)][id] : 0.0);
                 int it, fl;
-                con2prim(S, K, guess ? guess[id] : K[0], &eo, uo, &it, &fl);
+                const double Pi = (piq && S->nq > QB) ? piq[QB][id] : 0.0;
+                con2prim(S, K, Pi, guess ? guess[id] : K[0], &eo, uo, &it, &fl);
                 e_out[id] = eo;
                 for (int m = 0; m < 3; ++m) u_out[m][id] = uo[m];
                 long c = ((long)i * ny + j) * ne + k;
@@ -712,11 +759,13 @@ static void cells_con2prim(orc *S, double *const T[4], double *const piq[10], do
     }
 }
 
-/* tau~ T^{tau mu} of a primitive state (tau~ = tau, or 1 in Cartesian mode). */
+/* tau~ T^{tau mu} of a primitive state (tau~ = tau, or 1 in Cartesian mode);
+ * pic = (pi~, Pi[, n]) or NULL. */
 static void conserved_of(const orc *S, double e, const double u3[3], const double *pic,
                          double tauf, double Tout[4]) {
     double P, T, cs2, dP;
     eos_eval(&S->eos, e, &P, &T, &cs2, &dP);
+    if (pic && S->nq > QB) P += pic[QB];
     double uc[4] = {0, u3[0], u3[1], u3[2]};
     uc[0] = sqrt(1.0 + uc[1] * uc[1] + uc[2] * uc[2] + uc[3] * uc[3]);
     double w = (e > 0.0 ? e : 0.0) + P;
@@ -751,8 +800,13 @@ orc *orc_create(const orc_params *p) {
     if (p->viscous && !(p->etas > 0)) return NULL;
     if (p->viscous && !(p->taupi_coef > 0)) return NULL;
     if (!isfinite(p->lambda1_hat)) return NULL;
+    if (!(p->zetas >= 0.0) || !isfinite(p->zetas)) return NULL;
+    const int ext = p->zetas > 0.0 || p->baryon;
+    if (ext && !p->viscous) return NULL; /* Pi and n ride on the viscous step */
+    if (p->zetas > 0.0 && !(p->taubulk_coef > 0.0)) return NULL;
     orc *S = (orc *)calloc(1, sizeof(orc));
     S->p = *p;
+    S->nq = ext ? NQ : 10;
     S->NX = p->nx + 2 * NG;
     S->NY = p->ny + 2 * NG;
     S->NE = p->ne + 2 * NG;
@@ -766,7 +820,7 @@ orc *orc_create(const orc_params *p) {
         S->uprev[m] = alloc_field(S);
         S->u1[m] = alloc_field(S);
     }
-    for (int m = 0; m < 10; ++m) {
+    for (int m = 0; m < NQ; ++m) {
         S->pi[m] = alloc_field(S);
         S->pi1[m] = alloc_field(S);
         S->piN[m] = alloc_field(S);
@@ -797,7 +851,7 @@ void orc_destroy(orc *S) {
         free(S->uprev[m]);
         free(S->u1[m]);
     }
-    for (int m = 0; m < 10; ++m) {
+    for (int m = 0; m < NQ; ++m) {
         free(S->pi[m]);
         free(S->pi1[m]);
         free(S->piN[m]);
@@ -859,8 +913,8 @@ static void first_step_estimate(orc *S) {
     const double tf0 = S->p.cartesian ? 1.0 : tau0;
     fill_ghosts(S, S->e);
     for (int m = 0; m < 3; ++m) fill_ghosts(S, S->u[m]);
-    double *zp[10];
-    for (int m = 0; m < 10; ++m) zp[m] = S->zero;
+    double *zp[NQ];
+    for (int m = 0; m < NQ; ++m) zp[m] = S->zero;
     double cfl = 0.0;
     rhs(S, S->e, S->u, zp, zp, S->u, S->u, tau0, 1, 0, S->RT1, NULL, &cfl);
     int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
@@ -900,16 +954,20 @@ static void finish_initial(orc *S) {
     S->d.tau = S->tau;
 }
 
-/* Primitive initial state; pi10 may be NULL (pi~ = 0).  Arrays are C-ordered
+/* Primitive initial state; pi10 may be NULL (pi~ = 0), Pi and n too (zero; also
+ * zero unless zeta/s > 0, respectively baryon).  Arrays are C-ordered
  * (nx, ny, ne); pi10 holds 10 such blocks. */
-int orc_set_initial_primitive(orc *S, const double *e, const double *ux, const double *uy,
-                              const double *ue, const double *pi10) {
+int orc_set_initial_primitive_ext(orc *S, const double *e, const double *ux, const double *uy,
+                                  const double *ue, const double *pi10, const double *Pi,
+                                  const double *nb) {
     S->tau = S->p.tau0;
     copy_in(S, S->e, e);
     copy_in(S, S->u[0], ux);
     copy_in(S, S->u[1], uy);
     copy_in(S, S->u[2], ue);
     for (int m = 0; m < 10; ++m) copy_in(S, S->pi[m], (pi10 && S->p.viscous) ? pi10 + (long)m * S->ncell : NULL);
+    copy_in(S, S->pi[QB], S->p.zetas > 0.0 ? Pi : NULL);
+    copy_in(S, S->pi[QN], S->p.baryon ? nb : NULL);
     const double tf = S->p.cartesian ? 1.0 : S->tau;
     int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
     for (int i = 0; i < nx; ++i)
@@ -919,15 +977,20 @@ int orc_set_initial_primitive(orc *S, const double *e, const double *ux, const d
                 if (!(S->e[id] >= S->p.eps_cut)) { /* cutoff */
                     S->e[id] = 0.0;
                     for (int m = 0; m < 3; ++m) S->u[m][id] = 0.0;
-                    for (int m = 0; m < 10; ++m) S->pi[m][id] = 0.0;
+                    for (int m = 0; m < NQ; ++m) S->pi[m][id] = 0.0;
                 }
-                double u3[3] = {S->u[0][id], S->u[1][id], S->u[2][id]}, pic[10], Tc[4];
-                for (int m = 0; m < 10; ++m) pic[m] = S->pi[m][id];
+                double u3[3] = {S->u[0][id], S->u[1][id], S->u[2][id]}, pic[NQ], Tc[4];
+                for (int m = 0; m < NQ; ++m) pic[m] = S->pi[m][id];
                 conserved_of(S, S->e[id], u3, pic, tf, Tc);
                 for (int nu = 0; nu < 4; ++nu) S->T[nu][id] = Tc[nu];
             }
     finish_initial(S);
     return 0;
+}
+
+int orc_set_initial_primitive(orc *S, const double *e, const double *ux, const double *uy,
+                              const double *ue, const double *pi10) {
+    return orc_set_initial_primitive_ext(S, e, ux, uy, ue, pi10, NULL, NULL);
 }
 
 /* Conserved initial state T~^{tau mu} (4 blocks) plus optional pi~; the root
@@ -936,6 +999,7 @@ int orc_set_initial_conserved(orc *S, const double *T4, const double *pi10) {
     S->tau = S->p.tau0;
     for (int nu = 0; nu < 4; ++nu) copy_in(S, S->T[nu], T4 + (long)nu * S->ncell);
     for (int m = 0; m < 10; ++m) copy_in(S, S->pi[m], (pi10 && S->p.viscous) ? pi10 + (long)m * S->ncell : NULL);
+    for (int m = 10; m < NQ; ++m) copy_in(S, S->pi[m], NULL); /* Pi = n = 0 */
     cells_con2prim(S, S->T, S->pi, S->tau, NULL, S->e, S->u);
     int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
     for (int i = 0; i < nx; ++i)
@@ -943,7 +1007,7 @@ int orc_set_initial_conserved(orc *S, const double *T4, const double *pi10) {
             for (int k = 0; k < ne; ++k) {
                 long id = IDX(S, i, j, k);
                 if (S->e[id] == 0.0)
-                    for (int m = 0; m < 10; ++m) S->pi[m][id] = 0.0;
+                    for (int m = 0; m < NQ; ++m) S->pi[m][id] = 0.0;
             }
     finish_initial(S);
     return 0;
@@ -958,14 +1022,15 @@ static void one_step(orc *S) {
     const double h = S->p.h, taun = S->tau, tau1 = S->tau + h;
     int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
     double cfl = 0.0;
-    double *zp[10];
-    for (int m = 0; m < 10; ++m) zp[m] = S->zero;
+    const int nq = S->nq;
+    double *zp[NQ];
+    for (int m = 0; m < NQ; ++m) zp[m] = S->zero;
 
     /* ---- stage 1 at tau_n ---- */
     fill_ghosts(S, S->e);
     for (int m = 0; m < 3; ++m) fill_ghosts(S, S->u[m]);
     if (visc)
-        for (int m = 0; m < 10; ++m) fill_ghosts(S, S->pi[m]);
+        for (int m = 0; m < nq; ++m) fill_ghosts(S, S->pi[m]);
     double *const *piN_ = visc ? S->pi : zp;
     double st1 = rhs(S, S->e, S->u, piN_, piN_, S->uprev, S->u, taun, 1, visc, S->RT1,
                      S->Rpi1, &cfl);
@@ -981,11 +1046,11 @@ static void one_step(orc *S) {
                            s2 = 2.0 * ue - S->uprev[2][id];
                     if (MUT(16)) { s0 = ux; s1 = uy; s2 = ue; }
                     double uts = sqrt(1.0 + s0 * s0 + s1 * s1 + s2 * s2);
-                    double p1[10];
-                    for (int m = 0; m < 10; ++m)
+                    double p1[NQ];
+                    for (int m = 0; m < nq; ++m)
                         p1[m] = (utn * S->pi[m][id] + h * S->Rpi1[m][id]) / uts;
                     if (S->p.pi_reg > 0.0) regulate_pi(S, S->e[id], p1);
-                    for (int m = 0; m < 10; ++m) S->pi1[m][id] = p1[m];
+                    for (int m = 0; m < nq; ++m) S->pi1[m][id] = p1[m];
                 }
             }
     cells_con2prim(S, S->T1, visc ? S->pi1 : NULL, tau1, S->e, S->e1, S->u1);
@@ -994,7 +1059,7 @@ static void one_step(orc *S) {
     fill_ghosts(S, S->e1);
     for (int m = 0; m < 3; ++m) fill_ghosts(S, S->u1[m]);
     if (visc) {
-        for (int m = 0; m < 10; ++m) fill_ghosts(S, S->pi1[m]);
+        for (int m = 0; m < nq; ++m) fill_ghosts(S, S->pi1[m]);
         rhs(S, S->e1, S->u1, S->pi1, S->pi1, S->u, S->u1, tau1, 0, 1, NULL, S->Rpi2, &cfl);
         for (int i = 0; i < nx; ++i)
             for (int j = 0; j < ny; ++j)
@@ -1010,14 +1075,14 @@ static void one_step(orc *S) {
                     double uts = sqrt(1.0 + s0 * s0 + s1 * s1 + s2 * s2);
                     /* u'pi^{n+1} = u^n pi^n + h/2 (S1 + S2) with h S1 = u* pi' - u^n pi^n,
                      * pi' being the (possibly regulated) predictor */
-                    double pn[10];
-                    for (int m = 0; m < 10; ++m)
+                    double pn[NQ];
+                    for (int m = 0; m < nq; ++m)
                         pn[m] = (0.5 * (utn * S->pi[m][id] + uts * S->pi1[m][id]) +
                                  0.5 * h * S->Rpi2[m][id]) / ut1;
                     if (S->p.pi_reg > 0.0) regulate_pi(S, S->e1[id], pn);
-                    for (int m = 0; m < 10; ++m) S->piN[m][id] = pn[m];
+                    for (int m = 0; m < nq; ++m) S->piN[m][id] = pn[m];
                 }
-        for (int m = 0; m < 10; ++m) fill_ghosts(S, S->piN[m]);
+        for (int m = 0; m < nq; ++m) fill_ghosts(S, S->piN[m]);
     }
     double *const *piT2 = visc ? (MUT(14) ? S->pi1 : S->piN) : zp;
     double st2 = rhs(S, S->e1, S->u1, piT2, piT2, NULL, NULL, tau1, 1, 0, S->RT2, NULL, &cfl);
@@ -1037,7 +1102,7 @@ static void one_step(orc *S) {
     /* solve into S->e (e^n is no longer needed), the stage-1 solution is the guess */
     cells_con2prim(S, S->T, visc ? S->piN : NULL, tau1, S->e1, S->e, S->u);
     if (visc)
-        for (int m = 0; m < 10; ++m) {
+        for (int m = 0; m < nq; ++m) {
             double *t = S->pi[m];
             S->pi[m] = S->piN[m];
             S->piN[m] = t;
@@ -1051,7 +1116,7 @@ static void one_step(orc *S) {
                 long id = IDX(S, i, j, k);
                 if (S->e[id] == 0.0) {
                     vac++;
-                    for (int m = 0; m < 10; ++m) S->pi[m][id] = 0.0;
+                    for (int m = 0; m < nq; ++m) S->pi[m][id] = 0.0;
                 }
                 if (S->e[id] > emax) emax = S->e[id];
                 sumT += S->T[0][id];
@@ -1075,7 +1140,7 @@ int orc_step(orc *S, int n) {
 }
 
 /* Fields: 0 e, 1-3 u~ (x, y, eta), 4-13 pi~, 14-17 T~^{tau mu}, 18-20 u~ at the
- * previous time level.  dst gets the interior in C order. */
+ * previous time level, 21 Pi, 22 n.  dst gets the interior in C order. */
 int orc_read(const orc *S, int field, double *dst) {
     const double *src;
     if (field == 0)
@@ -1088,6 +1153,8 @@ int orc_read(const orc *S, int field, double *dst) {
         src = S->T[field - 14];
     else if (field >= 18 && field <= 20)
         src = S->uprev[field - 18];
+    else if (field == 21 || field == 22)
+        src = S->pi[QB + field - 21];
     else
         return -1;
     int nx = S->p.nx, ny = S->p.ny, ne = S->p.ne;
@@ -1095,7 +1162,9 @@ int orc_read(const orc *S, int field, double *dst) {
         for (int j = 0; j < ny; ++j)
             for (int k = 0; k < ne; ++k)
                 dst[((long)i * ny + j) * ne + k] =
-                    (field >= 4 && field <= 13 && !S->p.viscous) ? 0.0 : src[IDX(S, i, j, k)];
+                    ((field >= 4 && field <= 13 && !S->p.viscous) || (field >= 21 && S->nq <= QB))
+                        ? 0.0
+                        : src[IDX(S, i, j, k)];
     return 0;
 }
 
@@ -1114,8 +1183,17 @@ int orc_eos_eval(const orc *S, int n, const double *e, double *P, double *T, dou
 int orc_con2prim(const orc *S, int n, const double *K4, const double *guess, double *e,
                  double *u3, int *iters, int *flags) {
     for (int i = 0; i < n; ++i)
-        con2prim(S, K4 + 4 * (long)i, guess ? guess[i] : K4[4 * (long)i], &e[i], u3 + 3 * (long)i,
-                 &iters[i], &flags[i]);
+        con2prim(S, K4 + 4 * (long)i, 0.0, guess ? guess[i] : K4[4 * (long)i], &e[i],
+                 u3 + 3 * (long)i, &iters[i], &flags[i]);
+    return 0;
+}
+
+/* The root solve with a bulk pressure Pi[i] per state. */
+int orc_con2prim_bulk(const orc *S, int n, const double *K4, const double *Pi, double *e,
+                      double *u3, int *iters, int *flags) {
+    for (int i = 0; i < n; ++i)
+        con2prim(S, K4 + 4 * (long)i, Pi[i], K4[4 * (long)i], &e[i], u3 + 3 * (long)i, &iters[i],
+                 &flags[i]);
     return 0;
 }
 

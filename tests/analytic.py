@@ -43,6 +43,48 @@ def is_bjorken_rhs(etas):
     return f
 
 
+def bulk_bjorken_rhs(etas, zetas, taubulk_coef):
+    """0+1D Bjorken system with shear, bulk pressure and a conserved density,
+    conformal EoS, y = (eps, Phi, Pi, n):
+    d eps/d tau = -(eps + P + Pi - Phi)/tau,
+    d Phi/d tau = -(Phi - 4 eta/(3 tau))/tau_pi - 4/3 Phi/tau,
+    d Pi/d tau = -(Pi + zeta/tau)/tau_Pi - 4/3 Pi/tau,
+    d n/d tau = -n/tau (d_mu (n u^mu) = 0 with theta = 1/tau),
+    eta = (eta/s) s hbarc, zeta = (zeta/s) s hbarc, s = (eps+P)/T, tau_pi = 5 (eta/s)
+    hbarc/T, tau_Pi = taubulk_coef (zeta/s) hbarc/T."""
+
+    def f(tau, y):
+        e, phi, Pi, n = y
+        T = (e / C_SB) ** 0.25
+        P = e / 3.0
+        s = (e + P) / T
+        eta, zeta = etas * s * HBARC, zetas * s * HBARC
+        tpi, tPi = 5.0 * etas * HBARC / T, taubulk_coef * zetas * HBARC / T
+        return [-(e + P + Pi - phi) / tau,
+                -(phi - 4.0 * eta / (3.0 * tau)) / tpi - 4.0 / 3.0 * phi / tau,
+                -(Pi + zeta / tau) / tPi - 4.0 / 3.0 * Pi / tau,
+                -n / tau]
+
+    return f
+
+
+def bulk_bjorken_reference(y0, tau0, tau1, etas, zetas, taubulk_coef):
+    sol = solve_ivp(bulk_bjorken_rhs(etas, zetas, taubulk_coef), (tau0, tau1), list(y0),
+                    method="DOP853", rtol=1e-13, atol=1e-16)
+    return sol.y[:, -1]
+
+
+def gubser_density(x, y, tau, L, n_hat0):
+    """Conserved density on a Gubser flow of scale L: in the de Sitter frame
+    d_rho (cosh^2 rho n^) = 0, so n^ = n_hat0 / cosh^2 rho and, with conformal weight
+    3, n = n^ / tau^3, where (2 L tau cosh rho)^2 = L^4 + 2 L^2 (tau^2 + r^2) +
+    (tau^2 - r^2)^2."""
+    r2 = np.asarray(x, dtype=np.float64) ** 2 + np.asarray(y, dtype=np.float64) ** 2
+    Q = L ** 4 + 2.0 * L * L * (tau * tau + r2) + (tau * tau - r2) ** 2
+    cosh2 = Q / (2.0 * L * tau) ** 2
+    return n_hat0 / cosh2 / tau ** 3
+
+
 def is_bjorken_reference(eps0, phi0, tau0, tau1, etas):
     sol = solve_ivp(is_bjorken_rhs(etas), (tau0, tau1), [eps0, phi0], method="DOP853",
                     rtol=1e-13, atol=1e-16)

@@ -569,6 +569,159 @@ def pin_gubser_viscous():
 
 
 # ---------------------------------------------------------------------------
+# Bulk pressure Pi and net-baryon density n (eqns. Pitilde, Ntilde)
+# ---------------------------------------------------------------------------
+_BULK = dict(etas=0.08, zetas=0.04, taubulk_coef=5.0)
+
+
+def _bulk_reduced(y0, tau0, h, n, etas, zetas, taubulk_coef):
+    """The step's RK2 (pi and Pi first, then T with their new values) on the 0+1D
+    system of (Q = tau eps, Phi, Pi, n) with u~ = (1, 0, 0, 0) (then u* = u, the root
+    solve returns e = Q/tau, and the regulator keeps |Pi| <= P)."""
+    def src(e, phi, Pi, nb, tau):
+        T = (e / E.C_SB) ** 0.25
+        P = e / 3.0
+        s = (e + P) / T
+        eta, zeta = etas * s * E.HBARC, zetas * s * E.HBARC
+        tpi, tPi = 5.0 * etas * E.HBARC / T, taubulk_coef * zetas * E.HBARC / T
+        return (-(phi - 4.0 * eta / (3.0 * tau)) / tpi - 4.0 / 3.0 * phi / tau,
+                -(Pi + zeta / tau) / tPi - Pi / (3.0 * tau) - Pi / tau,
+                -nb / tau)
+
+    def clip(Pi, e):
+        return min(max(Pi, -e / 3.0), e / 3.0)
+
+    e, phi, Pi, nb = y0
+    Q, tau = tau0 * e, tau0
+    for _ in range(n):
+        e = Q / tau
+        RT1 = -(e / 3.0 + Pi - phi)
+        r1 = src(e, phi, Pi, nb, tau)
+        Q1 = Q + h * RT1
+        phi1, Pi1, nb1 = phi + h * r1[0], clip(Pi + h * r1[1], e), nb + h * r1[2]
+        e1 = Q1 / (tau + h)
+        r2 = src(e1, phi1, Pi1, nb1, tau + h)
+        phi = 0.5 * (phi + phi1) + 0.5 * h * r2[0]
+        Pi = clip(0.5 * (Pi + Pi1) + 0.5 * h * r2[1], e1)
+        nb = 0.5 * (nb + nb1) + 0.5 * h * r2[2]
+        RT2 = -(e1 / 3.0 + Pi - phi)
+        Q = Q + 0.5 * h * (RT1 + RT2)
+        tau += h
+    return np.array([Q / tau, phi, Pi, nb])
+
+
+def pin_bulk_bjorken():
+    """Bjorken flow with shear, bulk pressure and a conserved density: the 3D oracle
+    must reduce exactly to the 0+1D scheme (uniform grid), converge at O(h^2) to a
+    DOP853 solution of d(eps, Phi, Pi, n)/d tau, keep n tau constant (the RK2 step
+    maps n to n tau/(tau + h) exactly here),
+    and approach the Navier-Stokes bulk pressure -zeta/tau late."""
+    tau0, T0 = 0.6, 0.4
+    eps0 = E.C_SB * T0 ** 4
+    s0 = (4.0 / 3.0 * eps0) / T0
+    phi0 = 4.0 * _BULK["etas"] * s0 * E.HBARC / (3.0 * tau0)
+    Pi0 = -_BULK["zetas"] * s0 * E.HBARC / tau0
+    n0 = 2.0
+    y0 = (eps0, phi0, Pi0, n0)
+    g = ics.Grid(3, 4, 5, 0.3, 0.3, 0.3)
+    errs, red_dev = [], 0.0
+    tend = tau0 + 1.0
+    for h in (0.02, 0.01):
+        n = int(round((tend - tau0) / h))
+        o = _orc(*g.shape, g.dx, g.dy, g.de, tau0, h, viscous=True, baryon=True, **_BULK)
+        ic = ics.bjorken(g, eps0, phi0)
+        ic["Pi"] = np.full(g.shape, Pi0)
+        ic["nb"] = np.full(g.shape, n0)
+        o.set_initial(ic)
+        o.step(n)
+        got = np.array([o.read("eps"), -o.read("pi9"), o.read("Pi"), o.read("nb")])
+        red = _bulk_reduced(y0, tau0, h, n, **_BULK)
+        red_dev = max(red_dev, float(np.max(np.abs(got / red[:, None, None, None] - 1.0))))
+        ref = A.bulk_bjorken_reference(y0, tau0, tau0 + n * h, **_BULK)
+        errs.append(float(np.max(np.abs(got[:, 0, 0, 0] / ref - 1.0))))
+    ratio = errs[0] / errs[1]
+    # late time: Pi approaches -zeta theta (loose: O(tau_Pi / tau) corrections)
+    h = 0.02
+    o = _orc(*g.shape, g.dx, g.dy, g.de, tau0, h, viscous=True, baryon=True, **_BULK)
+    ic = ics.bjorken(g, eps0, phi0)
+    ic["Pi"] = np.full(g.shape, Pi0)
+    ic["nb"] = np.full(g.shape, n0)
+    o.set_initial(ic)
+    n = int(round(5.4 / h))
+    o.step(n)
+    tau = tau0 + n * h
+    e = o.read("eps")[0, 0, 0]
+    T = (e / E.C_SB) ** 0.25
+    Pi_ns = -_BULK["zetas"] * (4.0 / 3.0 * e / T) * E.HBARC / tau
+    ns_dev = abs(o.read("Pi")[0, 0, 0] / Pi_ns - 1.0)
+    ntau_dev = abs(o.read("nb")[0, 0, 0] * tau / (n0 * tau0) - 1.0)
+    ok = red_dev < 1e-12 and 3.5 < ratio < 4.5 and ns_dev < 0.05 and ntau_dev < 1e-12
+    return ok, dict(red_dev=red_dev, ratio=ratio, errs=errs, ns_dev=ns_dev, ntau_dev=ntau_dev)
+
+
+def pin_bulk_con2prim():
+    """Root solve with a bulk pressure: states (e, u~, Pi) with |Pi| < P mapped to
+    K = (e+P+Pi) u~^tau u~ - (P+Pi) g~^{tau .} here must come back to 1e-12."""
+    rng = np.random.default_rng(11)
+    n = 400
+    e = 10.0 ** rng.uniform(-3, 2, n)
+    u = rng.normal(0.0, 1.5, (n, 3))
+    Pi = rng.uniform(-0.95, 0.95, n) * e / 3.0
+    ut = np.sqrt(1.0 + (u * u).sum(axis=1))
+    W = e + e / 3.0 + Pi
+    K = np.empty((n, 4))
+    K[:, 0] = W * ut * ut - (e / 3.0 + Pi)
+    K[:, 1:] = (W * ut)[:, None] * u
+    o = _orc(1, 1, 1, 1.0, 1.0, 1.0, 1.0, 0.1, viscous=True, **_BULK)
+    eo, uo, _, fl = o.con2prim_bulk(K, Pi)
+    de = float(np.max(np.abs(eo / e - 1.0)))
+    du = float(np.max(np.abs(uo - u) / (1.0 + np.abs(u))))
+    ok = de < 1e-10 and du < 1e-10 and not np.any(fl & 1)
+    return ok, dict(de=de, du=du)
+
+
+def pin_bulk_gradient():
+    """A fluid at rest with uniform e and a linear bulk pressure Pi = a + b x
+    (Cartesian): T^{xx} = P + Pi, so d_t T^{tx} = -b at t = 0.  After one step h the
+    interior T^{tx} must be -b h to 2% (Pi relaxes by about h / (2 tau_Pi) meanwhile)."""
+    nx, dx, h = 24, 0.2, 0.001
+    g = ics.Grid(nx, 1, 1, dx, 1.0, 1.0)
+    X, _, _ = g.mesh()
+    e0, a, b = 10.0, 0.3, 0.05
+    o = _orc(nx, 1, 1, dx, 1.0, 1.0, 1.0, h, cartesian=True, viscous=True, **_BULK)
+    o.set_initial(dict(eps=np.full(g.shape, e0), ux=np.zeros(g.shape), uy=np.zeros(g.shape),
+                       ue=np.zeros(g.shape), Pi=a + b * X))
+    o.step(1)
+    Ttx = o.read("T1")[3:-3, 0, 0]
+    dev = float(np.max(np.abs(Ttx / (-b * h) - 1.0)))
+    return dev < 0.02, dict(dev=dev)
+
+
+def pin_baryon_gubser():
+    """Net-baryon density on the viscous Gubser flow (Sec. V.C setup: L = 2 fm,
+    eta/s = 0.2, lambda1_hat = -10), started from n = n^0 / (tau^3 cosh^2 rho): at
+    tau = 2 fm the interior (r <= 3 fm) L1 error of n must fall >= 2.5x from 41^2 to
+    81^2 cells and be below 0.5% on the fine grid."""
+    L, etas, lam, nh = 2.0, 0.2, -10.0, 3.0
+    coef = ics.gubser_viscous_taupi_coef(lam)
+    out = []
+    for n, dx, h in ((41, 0.3, 0.02), (81, 0.15, 0.01)):
+        g = ics.Grid(n, n, 1, dx, dx, 0.3)
+        o = _orc(n, n, 1, dx, dx, 0.3, 1.0, h, etas=etas, viscous=True, taupi_coef=coef,
+                 lambda1_hat=lam, baryon=True)
+        X, Y, _ = g.mesh()
+        ic = ics.gubser_viscous(g, 1.0, L=L, lambda1_hat=lam)
+        ic["nb"] = A.gubser_density(X, Y, 1.0, L, nh)
+        o.set_initial(ic)
+        o.step(int(round(1.0 / h)))
+        ex = A.gubser_density(X, Y, 2.0, L, nh)
+        m = (X ** 2 + Y ** 2) <= 9.0
+        out.append(float(np.abs(o.read("nb") - ex)[m].mean() / ex[m].max()))
+    r = out[0] / out[1]
+    return r >= 2.5 and out[1] < 0.005, dict(ratio=r, errs=out)
+
+
+# ---------------------------------------------------------------------------
 # Freeze-out surface finder (Sec. IV surface of constant e_f; surface_oracle.c)
 # ---------------------------------------------------------------------------
 def _slices(fn, shape, spacing, tau, nf=4):
@@ -875,6 +1028,10 @@ ALL_PINS = {
     "transversality": pin_transversality,
     "lambda1_static": pin_lambda1_static,
     "gubser_viscous": pin_gubser_viscous,
+    "bulk_bjorken": pin_bulk_bjorken,
+    "bulk_con2prim": pin_bulk_con2prim,
+    "bulk_gradient": pin_bulk_gradient,
+    "baryon_gubser": pin_baryon_gubser,
     "surface_bjorken": pin_surface_bjorken,
     "surface_plane": pin_surface_plane,
     "surface_gubser": pin_surface_gubser,

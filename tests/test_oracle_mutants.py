@@ -16,7 +16,9 @@ Mutants (see MUT(k) in oracle/hydro_oracle.c):
  tetrahedron fraction, 23 edge crossings measured from the wrong end, 24 the
  one-hot-vertex fraction missing a factor; spectra: 25 delta f with (1 + sigma f)
  instead of (1 - sigma f), 26 p^eta dSigma_eta without the 1/tau of the tilde
- component, 27 the sign of p^x u^x in p.u.
+ component, 27 the sign of p^x u^x in p.u; bulk and baryon: 28 the sign of
+ zeta theta in S_Pi, 29 S_Pi without its Pi u~^tau/tau term, 30 Pi left out of
+ T's density and flux, 31 the root solve without Pi, 32 S_n dropped.
 Mutant 16 (u* = u^n instead of 2u^n - u^{n-1}) alters only the predicted pi'
 at O(h) and the step at O(h^2), the scheme's own order, so no pin is expected
 to separate it; the GPU-oracle parity tests cover that code path.
@@ -30,7 +32,7 @@ import oracle as O
 
 from . import pins
 
-CAUGHT = list(range(1, 16)) + list(range(17, 28))
+CAUGHT = list(range(1, 16)) + list(range(17, 33))
 
 
 @pytest.mark.parametrize("k", CAUGHT)
