@@ -32,6 +32,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 BYTES_PER_CELL = {"stage1": (21 + 18) * 8, "stage2_pi": (31 + 10) * 8, "stage2_T": (22 + 8) * 8,
                   "first_estimate": (4 + 3) * 8, "init": 0, "reduce": 0}
 BYTES_PER_CELL_IDEAL = {"stage1": (8 + 5) * 8, "stage2_T": (8 + 4) * 8}
+# With bulk pressure Pi and baryon density n the transported set has 12 fields:
+# stage1 and stage2_pi read and write Pi and n with pi~ (+2 per pi~ block),
+# stage2_T reads Pi^{n+1} (+1).
+BYTES_PER_CELL_BULK = {"stage1": (23 + 20) * 8, "stage2_pi": (35 + 12) * 8,
+                       "stage2_T": (23 + 8) * 8}
 
 
 def source_sha256() -> str:
@@ -77,10 +82,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--workload", default="hotspots",
-                    choices=["hotspots", "gubser_dense", "large", "batch64"],
+                    choices=["hotspots", "gubser_dense", "large", "batch64", "bulk"],
                     help="hotspots: the benchmark configuration; gubser_dense: the same grid and "
                          "physics with a smooth Gubser profile that leaves no vacuum cells; large: "
-                         "385x385x129 single event; batch64: 64 uneven events in grouped launches")
+                         "385x385x129 single event; batch64: 64 uneven events in grouped launches; "
+                         "bulk: the benchmark configuration with bulk pressure and baryon density")
     ap.add_argument("--graph", action="store_true", help="replay each step as a HIP graph")
     ap.add_argument("--autotune", action="store_true",
                     help="time every tile shape first (on a discarded run) and use the fastest")
@@ -120,7 +126,7 @@ def main():
         print(json.dumps(bench_batch(args, learned=args.guess == "mlp")), flush=True)
         return
     wl = {"hotspots": W.hotspots_viscous, "gubser_dense": W.gubser_dense_viscous,
-          "large": W.large_event}[args.workload](steps=args.steps)
+          "large": W.large_event, "bulk": W.hotspots_bulk}[args.workload](steps=args.steps)
     if args.only_surface:
         print(json.dumps({"workload": wl.name, "freezeout_surface": surface_path(wl)}), flush=True)
         return
@@ -178,6 +184,8 @@ def main():
     value = ncell * args.steps / dt
     dom = max(per_kernel, key=lambda n: per_kernel[n]["total_ms"])
     bpc = BYTES_PER_CELL if p["viscous"] else BYTES_PER_CELL_IDEAL
+    if p.get("zetas", 0) > 0 or p.get("baryon", 0):
+        bpc = dict(BYTES_PER_CELL, **BYTES_PER_CELL_BULK)
     bytes_launch = bpc[dom] * ncell
     achieved = bytes_launch / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
     step_bytes = sum(bpc.get(n, 0) * ncell * per_kernel[n]["launches"] for n in per_kernel)
@@ -229,6 +237,15 @@ def main():
         out["paths"]["fp64_lambda1"] = mixed_path(wl, args, precision=0, lambda1_hat=-10.0)
         out["paths"]["fp64_lambda1"]["note"] = ("second-order lambda_1 term on, lambda1_hat = -10, "
                                                 "tau_pi = 5 eta/(sT)")
+        if wl.name.startswith("hotspots_viscous"):
+            pw = wl.params
+            wb = W.hotspots_bulk(nx=pw["nx"], ny=pw["ny"], ne=pw["ne"], dx=pw["dx"], dy=pw["dy"],
+                                 de=pw["de"])
+            out["paths"]["fp64_bulk_baryon"] = mixed_path(wb, args, precision=0,
+                                                          bytes_per_cell=BYTES_PER_CELL_BULK)
+            out["paths"]["fp64_bulk_baryon"]["note"] = (
+                "bulk pressure (zeta/s = 0.04, tau_Pi = 5 (zeta/s) hbarc/T) and net-baryon "
+                "density transported (16 components per face)")
         b = bench_batch(args, precision=1, learned=True, steps=10, warmup=2)
         out["paths"]["batch64_mixed_learned"] = {
             k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "newton_mean", "training")}
@@ -238,13 +255,15 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def mixed_path(wl, args, precision=1, quiet=False, **extra):
+def mixed_path(wl, args, precision=1, quiet=False, bytes_per_cell=None, **extra):
     """The same workload with FP32 reconstruction, fluxes and relaxation source
     (FP64 root solve, geometric source and state; errors against the FP64
     oracle are bounded by the GPU tests, <= 1e-6 in e and u~), or (precision 0,
     quiet) in FP64 with quiet tiles skipped (fields and diagnostics identical to
     the full computation bit for bit, tested).  `extra` overrides descriptor
-    fields (the second-order path sets lambda1_hat)."""
+    fields (the second-order path sets lambda1_hat).  With bytes_per_cell the
+    timed steps also record each pass's average duration (HIP events on the
+    library's stream) and its algorithmic HBM rate."""
     import torch
 
     import paper_1802_04449_amd as K
@@ -260,12 +279,27 @@ def mixed_path(wl, args, precision=1, quiet=False, **extra):
         g.set_initial(wl.ic)
     g.step(args.warmup)
     torch.cuda.synchronize()
+    if bytes_per_cell:
+        K.ktmi_set_timing(g.h, True)
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     g.step(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     out = {"value": wl.ncell * args.steps / dt, "unit": "cell-updates/s",
            "ms_per_step": dt / args.steps * 1e3, "steps": args.steps}
+    if bytes_per_cell:
+        kern = {}
+        for k, n in enumerate(K.ktmi_kernel_names()):
+            tot, cnt = K.ktmi_timing(g.h, k)
+            if cnt and n in bytes_per_cell:
+                ms = tot / cnt
+                gbs = bytes_per_cell[n] * wl.ncell / (ms * 1e-3) / 1e9
+                kern[n] = {"avg_launch_ms": round(ms, 4), "achieved_GBs": round(gbs, 1),
+                           "frac": round(gbs / HBM_PEAK_GBS, 4),
+                           "bytes_per_cell": bytes_per_cell[n]}
+        K.ktmi_set_timing(g.h, False)
+        out["kernels"] = kern
     if quiet:
         out["quiet_tiles"], out["tiles"] = K.ktmi_quiet_tiles(g.h)
     return out

@@ -9,6 +9,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 
+import numpy as np
+
 from . import eos as E
 from . import ics
 
@@ -69,6 +71,21 @@ def hotspots_viscous(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps=200
     g = ics.Grid(nx, ny, ne, dx, dy, de)
     return Workload(f"hotspots_viscous_{nx}x{ny}x{ne}", p, E.cached_synthetic_table(), steps,
                     ic=ics.hotspots(g, seed=seed))
+
+
+def hotspots_bulk(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps=200, seed=1,
+                  etas=0.08, zetas=0.04, baryon=True, n_peak=0.3) -> Workload:
+    """hotspots_viscous with bulk viscosity zeta/s = 0.04 (tau_Pi coefficient 5) and the
+    net-baryon density transported: Pi starts at zero, n = n_peak (e / e_max)^(3/4) fm^-3
+    (the shape of an entropy density; n_peak = 0.3 fm^-3 about twice nuclear density)."""
+    p = _params(nx, ny, ne, dx, dy, de, 0.6, 0.01, etas=etas, viscous=True)
+    p.update(zetas=zetas, taubulk_coef=5.0, baryon=int(baryon))
+    g = ics.Grid(nx, ny, ne, dx, dy, de)
+    ic = ics.hotspots(g, seed=seed)
+    ic["Pi"] = np.zeros(g.shape)
+    ic["nb"] = n_peak * (ic["eps"] / ic["eps"].max()) ** 0.75 if baryon else None
+    return Workload(f"hotspots_bulk_{nx}x{ny}x{ne}", p, E.cached_synthetic_table(), steps, ic=ic,
+                    note="bulk pressure and baryon density")
 
 
 def hotspots_minijets(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps=200, seed=2,

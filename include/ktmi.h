@@ -58,7 +58,9 @@ enum {
     KTMI_F_UX = 1,    /* u~^x, u~^y, u~^eta: 1..3 */
     KTMI_F_PI = 4,    /* pi~ components: 4..13 in the order above */
     KTMI_F_T = 14,    /* T~^{tau mu}: 14..17 */
-    KTMI_F_UPREV = 18 /* u~ at the previous time level: 18..20 */
+    KTMI_F_UPREV = 18, /* u~ at the previous time level: 18..20 */
+    KTMI_F_BULK = 21,  /* bulk pressure Pi (zero without bulk viscosity) */
+    KTMI_F_NB = 22     /* net-baryon density n (zero unless transported) */
 };
 
 typedef struct ktmi_desc {
@@ -84,6 +86,17 @@ typedef struct ktmi_desc {
     double lambda1_hat;  /* second-order term of eqn. pimn, -(lambda_1/tau_pi) pi^<mu_l pi^nu>l,
                             with lambda_1 = lambda1_hat / e (the dimensionless lambda1_hat = lambda_1 e
                             of Sec. V.C); 0 = the equations of Sec. II.  Must be finite */
+    double zetas;        /* zeta / s of the bulk pressure Pi (eqn. Pitilde; 0 in every run of the
+                            paper, which is the default: no bulk pressure).  Must be finite, >= 0 */
+    double taubulk_coef; /* tau_Pi = taubulk_coef (zeta/s) hbarc / T (default 5); > 0 with bulk */
+    int baryon;          /* 1: transport the net-baryon density n (eqn. Ntilde; passive, the EoS
+                            tables here being those of zero baryon chemical potential); 0 default.
+                            Bulk pressure and baryon density need viscous mode, FP64 and
+                            lambda1_hat = 0, and do not use the learned guess.  Pi and n obey
+                            d~_tau(u~^tau X) + d~_i(u~^i X) = S_X with
+                            S_Pi = -(Pi + zeta theta)/tau_Pi - Pi theta/3 - Pi u~^tau/tau,
+                            zeta = (zeta/s)(e+P) hbarc/T, S_n = -n u~^tau/tau; Pi adds to P in
+                            T^{mu nu} and in the root solve; the regulator clips Pi to [-P, P] */
 } ktmi_desc;
 
 typedef struct ktmi_diagnostics {
@@ -102,12 +115,14 @@ typedef struct ktmi_handle ktmi_handle;
 
 /* Fills d with the defaults: cutoff 1e-7, theta 1.8, tolerance 1e-12, 100
  * iterations, regulator 1.0, FP64, previous-stage guess, automatic tile,
- * taupi_coef 5, lambda1_hat 0.  Sizes are zero. */
+ * taupi_coef 5, lambda1_hat 0, zetas 0, taubulk_coef 5, baryon 0.  Sizes are zero. */
 void ktmi_desc_default(ktmi_desc *d);
 
 /* Validates d and creates a handle (host memory only).  KTMI_EINVAL if a size
  * is < 1, a spacing, tau0 or h is not > 0, viscous with etas <= 0 or
- * taupi_coef <= 0, or lambda1_hat is not finite. */
+ * taupi_coef <= 0, lambda1_hat is not finite, zetas is not finite and >= 0,
+ * baryon is not 0 or 1, or bulk/baryon is asked for without viscous mode, FP64
+ * and lambda1_hat = 0, or with taubulk_coef <= 0. */
 int ktmi_create(const ktmi_desc *d, ktmi_handle **out);
 
 /* Bytes of device workspace the handle needs (0 if d is invalid). */
@@ -137,7 +152,16 @@ int ktmi_set_eos_table(ktmi_handle *h, double e0, double de, int n, const double
 int ktmi_set_initial_primitive(ktmi_handle *h, const double *e, const double *ux,
                                const double *uy, const double *ue, const double *pi10);
 
-/* Initial conserved state: 4 device blocks of T~^{tau mu} and optional pi~;
+/* As ktmi_set_initial_primitive, plus the bulk pressure Pi and the net-baryon
+ * density n (eqns. Pitilde, Ntilde): device arrays of nx*ny*ne doubles, NULL for
+ * zero; Pi is ignored unless zetas > 0, n unless baryon.  T~ is formed with
+ * P + Pi; Pi and n are zero below the cutoff. */
+int ktmi_set_initial_primitive_ext(ktmi_handle *h, const double *e, const double *ux,
+                                   const double *uy, const double *ue, const double *pi10,
+                                   const double *Pi, const double *n);
+
+/* Initial conserved state: 4 device blocks of T~^{tau mu} and optional pi~
+ * (Pi = n = 0 with bulk/baryon);
  * the root solve (starting from E) yields (e, u~).  Then as above. */
 int ktmi_set_initial_conserved(ktmi_handle *h, const double *T4, const double *pi10);
 

@@ -24,6 +24,7 @@ FIELDS = {"eps": 0, "ux": 1, "uy": 2, "ue": 3}
 FIELDS.update({f"pi{m}": 4 + m for m in range(10)})
 FIELDS.update({f"T{m}": 14 + m for m in range(4)})
 FIELDS.update({"uprev_x": 18, "uprev_y": 19, "uprev_e": 20})
+FIELDS.update({"Pi": 21, "nb": 22})  # bulk pressure, net-baryon density
 
 
 class ktmi_desc(C.Structure):
@@ -34,7 +35,8 @@ class ktmi_desc(C.Structure):
                 ("eps_cut", C.c_double), ("theta", C.c_double), ("newton_tol", C.c_double),
                 ("newton_maxit", C.c_int), ("pi_reg", C.c_double), ("precision", C.c_int),
                 ("guess", C.c_int), ("tile", C.c_int), ("taupi_coef", C.c_double),
-                ("lambda1_hat", C.c_double)]
+                ("lambda1_hat", C.c_double), ("zetas", C.c_double),
+                ("taubulk_coef", C.c_double), ("baryon", C.c_int)]
 
 
 class ktmi_diagnostics(C.Structure):
@@ -62,6 +64,7 @@ def _load():
         "ktmi_set_eos_conformal": (C.c_int, [vp, C.c_double]),
         "ktmi_set_eos_table": (C.c_int, [vp, C.c_double, C.c_double, C.c_int, dp, dp, dp]),
         "ktmi_set_initial_primitive": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "ktmi_set_initial_primitive_ext": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "ktmi_set_initial_conserved": (C.c_int, [vp, vp, vp]),
         "ktmi_step": (C.c_int, [vp, C.c_int]),
         "ktmi_read": (C.c_int, [vp, C.c_int, vp]),
@@ -163,6 +166,14 @@ def ktmi_set_initial_primitive(h, e_ptr, ux_ptr, uy_ptr, ue_ptr, pi_ptr=None):
     _check(lib.ktmi_set_initial_primitive(h, C.c_void_p(e_ptr), C.c_void_p(ux_ptr),
                                           C.c_void_p(uy_ptr), C.c_void_p(ue_ptr),
                                           C.c_void_p(pi_ptr) if pi_ptr else None), h)
+
+
+def ktmi_set_initial_primitive_ext(h, e_ptr, ux_ptr, uy_ptr, ue_ptr, pi_ptr=None, Pi_ptr=None,
+                                   n_ptr=None):
+    def vp(x):
+        return C.c_void_p(x) if x else None
+    _check(lib.ktmi_set_initial_primitive_ext(h, vp(e_ptr), vp(ux_ptr), vp(uy_ptr), vp(ue_ptr),
+                                              vp(pi_ptr), vp(Pi_ptr), vp(n_ptr)), h)
 
 
 def ktmi_set_initial_conserved(h, T_ptr, pi_ptr=None):
@@ -424,8 +435,17 @@ class Hydro:
             keep = [self._dev(ic[k]).reshape(-1) for k in ("eps", "ux", "uy", "ue")]
             pi = ic.get("pi")
             pit = None if pi is None else self._dev(pi).reshape(10, -1)
-            ktmi_set_initial_primitive(self.h, *[t.data_ptr() for t in keep],
-                                       pit.data_ptr() if pit is not None else None)
+            Pi, nb = ((None if ic.get(k) is None else self._dev(ic[k]).reshape(-1))
+                      for k in ("Pi", "nb"))
+            if Pi is None and nb is None:
+                ktmi_set_initial_primitive(self.h, *[t.data_ptr() for t in keep],
+                                           pit.data_ptr() if pit is not None else None)
+            else:
+                ktmi_set_initial_primitive_ext(
+                    self.h, *[t.data_ptr() for t in keep],
+                    pit.data_ptr() if pit is not None else None,
+                    Pi.data_ptr() if Pi is not None else None,
+                    nb.data_ptr() if nb is not None else None)
             self.stream.synchronize()
 
     def set_initial_conserved(self, T4, pi=None):

@@ -24,8 +24,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
-NUM_PASSES = 8  # first estimate, stage1 (viscous, ideal), stage2 pi, stage2 T (viscous, ideal),
-#                 stage1 viscous and stage2 pi with the lambda_1 term
+NUM_PASSES = 11  # first estimate, stage1 (viscous, ideal), stage2 pi, stage2 T (viscous, ideal),
+#                 stage1 viscous and stage2 pi with the lambda_1 term, stage1 / stage2 pi /
+#                 stage2 T with bulk pressure and baryon density
 
 
 def _jobs():

@@ -21,14 +21,15 @@
 
 namespace ktmi {
 
-// Initial primitive state: cutoff, then T~^{tau mu} = tau0 Tc^{tau mu}(e, u~, pi~).
+// Initial primitive state: cutoff, then T~^{tau mu} = tau0 Tc^{tau mu}(e, u~, pi~)
+// (ext: with P + Pi, and Pi, n zero below the cutoff).
 __global__ __launch_bounds__(kBlock) void k_init_primitive(Fields f, StepParams p, EosDev eos,
-                                                            Geo g, int visc) {
+                                                            Geo g, int visc, int ext) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= p.ncell) return;
   double e = f.e[c];
   double u1 = f.u[0][c], u2 = f.u[1][c], u3 = f.u[2][c];
-  double pv[10];
+  double pv[10], Pi = ext ? f.pi[10][c] : 0.0;
 #pragma unroll
   for (int m = 0; m < 10; ++m) pv[m] = visc ? f.pi[m][c] : 0.0;
   if (!(e >= p.eps_cut)) {
@@ -36,9 +37,15 @@ __global__ __launch_bounds__(kBlock) void k_init_primitive(Fields f, StepParams 
     u1 = u2 = u3 = 0.0;
 #pragma unroll
     for (int m = 0; m < 10; ++m) pv[m] = 0.0;
+    if (ext) {
+      Pi = 0.0;
+      f.pi[10][c] = 0.0;
+      f.pi[11][c] = 0.0;
+    }
   }
   double P, cs2;
   eos_p_cs2(eos, e, P, cs2);
+  if (ext) P += Pi;
   const double ut = utau(u1, u2, u3);
   const double w = e + P;
   const double tf = g.cart ? 1.0 : g.tau;
@@ -264,6 +271,24 @@ static bool desc_ok(const ktmi_desc* d, std::string* why) {
     *why = "lambda1_hat must be finite";
     return false;
   }
+  if (!(d->zetas >= 0.0) || !std::isfinite(d->zetas) || (d->baryon != 0 && d->baryon != 1)) {
+    *why = "zetas must be finite and >= 0, baryon 0 or 1";
+    return false;
+  }
+  if (d->zetas > 0.0 || d->baryon) {
+    if (!d->viscous) {
+      *why = "bulk pressure and baryon density need viscous mode";
+      return false;
+    }
+    if (d->zetas > 0.0 && !(d->taubulk_coef > 0)) {
+      *why = "bulk viscosity needs taubulk_coef > 0";
+      return false;
+    }
+    if (d->precision != KTMI_FP64 || d->lambda1_hat != 0.0) {
+      *why = "bulk pressure and baryon density run in FP64 without the lambda_1 term";
+      return false;
+    }
+  }
   if (!(d->theta >= 1.0 && d->theta <= 2.0)) {
     *why = "theta must lie in [1, 2]";
     return false;
@@ -327,6 +352,10 @@ static size_t quiet_doubles(const ktmi_desc* d) {
 
 static const int kNumFields = 39;  // e, u(3), up(3), pi(10), T(4), e1, u1(3), pi1(10), T1(4)
 
+// Bulk pressure or baryon density in use: 4 more fields (Pi, n and their stage-1 values).
+static bool has_ext(const ktmi_desc* d) { return d->zetas > 0.0 || d->baryon; }
+static int num_fields(const ktmi_desc* d) { return kNumFields + (has_ext(d) ? 4 : 0); }
+
 static size_t field_stride(const ktmi_desc* d) {
   const size_t n = (size_t)d->nx * d->ny * d->ne;
   return (n + 31) / 32 * 32;  // 256-byte aligned fields
@@ -356,6 +385,11 @@ static StepParams step_params(const ktmi_handle* h) {
   p.inv_taupi_coef = visc_ok ? 1.0 / (h->d.taupi_coef * h->d.etas * kHbarc) : 0.0;
   p.eta_taupi = visc_ok ? 1.0 / h->d.taupi_coef : 0.0;
   p.lambda1_hat = h->d.lambda1_hat;
+  const bool bulk_ok = h->d.zetas > 0 && h->d.taubulk_coef > 0;
+  p.inv_taubulk_coef = bulk_ok ? 1.0 / (h->d.taubulk_coef * h->d.zetas * kHbarc) : 0.0;
+  p.zeta_taubulk = bulk_ok ? 1.0 / h->d.taubulk_coef : 0.0;
+  p.bulk = bulk_ok ? 1 : 0;
+  p.baryon = h->d.baryon ? 1 : 0;
   p.c_vac = sqrt(h->cs2_vac);
   p.eps_cut = h->d.eps_cut;
   p.theta = h->d.theta;
@@ -413,7 +447,9 @@ static const PassLauncher kPassLaunch[PASS_COUNT][2] = {
     {launch_pass0_f64, launch_pass0_f32}, {launch_pass1_f64, launch_pass1_f32},
     {launch_pass2_f64, launch_pass2_f32}, {launch_pass3_f64, launch_pass3_f32},
     {launch_pass4_f64, launch_pass4_f32}, {launch_pass5_f64, launch_pass5_f32},
-    {launch_pass6_f64, launch_pass6_f32}, {launch_pass7_f64, launch_pass7_f32}};
+    {launch_pass6_f64, launch_pass6_f32}, {launch_pass7_f64, launch_pass7_f32},
+    {launch_pass8_f64, launch_pass8_f32}, {launch_pass9_f64, launch_pass9_f32},
+    {launch_pass10_f64, launch_pass10_f32}};
 
 static void launch_class(int pass, hipStream_t s, int tile, int precision, bool net,
                          const EventDesc* evs, const GroupTable& gt) {
@@ -458,19 +494,21 @@ static int upload_event(ktmi_handle* h) {
 }
 
 // The kernels of one step for the events of one class (same tile, precision, mode).
-// mode: 0 ideal, 1 viscous (Sec. II), 2 viscous with the lambda_1 term.
+// mode: 0 ideal, 1 viscous (Sec. II), 2 viscous with the lambda_1 term, 3 viscous
+// with bulk pressure and baryon density (no network instances: net is ignored).
 static int enqueue_class_step(ktmi_handle* h, hipStream_t s, int tile, int precision, int mode,
                               bool net, const EventDesc* evs, const GroupTable& gt) {
   int rc;
   if (mode) {
-    const int p1 = mode == 2 ? PASS_STAGE1_V_L1 : PASS_STAGE1_V;
-    const int p2 = mode == 2 ? PASS_STAGE2_PI_L1 : PASS_STAGE2_PI;
-    rc = launch(h, K_STAGE1, [&] { launch_class(p1, s, tile, precision, net, evs, gt); });
+    const int p1 = mode == 3 ? PASS_STAGE1_BK : (mode == 2 ? PASS_STAGE1_V_L1 : PASS_STAGE1_V);
+    const int p2 = mode == 3 ? PASS_STAGE2_PI_BK : (mode == 2 ? PASS_STAGE2_PI_L1 : PASS_STAGE2_PI);
+    const int p3 = mode == 3 ? PASS_STAGE2_T_BK : PASS_STAGE2_T_V;
+    const bool nn = net && mode != 3;
+    rc = launch(h, K_STAGE1, [&] { launch_class(p1, s, tile, precision, nn, evs, gt); });
     if (rc) return rc;
     rc = launch(h, K_STAGE2PI, [&] { launch_class(p2, s, tile, precision, false, evs, gt); });
     if (rc) return rc;
-    return launch(h, K_STAGE2T,
-                  [&] { launch_class(PASS_STAGE2_T_V, s, tile, precision, net, evs, gt); });
+    return launch(h, K_STAGE2T, [&] { launch_class(p3, s, tile, precision, nn, evs, gt); });
   }
   rc = launch(h, K_STAGE1,
               [&] { launch_class(PASS_STAGE1_I, s, tile, precision, net, evs, gt); });
@@ -481,9 +519,11 @@ static int enqueue_class_step(ktmi_handle* h, hipStream_t s, int tile, int preci
 
 static bool uses_net(const ktmi_handle* h) { return h->d.guess == KTMI_GUESS_MLP; }
 
-// 0 ideal, 1 viscous, 2 viscous with the lambda_1 term
+// 0 ideal, 1 viscous, 2 viscous with the lambda_1 term, 3 with bulk / baryon
 static int step_mode(const ktmi_handle* h) {
-  return !h->d.viscous ? 0 : (h->d.lambda1_hat != 0.0 ? 2 : 1);
+  if (!h->d.viscous) return 0;
+  if (has_ext(&h->d)) return 3;
+  return h->d.lambda1_hat != 0.0 ? 2 : 1;
 }
 
 static int enqueue_step(ktmi_handle* h) {
@@ -594,6 +634,9 @@ void ktmi_desc_default(ktmi_desc* d) {
   d->tile = -1;
   d->taupi_coef = 5.0;
   d->lambda1_hat = 0.0;
+  d->zetas = 0.0;
+  d->taubulk_coef = 5.0;
+  d->baryon = 0;
 }
 
 size_t ktmi_workspace_bytes(const ktmi_desc* d) {
@@ -601,7 +644,7 @@ size_t ktmi_workspace_bytes(const ktmi_desc* d) {
   if (!desc_ok(d, &why)) return 0;
   const size_t fs = field_stride(d);
   const size_t nb = (size_t)max_tiles(d);
-  size_t bytes = (size_t)kNumFields * fs * sizeof(double);
+  size_t bytes = (size_t)num_fields(d) * fs * sizeof(double);
   bytes += ((2 * nb * kNP + 31) / 32 * 32) * sizeof(double);  // partials
   bytes += 32 * sizeof(double);                               // accumulators
   bytes += quiet_doubles(d) * sizeof(double);                 // quiet-tile flags
@@ -660,6 +703,10 @@ int ktmi_bind(ktmi_handle* h, void* ws, size_t bytes, void* stream) {
   for (int m = 0; m < 3; ++m) f.u1[m] = base + fs * q++;
   for (int m = 0; m < 10; ++m) f.pi1[m] = base + fs * q++;
   for (int m = 0; m < 4; ++m) f.T1[m] = base + fs * q++;
+  for (int m = 10; m < 12; ++m) {  // Pi and n, after the other fields
+    f.pi[m] = has_ext(&h->d) ? base + fs * q++ : nullptr;
+    f.pi1[m] = has_ext(&h->d) ? base + fs * q++ : nullptr;
+  }
   double* rest = base + fs * q;
   f.partial = rest;
   rest += (2 * (size_t)max_tiles(&h->d) * kNP + 31) / 32 * 32;
@@ -749,6 +796,12 @@ int ktmi_set_eos_table(ktmi_handle* h, double e0, double de, int n, const double
 
 int ktmi_set_initial_primitive(ktmi_handle* h, const double* e, const double* ux,
                                const double* uy, const double* ue, const double* pi10) {
+  return ktmi_set_initial_primitive_ext(h, e, ux, uy, ue, pi10, nullptr, nullptr);
+}
+
+int ktmi_set_initial_primitive_ext(ktmi_handle* h, const double* e, const double* ux,
+                                   const double* uy, const double* ue, const double* pi10,
+                                   const double* Pi, const double* nbar) {
   if (!h) return KTMI_EINVAL;
   if (int rc = check_setup(h)) return rc;
   if (!e || !ux || !uy || !ue) return fail(h, KTMI_EINVAL, "null field pointer");
@@ -764,12 +817,22 @@ int ktmi_set_initial_primitive(ktmi_handle* h, const double* e, const double* ux
     else
       hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, h->f.pi[m], (int)n);
   }
+  const bool ext = has_ext(&h->d);
+  if (ext) {
+    const double* src[2] = {h->d.zetas > 0.0 ? Pi : nullptr, h->d.baryon ? nbar : nullptr};
+    for (int m = 0; m < 2; ++m) {
+      if (src[m])
+        HIP_TRY(h, hipMemcpyAsync(h->f.pi[10 + m], src[m], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      else
+        hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, h->f.pi[10 + m], (int)n);
+    }
+  }
   h->tau = h->d.tau0;
   const StepParams p = step_params(h);
   const Geo g = geo(h, h->tau, h->tau);
   int rc = launch(h, K_INIT, [&] {
     hipLaunchKernelGGL(k_init_primitive, dim3(h->nblk), dim3(kBlock), 0, s, h->f, p, h->eos, g,
-                       h->d.viscous);
+                       h->d.viscous, ext ? 1 : 0);
   });
   if (rc) return rc;
   return finish_initial(h);
@@ -789,6 +852,9 @@ int ktmi_set_initial_conserved(ktmi_handle* h, const double* T4, const double* p
     else
       hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, h->f.pi[m], (int)n);
   }
+  if (has_ext(&h->d))  // Pi = n = 0
+    for (int m = 10; m < 12; ++m)
+      hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, h->f.pi[m], (int)n);
   h->tau = h->d.tau0;
   const StepParams p = step_params(h);
   const Geo g = geo(h, h->tau, h->tau);
@@ -904,6 +970,14 @@ int ktmi_read(ktmi_handle* h, int field, double* dst) {
   else if (field >= KTMI_F_PI && field < KTMI_F_PI + 10) {
     hipLaunchKernelGGL(k_read_pi, dim3(h->nblk), dim3(kBlock), 0, s, h->f.e,
                        h->f.pi[field - KTMI_F_PI], dst, n);
+    HIP_TRY(h, hipGetLastError());
+    return KTMI_OK;
+  } else if (field == KTMI_F_BULK || field == KTMI_F_NB) {
+    if (has_ext(&h->d))
+      hipLaunchKernelGGL(k_read_pi, dim3(h->nblk), dim3(kBlock), 0, s, h->f.e,
+                         h->f.pi[10 + field - KTMI_F_BULK], dst, n);
+    else
+      hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, dst, n);
     HIP_TRY(h, hipGetLastError());
     return KTMI_OK;
   } else if (field >= KTMI_F_T && field < KTMI_F_T + 4)

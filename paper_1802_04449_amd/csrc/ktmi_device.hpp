@@ -34,6 +34,11 @@ struct StepParams {
   double inv_taupi_coef;  // 1 / (b eta/s hbarc): 1/tau_pi = T * inv_taupi_coef (b = 5, Sec. II)
   double eta_taupi;       // 1 / b: eta_v / tau_pi = (e + P) / b
   double lambda1_hat;     // lambda_1 = lambda1_hat / e (0: no second-order term)
+  // bulk pressure (eqn. Pitilde): 1/tau_Pi = T * inv_taubulk_coef with tau_Pi =
+  // c (zeta/s) hbarc / T, zeta / tau_Pi = (e + P) * zeta_taubulk (= 1/c); both 0
+  // without bulk viscosity.  baryon: 1 when the net-baryon density is transported.
+  double inv_taubulk_coef, zeta_taubulk;
+  int bulk, baryon;
   double eps_cut, theta, newton_tol, pi_reg;
   double c_vac;  // local speed of a vacuum state, sqrt(cs2(0))
   int newton_maxit;
@@ -164,6 +169,9 @@ __device__ __forceinline__ double eos_p(const EosDev& q, double e) {
 // [max(0, E - M^2/E), E].  Safeguarded Newton (bisection when a step leaves the
 // bracket) to |de| <= tol e, then one more Newton step; the cutoff applies to
 // the root.  Velocity: u~^i = K^i / sqrt((E+P)(e+P)).
+// BK (bulk pressure Pi, eqn. Pitilde): P becomes P + Pi in f, f' and the
+// velocity, and the bracket and the cap of M use B = E + min(Pi, 0) in place of
+// E (no root when B <= 0: vacuum, flagged as clamped).
 // ---------------------------------------------------------------------------
 struct Prim {
   double e, u1, u2, u3;
@@ -171,8 +179,10 @@ struct Prim {
 
 __device__ __forceinline__ Prim vacuum() { return Prim{0.0, 0.0, 0.0, 0.0}; }
 
+template <bool BK = false>
 __device__ inline Prim con2prim(const EosDev& q, const StepParams& p, double E, double K1,
-                                double K2, double K3, double guess, int& iters, int& flags) {
+                                double K2, double K3, double guess, int& iters, int& flags,
+                                double Pi = 0.0) {
   iters = 0;
   flags = 0;
   if (isnan(E) || isnan(K1) || isnan(K2) || isnan(K3)) {
@@ -183,8 +193,16 @@ __device__ inline Prim con2prim(const EosDev& q, const StepParams& p, double E, 
     flags = kVac;
     return vacuum();
   }
+  double B = E;
+  if constexpr (BK) {
+    B = E + (Pi < 0.0 ? Pi : 0.0);
+    if (!(B > 0.0)) {
+      flags = kVac | kClamp;
+      return vacuum();
+    }
+  }
   double M2 = K1 * K1 + K2 * K2 + K3 * K3;
-  const double Mmax = (1.0 - 1e-10) * E;
+  const double Mmax = (1.0 - 1e-10) * B;
   if (M2 > Mmax * Mmax) {
     const double s = Mmax / sqrt(M2);
     K1 *= s;
@@ -193,7 +211,7 @@ __device__ inline Prim con2prim(const EosDev& q, const StepParams& p, double E, 
     M2 = K1 * K1 + K2 * K2 + K3 * K3;
     flags |= kClamp;
   }
-  double lo = E - M2 / E;
+  double lo = E - M2 / B;
   lo = lo < 0.0 ? 0.0 : lo;
   double hi = E;
   const double lo0 = lo, hi0 = hi;
@@ -210,7 +228,7 @@ __device__ inline Prim con2prim(const EosDev& q, const StepParams& p, double E, 
     }
     double P, dP;
     eos_p_dp(q, x, P, dP);
-    const double r = 1.0 / (E + P);  // one division for f and f'
+    const double r = 1.0 / (BK ? (E + P) + Pi : E + P);  // one division for f and f'
     const double f = x - E + M2 * r;
     const double df = 1.0 - M2 * dP * r * r;
     if (f == 0.0) {
@@ -240,7 +258,7 @@ __device__ inline Prim con2prim(const EosDev& q, const StepParams& p, double E, 
   {
     double P, dP;
     eos_p_dp(q, x, P, dP);
-    const double r = 1.0 / (E + P);
+    const double r = 1.0 / (BK ? (E + P) + Pi : E + P);
     const double f = x - E + M2 * r;
     const double df = 1.0 - M2 * dP * r * r;
     const double xp = x - f / df;
@@ -251,7 +269,7 @@ __device__ inline Prim con2prim(const EosDev& q, const StepParams& p, double E, 
     flags |= kVac;
     return vacuum();
   }
-  const double P = eos_p(q, x);
+  const double P = BK ? eos_p(q, x) + Pi : eos_p(q, x);
   const double inv = 1.0 / sqrt((E + P) * (x + P));
   return Prim{x, K1 * inv, K2 * inv, K3 * inv};
 }

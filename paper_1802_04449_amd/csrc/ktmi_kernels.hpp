@@ -49,11 +49,12 @@ struct FieldsT {
   D* e;       // e^n, overwritten by e^{n+1} in stage2T
   D* u[3];    // u~^n
   D* up[3];   // u~^{n-1}; stage2T writes u~^{n+1} here
-  D* pi[10];  // pi~^n, overwritten by pi~^{n+1} in stage2pi
+  D* pi[12];  // pi~^n (0..9), then Pi (10) and n (11) with bulk/baryon (else null);
+              // overwritten by their n+1 values in stage2pi
   D* T[4];    // T~^{tau mu, n}, overwritten by T^{n+1} in stage2T
   D* e1;      // stage-1 prediction
   D* u1[3];
-  D* pi1[10];
+  D* pi1[12];
   D* T1[4];
   D* partial;  // [2][kNP][nblk]: stage1 then stage2T, slot-major
   D* acc;      // [16] accumulated diagnostics
@@ -73,7 +74,7 @@ __device__ __forceinline__ DFields dfields(const Fields& f) {
     d.u1[m] = (gdouble*)f.u1[m];
   }
 #pragma unroll
-  for (int m = 0; m < 10; ++m) {
+  for (int m = 0; m < 12; ++m) {
     d.pi[m] = (gdouble*)f.pi[m];
     d.pi1[m] = (gdouble*)f.pi1[m];
   }
@@ -296,14 +297,16 @@ __device__ __forceinline__ double ld_pi(const gdouble* const* pi, int m, int idx
 // clamping).  Q_T = tau Tc^{tau nu}, F_T = tau Tc^{axis nu}; Q_pi = u~^tau
 // pi~, F_pi = u~^axis pi~; c = max local speed of the two face states.  The
 // components the pass uses (T~'s if DO_T, pi~'s if DO_PI) go to out[k * F];
-// returns c.
+// returns c.  BK: the transported set also holds the bulk pressure Pi (k = 14),
+// which adds to P in T~'s Q and F (eqn. Pitilde), and the net-baryon density n
+// (k = 15); both have the flux form of the pi~ components.
 //
 // Evaluated as a stream to keep few values live: e and u~ first (face states,
 // u~^tau, P, c_s^2, e + P, speeds, the fluid part of T~'s Q and F), then one
 // pi~ component at a time (its face states, its own flux, its terms in T~'s Q
 // and F), then T~'s flux.  The arithmetic of every component is that of
 // tau (w u u - P g + pi) and u pi as written, in that order.
-template <typename R, bool DO_T, bool DO_PI, int PI_SRC>
+template <typename R, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false>
 __device__ __forceinline__ R face_flux_stream(const gdouble* __restrict__ e, const gdouble* const* u,
                                        const gdouble* const* pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
@@ -312,6 +315,7 @@ __device__ __forceinline__ R face_flux_stream(const gdouble* __restrict__ e, con
 #pragma unroll
   for (int t = 0; t < 4; ++t) idx[t] = base + clampi(a - 1 + t, 0, n - 1) * stride;
   static_assert(PI_SRC != 2, "as-stored pi~ needs face_flux_all");
+  constexpr int NQ = BK ? 12 : 10;
   // Vacuum faces: every state the kernels write has u~ = 0 where e = 0, and
   // pi~ reads as zero there (PI_SRC 0/1), so e alone decides and a vacuum face
   // skips the other loads.
@@ -324,23 +328,28 @@ __device__ __forceinline__ R face_flux_stream(const gdouble* __restrict__ e, con
   }
   if (vac) {
 #pragma unroll
-    for (int k = 0; k < 14; ++k)
+    for (int k = 0; k < 4 + NQ; ++k)
       if (k < 4 ? DO_T : DO_PI) out[k * F] = R(0);
     return (R)p.c_vac;
   }
   const R th = (R)p.theta;
-  // e and u~ face states
-  R fL[4], fR[4];
+  // e and u~ face states (and Pi's, which T~'s pressure needs)
+  constexpr int NV = BK ? 5 : 4;
+  R fL[NV], fR[NV];
   {
-    R q4[4][4];
+    R q4[NV][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) q4[0][t] = (R)ev[t];
 #pragma unroll
     for (int m = 0; m < 3; ++m)
 #pragma unroll
       for (int t = 0; t < 4; ++t) q4[1 + m][t] = (R)u[m][idx[t]];
+    if constexpr (BK) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+      for (int t = 0; t < 4; ++t) q4[4][t] = (R)ld_pi<PI_SRC>(pi, 10, idx[t], ev[t]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
       fL[v] = q4[v][1] + R(0.5) * mm_slope_r<R>(th, q4[v][0], q4[v][1], q4[v][2]);
       fR[v] = q4[v][2] - R(0.5) * mm_slope_r<R>(th, q4[v][1], q4[v][2], q4[v][3]);
     }
@@ -353,6 +362,7 @@ __device__ __forceinline__ R face_flux_stream(const gdouble* __restrict__ e, con
     ut[side] = sqrt(R(1) + ux * ux + uy * uy + ue * ue);
     R P, cs2;
     eos_p_cs2_r<R>(eos, q[0], P, cs2);
+    if constexpr (BK) P = P + q[4];  // P + Pi
     const R w = (q[0] > R(0) ? q[0] : R(0)) + P;
     const R u4[4] = {ut[side], ux, uy, ue};
     ud[side] = u4[axis];
@@ -366,9 +376,17 @@ __device__ __forceinline__ R face_flux_stream(const gdouble* __restrict__ e, con
     sp[side] = local_speed_r<R>(ut[side], ux, uy, ue, ud[side], cs2);
   }
   const R c = fmax(sp[0], sp[1]);
-  // pi~ components, one at a time
+  if constexpr (BK) {
+    if (DO_PI) {  // Pi's own flux
+      const R QL = ut[0] * fL[4], QR = ut[1] * fR[4];
+      const R FL = ud[0] * fL[4], FR = ud[1] * fR[4];
+      out[14 * F] = R(0.5) * (FL + FR) - R(0.5) * c * (QR - QL);
+    }
+  }
+  // pi~ components (and n), one at a time
 #pragma unroll
-  for (int m = 0; m < 10; ++m) {
+  for (int m = 0; m < NQ; ++m) {
+    if (m == 10) continue;  // Pi: done above
     bool inT = false;
 #pragma unroll
     for (int nu = 0; nu < 4; ++nu) inT = inT || m == sym(0, nu) || m == sym(axis, nu);
@@ -415,11 +433,12 @@ __device__ __forceinline__ R face_flux_stream(const gdouble* __restrict__ e, con
 // KT face flux H = [F(Q^r) + F(Q^l)]/2 - c (Q^r - Q^l)/2 (Sec. III, eq. flux_out)
 // at the face between cells a and a+1 along `axis` (1 = x, 2 = y, 3 = eta).
 // `base` is the flat index of the row's cell with coordinate 0 along the axis.
-// Components 0..3: T~^{d nu} part (if DO_T); 4..13: u~^d pi~ part (if DO_PI).
+// Components 0..3: T~^{d nu} part (if DO_T); 4..13: u~^d pi~ part (if DO_PI);
+// BK: 14, 15 the u~^d Pi and u~^d n parts (Pi also adds to P in T~'s part).
 // Returns the face's local speed c.  A face whose four stencil cells are exact
 // vacuum (all primitives zero) has H = 0 and c = c_vac, so it skips the arithmetic.
 // R is the arithmetic type (double, or float on the mixed-precision path).
-template <typename R, bool DO_T, bool DO_PI, int PI_SRC>
+template <typename R, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false>
 __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const gdouble* const* u,
                                        const gdouble* const* pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
@@ -433,6 +452,7 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
   // loaded first and a vacuum face skips the other loads.  As-stored pi~
   // (PI_SRC 2) can be nonzero where e = 0, so there the whole stencil is loaded
   // at once (no dependent second round of loads) and e and pi~ decide.
+  constexpr int NQ = BK ? 12 : 10, NC = 4 + NQ;
   double ev[4];
   bool vac = true;
 #pragma unroll
@@ -440,14 +460,14 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
     ev[t] = e[idx[t]];
     vac = vac && (ev[t] == 0.0);
   }
-  R q4[14][4];
+  R q4[NC][4];
   if (PI_SRC == 2) {
     // Without the pi~ flux only the components in T~'s density (tau nu) and
-    // flux (axis nu) matter: the others are neither loaded nor tested.
+    // flux (axis nu) matter (and Pi): the others are neither loaded nor tested.
 #pragma unroll
-    for (int m = 0; m < 10; ++m) {
+    for (int m = 0; m < NQ; ++m) {
       const bool used = DO_PI || m < 4 || m == sym(axis, 1) || m == sym(axis, 2) ||
-                        m == sym(axis, 3);
+                        m == sym(axis, 3) || m == 10;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const double x = used ? pi[m][idx[t]] : 0.0;
@@ -460,9 +480,10 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
 #pragma unroll
       for (int t = 0; t < 4; ++t) q4[1 + m][t] = (R)u[m][idx[t]];
   }
-  if (vac) {
+  if (vac) {  // only the components the pass uses: the LDS holds no others
 #pragma unroll
-    for (int k = 0; k < 14; ++k) out[k * F] = R(0);
+    for (int k = 0; k < NC; ++k)
+      if (k < 4 ? DO_T : DO_PI) out[k * F] = R(0);
     return (R)p.c_vac;
   }
 #pragma unroll
@@ -473,14 +494,14 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
 #pragma unroll
       for (int t = 0; t < 4; ++t) q4[1 + m][t] = (R)u[m][idx[t]];
 #pragma unroll
-    for (int m = 0; m < 10; ++m)
+    for (int m = 0; m < NQ; ++m)
 #pragma unroll
       for (int t = 0; t < 4; ++t) q4[4 + m][t] = (R)ld_pi<PI_SRC>(pi, m, idx[t], ev[t]);
   }
-  R qL[14], qR[14];
+  R qL[NC], qR[NC];
   const R th = (R)p.theta;
 #pragma unroll
-  for (int v = 0; v < 14; ++v) {
+  for (int v = 0; v < NC; ++v) {
     const R a0 = q4[v][0], a1 = q4[v][1], a2 = q4[v][2], a3 = q4[v][3];
     qL[v] = a1 + R(0.5) * mm_slope_r<R>(th, a0, a1, a2);
     qR[v] = a2 - R(0.5) * mm_slope_r<R>(th, a1, a2, a3);
@@ -496,6 +517,7 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
     ut[side] = sqrt(R(1) + ux * ux + uy * uy + ue * ue);
     R cs2;
     eos_p_cs2_r<R>(eos, q[0], P[side], cs2);
+    if constexpr (BK) P[side] = P[side] + q[14];  // P + Pi
     w[side] = (q[0] > R(0) ? q[0] : R(0)) + P[side];
     const R u4[4] = {ut[side], ux, uy, ue};
     ud[side] = u4[axis];
@@ -516,18 +538,13 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
       }
       out[nu * F] = R(0.5) * (Fx[0] + Fx[1]) - R(0.5) * c * (Q[1] - Q[0]);
     }
-  } else {
-#pragma unroll
-    for (int nu = 0; nu < 4; ++nu) out[nu * F] = R(0);
   }
 #pragma unroll
-  for (int m = 0; m < 10; ++m) {
+  for (int m = 0; m < NQ; ++m) {
     if (DO_PI) {
       const R QL = ut[0] * qL[4 + m], QR = ut[1] * qR[4 + m];
       const R FL = ud[0] * qL[4 + m], FR = ud[1] * qR[4 + m];
       out[(4 + m) * F] = R(0.5) * (FL + FR) - R(0.5) * c * (QR - QL);
-    } else {
-      out[(4 + m) * F] = R(0);
     }
   }
   return c;
@@ -536,16 +553,18 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
 // KT flux divergence of the thread's cell over all three axes (Sec. III, eq. kt):
 // R[q] = -sum_d (H_{+1/2} - H_{-1/2}) / Delta_d.  Every face of the tile is
 // computed once by one thread and staged in LDS (component-major).  Returns
-// max over the computed faces of c / Delta (for the CFL diagnostic).
-template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC>
+// max over the computed faces of c / Delta (for the CFL diagnostic).  BK: R and
+// the LDS hold 16 components (with Pi and n).
+template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false>
 __device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
                                                   const gdouble* const* u, const gdouble* const* pi,
                                                   const StepParams& p, const EosDev& eos,
-                                                  double tauf, const Pos& q, double R[14],
+                                                  double tauf, const Pos& q, double* R,
                                                   RT* lds) {
   constexpr int N = TX * TY * TZ;
+  constexpr int NQ = BK ? 12 : 10, NC = 4 + NQ;
 #pragma unroll
-  for (int k = 0; k < 14; ++k) R[k] = 0.0;
+  for (int k = 0; k < NC; ++k) R[k] = 0.0;
   double cfl = 0.0;
   const int tid = threadIdx.x;
   // Whole-tile vacuum test.  Every face stencil of the tile reads cells in the
@@ -581,7 +600,7 @@ __device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
         const int k = clampi(q.k0 - 2 + bz, 0, p.ne - 1);
         const int c = (i * p.ny + j) * p.ne + k;
 #pragma unroll
-        for (int m = 0; m < 10; ++m) nz |= pi[m][c] != 0.0;
+        for (int m = 0; m < NQ; ++m) nz |= pi[m][c] != 0.0;
       }
       any = __syncthreads_or(nz);
     }
@@ -622,15 +641,15 @@ __device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
         // stage 2 (as-stored pi~): all loads at once with the per-face e/pi~ test
         RT c;
         if constexpr (PI_SRC == 2)
-          c = face_flux_all<RT, DO_T, DO_PI, PI_SRC>(e, u, pi, base, ga - 1, nd, stride, d + 1,
-                                                     (RT)tauf, p, eos, lds + f, F);
+          c = face_flux_all<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride, d + 1,
+                                                         (RT)tauf, p, eos, lds + f, F);
         else
-          c = face_flux_stream<RT, DO_T, DO_PI, PI_SRC>(e, u, pi, base, ga - 1, nd, stride, d + 1,
-                                                        (RT)tauf, p, eos, lds + f, F);
+          c = face_flux_stream<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride,
+                                                            d + 1, (RT)tauf, p, eos, lds + f, F);
         cfl = fmax(cfl, (double)c * inv_del);
       } else {
 #pragma unroll
-        for (int k = 0; k < 14; ++k)
+        for (int k = 0; k < NC; ++k)
           if (k < 4 ? DO_T : DO_PI) lds[k * F + f] = RT(0);
       }
     }
@@ -649,7 +668,7 @@ __device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
       }
       const RT rinv = (RT)inv_del;
 #pragma unroll
-      for (int k = 0; k < 14; ++k)  // only the components this pass evaluates
+      for (int k = 0; k < NC; ++k)  // only the components this pass evaluates
         if (k < 4 ? DO_T : DO_PI) R[k] -= (double)((lds[k * F + fp] - lds[k * F + fm]) * rinv);
     }
     __syncthreads();
@@ -658,22 +677,25 @@ __device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
   return cfl;
 }
 
-template <int TX, int TY, int TZ>
+// LDS elements of the face fluxes: NC components of the largest face set.
+template <int TX, int TY, int TZ, int NC = 14>
 constexpr int lds_doubles() {
   constexpr int N = TX * TY * TZ;
   constexpr int fx = (TX + 1) * (N / TX), fy = (TY + 1) * (N / TY), fz = (TZ + 1) * (N / TZ);
   constexpr int m = fx > fy ? (fx > fz ? fx : fz) : (fy > fz ? fy : fz);
-  return 14 * m;
+  return NC * m;
 }
 
 // Waves per SIMD asked of the stage-2 passes: 3 where the tile's LDS leaves
 // room for three workgroups per CU (160 KB), else no bound.  Capping their
 // registers for a third wave is a net gain (stage2_pi 10-16%, stage2_T 1-5% on
 // the 201x201x105 grids, with a few spilled registers); stage1 loses from the
-// same cap, so it has none, nor has the lambda_1 variant of stage2_pi.
-template <typename RT, int TX, int TY, int TZ, bool L1>
+// same cap, so it has none, nor have the lambda_1 and bulk variants of stage2_pi
+// (the bulk one spills 96 bytes a lane under the cap: 1.06 ms against 0.75 ms
+// without it; its stage2_T keeps the cap, 0.67 ms against 0.79 ms).
+template <typename RT, int TX, int TY, int TZ, bool L1, int NC = 14>
 constexpr int pi_waves() {
-  return !L1 && 163840 / (int)(lds_doubles<TX, TY, TZ>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
+  return !L1 && 163840 / (int)(lds_doubles<TX, TY, TZ, NC>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
 }
 
 // u~^tau of spatial components.
@@ -691,11 +713,15 @@ __device__ __forceinline__ double utau(double a, double b, double c) {
 // eqn. projector applied to X^{ab} = pi^{a l} g_{l l} pi^{b l}, expanded as
 // X - u w - w u + u u (u.w) - (1/3)(g - u u)(g:X - u.w) with w^b = u_a X^{ab}
 // (an identity for any symmetric X; pi's transversality is not assumed).
-template <typename R, bool L1>
+// BK adds the sources of Pi and n (eqns. Pitilde, Ntilde):
+// S_Pi = -(Pi + zeta theta)/tau_Pi - Pi theta/3 - Pi u~^tau/tau (zeta / tau_Pi =
+// (e + P)/c for tau_Pi = c (zeta/s) hbarc / T), S_n = -n u~^tau/tau; pc_d and
+// S_d then hold 12 components.
+template <typename R, bool L1, bool BK = false>
 __device__ __forceinline__ void pi_source(const gdouble* const* u, const gdouble* const* uE,
                                           const gdouble* const* uL, const StepParams& p,
                                           const EosDev& eos, const Geo& g, const Pos& q,
-                                          double ec_d, const double pc_d[10], double S_d[10]) {
+                                          double ec_d, const double* pc_d, double* S_d) {
   const R ec = (R)ec_d;
   R pc[10];
 #pragma unroll
@@ -775,6 +801,18 @@ __device__ __forceinline__ void pi_source(const gdouble* const* u, const gdouble
       S_d[m] = (double)s;
     }
   }
+  if constexpr (BK) {
+    const R Pi = (R)pc_d[10], nb = (R)pc_d[11];
+    R sPi = -Pi * (T * (R)p.inv_taubulk_coef) - (R)p.zeta_taubulk * (ec + P) * theta -
+            Pi * theta * third;
+    R sn = R(0);
+    if (!cart) {
+      sPi -= Pi * uc[0] * inv_tau;
+      sn = -(nb * uc[0] * inv_tau);
+    }
+    S_d[10] = p.bulk ? (double)sPi : 0.0;
+    S_d[11] = p.baryon ? (double)sn : 0.0;
+  }
   if constexpr (L1) {
     R X[10];
 #pragma unroll
@@ -805,17 +843,21 @@ __device__ __forceinline__ void pi_source(const gdouble* const* u, const gdouble
 }
 
 // Scale pi~ so that sqrt(|pi~:pi~|) <= pi_reg (e+P); zero it where e+P = 0.
+// BK: Pi is clipped to [-P, P] and Pi, n are zero where e+P = 0 too.
+template <bool BK = false>
 __device__ __forceinline__ void regulate(const EosDev& eos, const StepParams& p, double e,
-                                         double pv[10]) {
+                                         double* pv) {
   if (!(p.pi_reg > 0.0)) return;
+  constexpr int NQ = BK ? 12 : 10;
   double P, c;
   eos_p_cs2(eos, e, P, c);
   const double w = (e > 0.0 ? e : 0.0) + P;
   if (!(w > 0.0)) {
 #pragma unroll
-    for (int m = 0; m < 10; ++m) pv[m] = 0.0;
+    for (int m = 0; m < NQ; ++m) pv[m] = 0.0;
     return;
   }
+  if constexpr (BK) pv[10] = fmin(fmax(pv[10], -P), P);
   // g~ g~ pi pi: diagonal tt/xx/yy/ee once, off-diagonals twice with sign g_mu g_nu
   const double pp = pv[0] * pv[0] + pv[4] * pv[4] + pv[7] * pv[7] + pv[9] * pv[9] -
                     2.0 * (pv[1] * pv[1] + pv[2] * pv[2] + pv[3] * pv[3]) +
@@ -943,11 +985,13 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(const EventDesc* __re
   f.up[2][c] = 2.0 * u3 - s.u3;
 }
 
-// Stage 1 at tau_n (predictor) for the ideal (VISC = false) or viscous path.
-template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool L1>
+// Stage 1 at tau_n (predictor) for the ideal (VISC = false) or viscous path;
+// BK (viscous only): also Pi and n, with P + Pi in T~ and in the root solve.
+template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool L1, bool BK = false>
 __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__ evs,
                                                     GroupTable gt) {
-  __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
+  constexpr int NQ = BK ? 12 : 10;
+  __shared__ RT lds[lds_doubles<TX, TY, TZ, 4 + NQ>()];
   const Ctx cx = load_ctx(evs, gt, 0);
   const DFields& f = cx.f;
   const StepParams& p = cx.p;
@@ -963,46 +1007,48 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
     block_partials(v, f.partial, cx.tg.ntiles, cx.tile);
     return;
   }
-  double R[14];
-  const double cfl =
-      tile_divergence<RT, TX, TY, TZ, true, VISC, VISC ? 1 : 0>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
+  double R[4 + NQ];
+  const double cfl = tile_divergence<RT, TX, TY, TZ, true, VISC, VISC ? 1 : 0, BK>(
+      f.e, f.u, f.pi, p, eos, tf, q, R, lds);
   v[P_CFL] = cfl * p.h;
-  double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0;
+  double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0, Pi1 = 0.0;
   if (q.active) {
     const int c = q.c;
     const double e = f.e[c], u1 = f.u[0][c], u2 = f.u[1][c], u3 = f.u[2][c];
     const double ut = utau(u1, u2, u3);
-    double pc[10];
+    double pc[NQ];
 #pragma unroll
-    for (int m = 0; m < 10; ++m) pc[m] = VISC ? (e == 0.0 ? 0.0 : f.pi[m][c]) : 0.0;
+    for (int m = 0; m < NQ; ++m) pc[m] = VISC ? (e == 0.0 ? 0.0 : f.pi[m][c]) : 0.0;
     if (!g.cart) {  // geometric source S_T = (-Tc^{ee}, 0, 0, -Tc^{te})
       double P, cs2;
       eos_p_cs2(eos, e, P, cs2);
+      if constexpr (BK) P += pc[10];
       const double w = (e > 0.0 ? e : 0.0) + P;
       const double see = -(w * u3 * u3 + P + pc[9]);
       R[0] += see;
       R[3] += -(w * ut * u3 + pc[3]);
       v[P_GEO] = see;
     }
-    double p1[10];
+    double p1[NQ];
     if (VISC) {
       if (e >= p.eps_cut) {
-        double S[10];
-        pi_source<RT, L1>(f.u, f.up, f.u, p, eos, g, q, e, pc, S);
+        double S[NQ];
+        pi_source<RT, L1, BK>(f.u, f.up, f.u, p, eos, g, q, e, pc, S);
 #pragma unroll
-        for (int m = 0; m < 10; ++m) R[4 + m] += S[m];
+        for (int m = 0; m < NQ; ++m) R[4 + m] += S[m];
       }
       const double s1 = 2.0 * u1 - f.up[0][c], s2 = 2.0 * u2 - f.up[1][c],
                    s3 = 2.0 * u3 - f.up[2][c];
       const double inv_uts = 1.0 / utau(s1, s2, s3);
 #pragma unroll
-      for (int m = 0; m < 10; ++m) p1[m] = (ut * pc[m] + p.h * R[4 + m]) * inv_uts;
-      regulate(eos, p, e, p1);
+      for (int m = 0; m < NQ; ++m) p1[m] = (ut * pc[m] + p.h * R[4 + m]) * inv_uts;
+      regulate<BK>(eos, p, e, p1);
 #pragma unroll
-      for (int m = 0; m < 10; ++m) st_cell(f.pi1[m] + c, p1[m]);
+      for (int m = 0; m < NQ; ++m) st_cell(f.pi1[m] + c, p1[m]);
+      if constexpr (BK) Pi1 = p1[10];
     } else {
 #pragma unroll
-      for (int m = 0; m < 10; ++m) p1[m] = 0.0;
+      for (int m = 0; m < NQ; ++m) p1[m] = 0.0;
     }
     double T1[4];
 #pragma unroll
@@ -1019,7 +1065,7 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
   if (q.active) {
     const int c = q.c;
     int it, fl;
-    const Prim s = con2prim(eos, p, K[0], K[1], K[2], K[3], x0, it, fl);
+    const Prim s = con2prim<BK>(eos, p, K[0], K[1], K[2], K[3], x0, it, fl, Pi1);
     count_solve(v, it, fl);
     st_cell(f.e1 + c, s.e);
     st_cell(f.u1[0] + c, s.u1);
@@ -1030,11 +1076,13 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
 }
 
 // Stage 2, part 1 (tau_{n+1}): pi^{n+1} = [ (u^n pi^n + u* pi')/2 + h/2 R_pi(e', u', pi') ] / u'^tau.
-template <typename RT, int TX, int TY, int TZ, bool L1>
+// BK: Pi^{n+1} and n^{n+1} the same way.
+template <typename RT, int TX, int TY, int TZ, bool L1, bool BK = false>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, L1>()))) void k_stage2_pi(
+__attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, L1 || BK, BK ? 16 : 14>()))) void k_stage2_pi(
     const EventDesc* __restrict__ evs, GroupTable gt) {
-  __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
+  constexpr int NQ = BK ? 12 : 10;
+  __shared__ RT lds[lds_doubles<TX, TY, TZ, 4 + NQ>()];
   const Ctx cx = load_ctx(evs, gt, 1);
   const DFields& f = cx.f;
   const StepParams& p = cx.p;
@@ -1043,38 +1091,38 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, L1>()))) void k_stag
   const Pos q = cell_pos<TX, TY, TZ>(p, cx.tg, cx.tile);
   if (tile_asleep<TX, TY, TZ>(p, cx.tg, cx.qcur, cx.tile)) return;
   const double tf = g.cart ? 1.0 : g.tau;
-  double R[14];
-  tile_divergence<RT, TX, TY, TZ, false, true, 2>(f.e1, f.u1, f.pi1, p, eos, tf, q, R, lds);
+  double R[4 + NQ];
+  tile_divergence<RT, TX, TY, TZ, false, true, 2, BK>(f.e1, f.u1, f.pi1, p, eos, tf, q, R, lds);
   bool quiet = true;  // this cell's part of the quiet-tile test
   if (q.active) {
     const int c = q.c;
     const double e1 = f.e1[c];
-    double pc[10];
+    double pc[NQ];
 #pragma unroll
-    for (int m = 0; m < 10; ++m) pc[m] = f.pi1[m][c];
+    for (int m = 0; m < NQ; ++m) pc[m] = f.pi1[m][c];
     if (e1 >= p.eps_cut) {
-      double S[10];
-      pi_source<RT, L1>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
+      double S[NQ];
+      pi_source<RT, L1, BK>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
 #pragma unroll
-      for (int m = 0; m < 10; ++m) R[4 + m] += S[m];
+      for (int m = 0; m < NQ; ++m) R[4 + m] += S[m];
     }
     const double en = f.e[c];
     const double a1 = f.u[0][c], a2 = f.u[1][c], a3 = f.u[2][c];
     const double utn = utau(a1, a2, a3);
     const double uts = utau(2.0 * a1 - f.up[0][c], 2.0 * a2 - f.up[1][c], 2.0 * a3 - f.up[2][c]);
     const double inv_ut1 = 1.0 / utau(f.u1[0][c], f.u1[1][c], f.u1[2][c]);
-    double pn[10];
+    double pn[NQ];
 #pragma unroll
-    for (int m = 0; m < 10; ++m) {
+    for (int m = 0; m < NQ; ++m) {
       const double pin = en == 0.0 ? 0.0 : f.pi[m][c];
       pn[m] = (0.5 * (utn * pin + uts * pc[m]) + 0.5 * p.h * R[4 + m]) * inv_ut1;
     }
-    regulate(eos, p, e1, pn);
+    regulate<BK>(eos, p, e1, pn);
 #pragma unroll
-    for (int m = 0; m < 10; ++m) st_cell(f.pi[m] + c, pn[m]);
+    for (int m = 0; m < NQ; ++m) st_cell(f.pi[m] + c, pn[m]);
     quiet = en == 0.0 && e1 == 0.0;
 #pragma unroll
-    for (int m = 0; m < 10; ++m) quiet = quiet && pc[m] == 0.0 && pn[m] == 0.0;
+    for (int m = 0; m < NQ; ++m) quiet = quiet && pc[m] == 0.0 && pn[m] == 0.0;
   }
   if (p.quiet_r[0] > 0) {
     const int all = __syncthreads_and(quiet);
@@ -1084,7 +1132,8 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, L1>()))) void k_stag
 
 // Stage 2, part 2 (tau_{n+1}): T^{n+1} = T^n + [(T' - T^n) + h R_T(e', u', pi^{n+1})]/2,
 // root solve -> (e, u~)^{n+1} (written over e^n and u~^{n-1}), diagnostics.
-template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET>
+// BK: P + Pi^{n+1} in T~ and in the root solve.
+template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool BK = false>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, false>()))) void k_stage2_T(const EventDesc* __restrict__ evs,
                                                      GroupTable gt) {
@@ -1110,20 +1159,23 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, false>()))) void k_s
     if (threadIdx.x == 0) cx.qnext[cx.tile] = 1;
     return;
   }
-  double R[14];
-  const double cfl = tile_divergence<RT, TX, TY, TZ, true, false, VISC ? 2 : 0>(f.e1, f.u1, f.pi, p,
-                                                                          eos, tf, q, R, lds);
+  constexpr int NT = BK ? 11 : 10;  // the components T~ uses: pi~ (and Pi)
+  double R[BK ? 16 : 14];
+  const double cfl = tile_divergence<RT, TX, TY, TZ, true, false, VISC ? 2 : 0, BK>(
+      f.e1, f.u1, f.pi, p, eos, tf, q, R, lds);
   v[P_CFL] = cfl * p.h;
-  double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0;
+  double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0, PiN = 0.0;
   if (q.active) {
     const int c = q.c;
     const double e1 = f.e1[c], u1 = f.u1[0][c], u2 = f.u1[1][c], u3 = f.u1[2][c];
-    double pc[10];
+    double pc[NT];
 #pragma unroll
-    for (int m = 0; m < 10; ++m) pc[m] = VISC ? f.pi[m][c] : 0.0;
+    for (int m = 0; m < NT; ++m) pc[m] = VISC ? f.pi[m][c] : 0.0;
+    if constexpr (BK) PiN = pc[10];
     if (!g.cart) {
       double P, cs2;
       eos_p_cs2(eos, e1, P, cs2);
+      if constexpr (BK) P += PiN;
       const double w = (e1 > 0.0 ? e1 : 0.0) + P;
       const double ut = utau(u1, u2, u3);
       const double see = -(w * u3 * u3 + P + pc[9]);
@@ -1149,7 +1201,7 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, false>()))) void k_s
   if (q.active) {
     const int c = q.c;
     int it, fl;
-    const Prim s = con2prim(eos, p, K[0], K[1], K[2], K[3], x0, it, fl);
+    const Prim s = con2prim<BK>(eos, p, K[0], K[1], K[2], K[3], x0, it, fl, PiN);
     count_solve(v, it, fl);
     if (p.quiet_r[0] > 0)  // e before and after stage 1 (viscous: tested in stage2pi)
       quiet = VISC || (f.e[c] == 0.0 && prev == 0.0);
@@ -1185,10 +1237,12 @@ constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 // defined in its own object (ktmi_stencil.hip built per pass and type).  `net`
 // selects the instances whose root solves take the network's guess.  The
 // passes that evaluate S_pi come twice: without and with the lambda_1 term
-// (a compile-time choice, so the first-order kernels keep their registers).
+// (a compile-time choice, so the first-order kernels keep their registers), and
+// the three viscous passes come once more with bulk pressure and baryon density.
 enum Pass : int {
   PASS_FIRST = 0, PASS_STAGE1_V, PASS_STAGE1_I, PASS_STAGE2_PI, PASS_STAGE2_T_V, PASS_STAGE2_T_I,
-  PASS_STAGE1_V_L1, PASS_STAGE2_PI_L1, PASS_COUNT
+  PASS_STAGE1_V_L1, PASS_STAGE2_PI_L1, PASS_STAGE1_BK, PASS_STAGE2_PI_BK, PASS_STAGE2_T_BK,
+  PASS_COUNT
 };
 typedef void (*PassLauncher)(hipStream_t s, int tile, bool net, const EventDesc* evs,
                              const GroupTable& gt);
@@ -1203,6 +1257,9 @@ KTMI_DECLARE_PASS(4)
 KTMI_DECLARE_PASS(5)
 KTMI_DECLARE_PASS(6)
 KTMI_DECLARE_PASS(7)
+KTMI_DECLARE_PASS(8)
+KTMI_DECLARE_PASS(9)
+KTMI_DECLARE_PASS(10)
 #undef KTMI_DECLARE_PASS
 
 }  // namespace ktmi

@@ -1,10 +1,11 @@
 // ktmi_stencil.hip -- instances of one stencil pass of the RK2 step for one
 // arithmetic type, and the launcher the host code calls for them.  The build
-// compiles this file once per (pass, type) with -DKTMI_PASS=<0..7>
+// compiles this file once per (pass, type) with -DKTMI_PASS=<0..10>
 // -DKTMI_RT=<double|float> -DKTMI_LAUNCH_FN=launch_pass<P>_<f64|f32>, so the
 // instances compile in parallel.  Passes: 0 first-step estimate, 1 / 2 stage 1
 // (viscous / ideal), 3 stage 2 pi, 4 / 5 stage 2 T (viscous / ideal), 6 / 7
-// stage 1 viscous / stage 2 pi with the second-order lambda_1 term.
+// stage 1 viscous / stage 2 pi with the second-order lambda_1 term, 8 / 9 / 10
+// stage 1 / stage 2 pi / stage 2 T with bulk pressure and baryon density.
 #include "ktmi_kernels.hpp"
 
 #if !defined(KTMI_PASS) || !defined(KTMI_RT) || !defined(KTMI_LAUNCH_FN)
@@ -32,13 +33,19 @@ void launch_tile(dim3 g, dim3 b, hipStream_t s, const EventDesc* evs, const Grou
   hipLaunchKernelGGL((k_stage1<KTMI_RT, X, Y, Z, true, N, true>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 7
   hipLaunchKernelGGL((k_stage2_pi<KTMI_RT, X, Y, Z, true>), g, b, 0, s, evs, gt);
+#elif KTMI_PASS == 8
+  hipLaunchKernelGGL((k_stage1<KTMI_RT, X, Y, Z, true, false, false, true>), g, b, 0, s, evs, gt);
+#elif KTMI_PASS == 9
+  hipLaunchKernelGGL((k_stage2_pi<KTMI_RT, X, Y, Z, false, true>), g, b, 0, s, evs, gt);
+#elif KTMI_PASS == 10
+  hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, true, false, true>), g, b, 0, s, evs, gt);
 #else
 #error "KTMI_PASS out of range"
 #endif
 }
 
-// passes without a root solve have no network instances
-constexpr bool kHasNet = KTMI_PASS != 0 && KTMI_PASS != 3 && KTMI_PASS != 7;
+// passes without a root solve, and the bulk passes, have no network instances
+constexpr bool kHasNet = KTMI_PASS != 0 && KTMI_PASS != 3 && KTMI_PASS < 7;
 
 }  // namespace
 

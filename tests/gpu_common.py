@@ -12,6 +12,8 @@ GROUPS = {
     "pi": [f"pi{m}" for m in range(10)],
     "T": [f"T{m}" for m in range(4)],
     "uprev": ["uprev_x", "uprev_y", "uprev_e"],
+    "Pi": ["Pi"],
+    "nb": ["nb"],
 }
 
 
@@ -23,7 +25,9 @@ def oracle_params(p: dict, **kw) -> O.Params:
                     cartesian=bool(q["cartesian"]), **{k: q[k] for k in
                                                       ("eps_cut", "theta", "newton_tol",
                                                        "newton_maxit", "pi_reg", "taupi_coef",
-                                                       "lambda1_hat") if k in q})
+                                                       "lambda1_hat", "zetas", "taubulk_coef")
+                                                      if k in q},
+                    baryon=bool(q.get("baryon", 0)))
 
 
 def run_oracle(wl, steps, threads=None, **kw):

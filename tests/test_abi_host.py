@@ -49,13 +49,23 @@ def test_defaults_follow_the_paper():
     assert d.eps_cut == 1e-7  # energy-density cutoff of Sec. V.A
     assert d.newton_tol == 1e-12 and d.precision == K.KTMI_FP64
     assert d.taupi_coef == 5.0 and d.lambda1_hat == 0.0  # tau_pi = 5 eta/(sT), Sec. II
+    assert d.zetas == 0.0 and d.baryon == 0  # no bulk pressure, no baryon density (Sec. III)
+    assert d.taubulk_coef == 5.0
 
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ne=-1), dict(dx=0.0), dict(h=-0.01),
                                  dict(tau0=0.0), dict(viscous=1, etas=0.0), dict(theta=2.5),
                                  dict(newton_maxit=0), dict(precision=7), dict(guess=9),
                                  dict(viscous=1, etas=0.1, taupi_coef=0.0),
-                                 dict(lambda1_hat=float("nan")), dict(lambda1_hat=float("inf"))])
+                                 dict(lambda1_hat=float("nan")), dict(lambda1_hat=float("inf")),
+                                 dict(zetas=0.05),  # bulk without viscous mode
+                                 dict(baryon=1),  # baryon density without viscous mode
+                                 dict(viscous=1, etas=0.1, zetas=-0.1),
+                                 dict(viscous=1, etas=0.1, zetas=float("nan")),
+                                 dict(viscous=1, etas=0.1, zetas=0.05, taubulk_coef=0.0),
+                                 dict(viscous=1, etas=0.1, baryon=2),
+                                 dict(viscous=1, etas=0.1, zetas=0.05, precision=1),
+                                 dict(viscous=1, etas=0.1, baryon=1, lambda1_hat=-10.0)])
 def test_invalid_descriptors_rejected(bad):
     import paper_1802_04449_amd as K
     d = _desc(**bad)
@@ -81,6 +91,14 @@ def test_workspace_size_and_state_errors():
             K.ktmi_bind(h, 256, n - 8, 0)
     finally:
         K.ktmi_destroy(h)
+
+
+def test_bulk_workspace_holds_four_more_fields():
+    import paper_1802_04449_amd as K
+    d0 = _desc(viscous=1, etas=0.1)
+    d1 = _desc(viscous=1, etas=0.1, zetas=0.05, baryon=1)
+    n = 8 * 8 * 4  # cells of _desc, padded to 32
+    assert K.ktmi_workspace_bytes(d1) - K.ktmi_workspace_bytes(d0) == 4 * ((n + 31) // 32 * 32) * 8
 
 
 def test_tile_shapes_cover_256_threads():

@@ -1,0 +1,121 @@
+"""Bulk pressure Pi and net-baryon density n (eqns. Pitilde, Ntilde) on the GPU:
+the bulk passes (stage 1, stage 2 pi, stage 2 T with 12 transported components)
+against the CPU oracle on the same seeded inputs at 1e-12, the 0+1D Bjorken
+limits, the reduction to the viscous step when both are off, and bitwise
+identical quiet-tile skipping."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from hydro_inputs import eos as E
+from hydro_inputs import ics
+from hydro_inputs import workloads as W
+
+from . import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _both(wl, steps, tol=TOL, threads=None, **kw):
+    _say(f"{wl.name} steps={steps} kw={kw}")
+    g = G.run_gpu(wl, steps, **kw)
+    gf = g.fields()
+    o = G.run_oracle(wl, steps, threads=threads, **kw)
+    of = o.fields()
+    rel = G.assert_parity(gf, of, tol, wl.name)
+    return g, o, gf, of, rel
+
+
+def test_bulk_baryon_hotspots_ragged():
+    """Hotspots with zeta/s = 0.04 and the baryon density, table EoS, ragged grid
+    (37 x 41 x 11, no dimension a multiple of the tile), 20 steps: every field,
+    Pi and n included."""
+    wl = W.hotspots_bulk(nx=37, ny=41, ne=11, dx=0.35, dy=0.35, de=0.4, steps=20, seed=6)
+    g, o, gf, of, rel = _both(wl, 20)
+    assert np.abs(of["Pi"]).max() > 0.1 and of["nb"].max() > 0.05
+    # the bulk pressure matters: the same run without it differs well above the bar
+    f0 = G.run_oracle(wl, 20, zetas=0.0).fields()
+    d = G.compare(f0, of)
+    assert d["eps"] > 1e-5, d
+
+
+def test_bulk_only_and_baryon_only():
+    """Each of the two alone (bulk without n, n without bulk), 10 steps."""
+    for kw in (dict(baryon=0), dict(zetas=0.0)):
+        wl = W.hotspots_bulk(nx=29, ny=21, ne=9, dx=0.4, dy=0.4, de=0.4, steps=10, seed=4)
+        wl.params.update(kw)
+        if kw.get("baryon") == 0:
+            wl.ic["nb"] = None
+        _both(wl, 10)
+
+
+def test_bulk_bjorken_limits():
+    """Uniform Bjorken state (3 x 4 x 5 cells, conformal EoS) with shear, bulk and n:
+    the GPU matches the oracle at 1e-12 and keeps n tau exactly (the RK2 step maps
+    n to n tau/(tau + h) here) over 100 steps."""
+    import paper_1802_04449_amd as K
+    tau0, T0, h, n = 0.6, 0.4, 0.01, 100
+    eps0 = E.C_SB * T0 ** 4
+    g = ics.Grid(3, 4, 5, 0.3, 0.3, 0.3)
+    ic = ics.bjorken(g, eps0, 0.05)
+    ic["Pi"] = np.full(g.shape, -0.2)
+    ic["nb"] = np.full(g.shape, 2.0)
+    params = dict(nx=3, ny=4, ne=5, dx=0.3, dy=0.3, de=0.3, tau0=tau0, h=h, etas=0.08,
+                  viscous=1, cartesian=0, zetas=0.04, taubulk_coef=5.0, baryon=1)
+    wl = W.Workload("bjorken_bulk_3x4x5", params, "conformal", n, ic=ic)
+    _say("bulk Bjorken")
+    g_, o, gf, of, rel = _both(wl, n)
+    ntau = gf["nb"] * (tau0 + n * h) / (2.0 * tau0)
+    assert np.max(np.abs(ntau - 1.0)) < 1e-13, float(np.max(np.abs(ntau - 1.0)))
+    assert K.Hydro  # the library was loaded
+
+
+def test_bulk_passes_reduce_to_viscous_step():
+    """The bulk passes with zeta/s = 0 and n = 0 (baryon on) give the viscous step's
+    e, u~, pi~ and T~: the extra terms are exact zeros."""
+    wl = W.hotspots_viscous(nx=33, ny=27, ne=9, dx=0.4, dy=0.4, de=0.4, steps=8, seed=5)
+    _say("bulk passes reduce to the viscous step")
+    a = G.run_gpu(wl, 8).fields()
+    b = G.run_gpu(wl, 8, baryon=1).fields()
+    worst = 0.0
+    for k in a:
+        if k in ("Pi", "nb"):
+            assert np.abs(b[k]).max() == 0.0, k
+            continue
+        scale = max(float(np.abs(a[k]).max()), 1.0)
+        worst = max(worst, float(np.abs(a[k] - b[k]).max()) / scale)
+    _say(f"max deviation {worst:.2e}")
+    assert worst <= 1e-15, worst
+
+
+def test_bulk_quiet_skip_bitwise():
+    """Quiet-tile skipping on the bulk path gives bitwise identical fields."""
+    import paper_1802_04449_amd as K
+    wl = W.hotspots_bulk(nx=61, ny=57, ne=17, dx=0.3, dy=0.3, de=0.35, steps=12, seed=8)
+    _say("bulk quiet skip")
+    out = []
+    for on in (False, True):
+        g = K.Hydro(**wl.params)
+        g.set_eos(wl.eos)
+        g.set_initial(wl.ic)
+        g.set_quiet_skip(on)
+        g.step(12)
+        out.append(g.fields())
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
+def test_bulk_full_size_201x201x105():
+    """The benchmark grid with bulk pressure and baryon density, 2 steps, compared
+    over every cell."""
+    wl = W.hotspots_bulk(steps=2)
+    threads = min(16, os.cpu_count() or 1)
+    _both(wl, 2, threads=threads)
