@@ -550,12 +550,86 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
   return c;
 }
 
+// Faces of a TX x TY x TZ tile along each axis, F_d = (T_d + 1) N / T_d, split
+// into M_d = kBlock floor(F_d / kBlock) faces evaluated in full rounds (one face
+// per thread and round) and R_d = F_d - M_d remainder faces.  The remainders of
+// the three axes are evaluated together in one round (their own LDS area), so a
+// 4x4x16 tile takes 4 rounds of face evaluations (144 remainder faces, then 256
+// per axis) instead of 6 in which every axis' second round keeps one wave busy.
+// Measured on the 201x201x105 grids this speeds up stage 1 by 5-13% and slows the
+// stage-2 passes (up to 30%: their all-loads face evaluation is long, and the
+// remainder round adds three more inlined copies of it), so it is chosen per
+// pass: SPLIT = false puts every face in full rounds (M_d = F_d, no remainder).
+template <int TX, int TY, int TZ, bool SPLIT = true>
+struct FaceLayout {
+  static constexpr int N = TX * TY * TZ;
+  static constexpr int F0 = (TX + 1) * (N / TX), F1 = (TY + 1) * (N / TY), F2 = (TZ + 1) * (N / TZ);
+  static constexpr int M0 = SPLIT ? F0 / kBlock * kBlock : F0;
+  static constexpr int M1 = SPLIT ? F1 / kBlock * kBlock : F1;
+  static constexpr int M2 = SPLIT ? F2 / kBlock * kBlock : F2;
+  static constexpr int R0 = F0 - M0, R1 = F1 - M1, R2 = F2 - M2;
+  static constexpr int RSUM = R0 + R1 + R2;
+  static constexpr int MMAX = M0 > M1 ? (M0 > M2 ? M0 : M2) : (M1 > M2 ? M1 : M2);
+  static_assert(RSUM <= kBlock, "remainder faces must fit one round");
+};
+
+// Face f of axis d (0 x, 1 y, 2 eta) of the thread's tile: its flux components go
+// to out[k * S] (zeros for a face outside the grid); returns c / Delta_d (0 outside).
+template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC, bool BK>
+__device__ __forceinline__ double eval_face(const gdouble* __restrict__ e, const gdouble* const* u,
+                                            const gdouble* const* pi, const StepParams& p,
+                                            const EosDev& eos, double tauf, const Pos& q, int d,
+                                            int f, RT* out, int S) {
+  constexpr int NC = BK ? 16 : 14;
+  const int nd = d == 0 ? p.nx : (d == 1 ? p.ny : p.ne);
+  const double inv_del = d == 0 ? p.inv_dx : (d == 1 ? p.inv_dy : p.inv_de / tauf);
+  const int stride = d == 0 ? p.ny * p.ne : (d == 1 ? p.ne : 1);
+  // face f -> (a: position along the axis in [0, Td], lx/ly/lz of the other axes);
+  // the ordering keeps eta fastest among consecutive threads where possible
+  int a, fx, fy, fz;
+  if (d == 0) {
+    a = f / (TY * TZ);
+    const int o = f % (TY * TZ);
+    fx = 0; fy = o / TZ; fz = o % TZ;
+  } else if (d == 1) {
+    fx = f / ((TY + 1) * TZ);
+    const int o = f % ((TY + 1) * TZ);
+    a = o / TZ; fy = 0; fz = o % TZ;
+  } else {
+    const int o = f / (TZ + 1);
+    a = f % (TZ + 1);
+    fx = o / TY; fy = o % TY; fz = 0;
+  }
+  const int gi = q.i0 + fx, gj = q.j0 + fy, gk = q.k0 + fz;
+  const int ga = (d == 0 ? q.i0 : (d == 1 ? q.j0 : q.k0)) + a;  // right cell of the face
+  const bool inrow = (d == 0 || gi < p.nx) && (d == 1 || gj < p.ny) && (d == 2 || gk < p.ne);
+  if (inrow && ga <= nd) {
+    const int base = d == 0 ? (gj * p.ne + gk)
+                            : (d == 1 ? (gi * p.ny) * p.ne + gk : (gi * p.ny + gj) * p.ne);
+    // stage 1 (pi~ masked by e): the streamed evaluation (fewer registers);
+    // stage 2 (as-stored pi~): all loads at once with the per-face e/pi~ test
+    RT c;
+    if constexpr (PI_SRC == 2)
+      c = face_flux_all<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride, d + 1,
+                                                     (RT)tauf, p, eos, out, S);
+    else
+      c = face_flux_stream<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride, d + 1,
+                                                        (RT)tauf, p, eos, out, S);
+    return (double)c * inv_del;
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k)
+    if (k < 4 ? DO_T : DO_PI) out[k * S] = RT(0);
+  return 0.0;
+}
+
 // KT flux divergence of the thread's cell over all three axes (Sec. III, eq. kt):
 // R[q] = -sum_d (H_{+1/2} - H_{-1/2}) / Delta_d.  Every face of the tile is
 // computed once by one thread and staged in LDS (component-major).  Returns
 // max over the computed faces of c / Delta (for the CFL diagnostic).  BK: R and
-// the LDS hold 16 components (with Pi and n).
-template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false>
+// the LDS hold 16 components (with Pi and n).  SPLIT: the face rounds of FaceLayout.
+template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false,
+          bool SPLIT = false>
 __device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
                                                   const gdouble* const* u, const gdouble* const* pi,
                                                   const StepParams& p, const EosDev& eos,
@@ -606,84 +680,142 @@ __device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
     }
     if (!any) return vacuum_cfl<RT>(p, tauf);
   }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int nd = d == 0 ? p.nx : (d == 1 ? p.ny : p.ne);
-    if (nd == 1) continue;  // both faces see identical states: zero divergence
-    const int Td = d == 0 ? TX : (d == 1 ? TY : TZ);
-    const int F = (Td + 1) * (N / Td);
-    const double inv_del = d == 0 ? p.inv_dx : (d == 1 ? p.inv_dy : p.inv_de / tauf);
-    const int stride = d == 0 ? p.ny * p.ne : (d == 1 ? p.ne : 1);
-    for (int f = tid; f < F; f += kBlock) {
-      // face f -> (a: position along the axis in [0, Td], lx/ly/lz of the other axes);
-      // the ordering keeps eta fastest among consecutive threads where possible
-      int a, fx, fy, fz;
-      if (d == 0) {
-        a = f / (TY * TZ);
-        const int o = f % (TY * TZ);
-        fx = 0; fy = o / TZ; fz = o % TZ;
-      } else if (d == 1) {
-        fx = f / ((TY + 1) * TZ);
-        const int o = f % ((TY + 1) * TZ);
-        a = o / TZ; fy = 0; fz = o % TZ;
-      } else {
-        const int o = f / (TZ + 1);
-        a = f % (TZ + 1);
-        fx = o / TY; fy = o % TY; fz = 0;
-      }
-      const int gi = q.i0 + fx, gj = q.j0 + fy, gk = q.k0 + fz;
-      const int ga = (d == 0 ? q.i0 : (d == 1 ? q.j0 : q.k0)) + a;  // right cell of the face
-      const bool inrow = (d == 0 || gi < p.nx) && (d == 1 || gj < p.ny) && (d == 2 || gk < p.ne);
-      if (inrow && ga <= nd) {
-        const int base = d == 0 ? (gj * p.ne + gk)
-                                : (d == 1 ? (gi * p.ny) * p.ne + gk : (gi * p.ny + gj) * p.ne);
-        // stage 1 (pi~ masked by e): the streamed evaluation (fewer registers);
-        // stage 2 (as-stored pi~): all loads at once with the per-face e/pi~ test
-        RT c;
-        if constexpr (PI_SRC == 2)
-          c = face_flux_all<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride, d + 1,
-                                                         (RT)tauf, p, eos, lds + f, F);
-        else
-          c = face_flux_stream<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride,
-                                                            d + 1, (RT)tauf, p, eos, lds + f, F);
-        cfl = fmax(cfl, (double)c * inv_del);
-      } else {
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-          if (k < 4 ? DO_T : DO_PI) lds[k * F + f] = RT(0);
+  if constexpr (SPLIT) {
+    using L = FaceLayout<TX, TY, TZ, SPLIT>;
+    RT* const rem = lds + NC * L::MMAX;  // remainder faces, axis after axis
+    // Remainder round: the last R_d faces of every axis, one per thread.
+    if constexpr (L::RSUM > 0) {
+      if (tid < L::R0) {
+        if (p.nx > 1)
+          cfl = fmax(cfl, eval_face<RT, TX, TY, TZ, DO_T, DO_PI, PI_SRC, BK>(
+                              e, u, pi, p, eos, tauf, q, 0, L::M0 + tid, rem + tid, L::R0));
+      } else if (tid < L::R0 + L::R1) {
+        const int t = tid - L::R0;
+        if (p.ny > 1)
+          cfl = fmax(cfl, eval_face<RT, TX, TY, TZ, DO_T, DO_PI, PI_SRC, BK>(
+                              e, u, pi, p, eos, tauf, q, 1, L::M1 + t, rem + NC * L::R0 + t, L::R1));
+      } else if (tid < L::RSUM) {
+        const int t = tid - L::R0 - L::R1;
+        if (p.ne > 1)
+          cfl = fmax(cfl, eval_face<RT, TX, TY, TZ, DO_T, DO_PI, PI_SRC, BK>(
+                              e, u, pi, p, eos, tauf, q, 2, L::M2 + t,
+                              rem + NC * (L::R0 + L::R1) + t, L::R2));
       }
     }
-    __syncthreads();
-    if (q.active) {
-      int fm, fp;
-      if (d == 0) {
-        fm = q.lx * (TY * TZ) + q.ly * TZ + q.lz;
-        fp = fm + TY * TZ;
-      } else if (d == 1) {
-        fm = q.lx * ((TY + 1) * TZ) + q.ly * TZ + q.lz;
-        fp = fm + TZ;
-      } else {
-        fm = (q.lx * TY + q.ly) * (TZ + 1) + q.lz;
-        fp = fm + 1;
+  #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int nd = d == 0 ? p.nx : (d == 1 ? p.ny : p.ne);
+      if (nd == 1) continue;  // both faces see identical states: zero divergence
+      const int M = d == 0 ? L::M0 : (d == 1 ? L::M1 : L::M2);
+      const int Rd = d == 0 ? L::R0 : (d == 1 ? L::R1 : L::R2);
+      RT* const remd = rem + NC * (d == 0 ? 0 : (d == 1 ? L::R0 : L::R0 + L::R1));
+      for (int f = tid; f < M; f += kBlock)
+        cfl = fmax(cfl, eval_face<RT, TX, TY, TZ, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, p, eos, tauf,
+                                                                             q, d, f, lds + f, M));
+      __syncthreads();
+      if (q.active) {
+        int fm, fp;
+        if (d == 0) {
+          fm = q.lx * (TY * TZ) + q.ly * TZ + q.lz;
+          fp = fm + TY * TZ;
+        } else if (d == 1) {
+          fm = q.lx * ((TY + 1) * TZ) + q.ly * TZ + q.lz;
+          fp = fm + TZ;
+        } else {
+          fm = (q.lx * TY + q.ly) * (TZ + 1) + q.lz;
+          fp = fm + 1;
+        }
+        // slot of face f: the full-round area (stride M) or the remainder area (stride R_d)
+        const bool mm = Rd == 0 || fm < M, mp = Rd == 0 || fp < M;
+        const RT* const am = mm ? lds + fm : remd + (fm - M);
+        const RT* const ap = mp ? lds + fp : remd + (fp - M);
+        const int sm = mm ? M : Rd, sp = mp ? M : Rd;
+        const RT rinv = (RT)(d == 0 ? p.inv_dx : (d == 1 ? p.inv_dy : p.inv_de / tauf));
+  #pragma unroll
+        for (int k = 0; k < NC; ++k)  // only the components this pass evaluates
+          if (k < 4 ? DO_T : DO_PI) R[k] -= (double)((ap[k * sp] - am[k * sm]) * rinv);
       }
-      const RT rinv = (RT)inv_del;
-#pragma unroll
-      for (int k = 0; k < NC; ++k)  // only the components this pass evaluates
-        if (k < 4 ? DO_T : DO_PI) R[k] -= (double)((lds[k * F + fp] - lds[k * F + fm]) * rinv);
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+  #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int nd = d == 0 ? p.nx : (d == 1 ? p.ny : p.ne);
+      if (nd == 1) continue;  // both faces see identical states: zero divergence
+      const int Td = d == 0 ? TX : (d == 1 ? TY : TZ);
+      const int F = (Td + 1) * (N / Td);
+      const double inv_del = d == 0 ? p.inv_dx : (d == 1 ? p.inv_dy : p.inv_de / tauf);
+      const int stride = d == 0 ? p.ny * p.ne : (d == 1 ? p.ne : 1);
+      for (int f = tid; f < F; f += kBlock) {
+        // face f -> (a: position along the axis in [0, Td], lx/ly/lz of the other axes);
+        // the ordering keeps eta fastest among consecutive threads where possible
+        int a, fx, fy, fz;
+        if (d == 0) {
+          a = f / (TY * TZ);
+          const int o = f % (TY * TZ);
+          fx = 0; fy = o / TZ; fz = o % TZ;
+        } else if (d == 1) {
+          fx = f / ((TY + 1) * TZ);
+          const int o = f % ((TY + 1) * TZ);
+          a = o / TZ; fy = 0; fz = o % TZ;
+        } else {
+          const int o = f / (TZ + 1);
+          a = f % (TZ + 1);
+          fx = o / TY; fy = o % TY; fz = 0;
+        }
+        const int gi = q.i0 + fx, gj = q.j0 + fy, gk = q.k0 + fz;
+        const int ga = (d == 0 ? q.i0 : (d == 1 ? q.j0 : q.k0)) + a;  // right cell of the face
+        const bool inrow = (d == 0 || gi < p.nx) && (d == 1 || gj < p.ny) && (d == 2 || gk < p.ne);
+        if (inrow && ga <= nd) {
+          const int base = d == 0 ? (gj * p.ne + gk)
+                                  : (d == 1 ? (gi * p.ny) * p.ne + gk : (gi * p.ny + gj) * p.ne);
+          // stage 1 (pi~ masked by e): the streamed evaluation (fewer registers);
+          // stage 2 (as-stored pi~): all loads at once with the per-face e/pi~ test
+          RT c;
+          if constexpr (PI_SRC == 2)
+            c = face_flux_all<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride, d + 1,
+                                                           (RT)tauf, p, eos, lds + f, F);
+          else
+            c = face_flux_stream<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride,
+                                                              d + 1, (RT)tauf, p, eos, lds + f, F);
+          cfl = fmax(cfl, (double)c * inv_del);
+        } else {
+  #pragma unroll
+          for (int k = 0; k < NC; ++k)
+            if (k < 4 ? DO_T : DO_PI) lds[k * F + f] = RT(0);
+        }
+      }
+      __syncthreads();
+      if (q.active) {
+        int fm, fp;
+        if (d == 0) {
+          fm = q.lx * (TY * TZ) + q.ly * TZ + q.lz;
+          fp = fm + TY * TZ;
+        } else if (d == 1) {
+          fm = q.lx * ((TY + 1) * TZ) + q.ly * TZ + q.lz;
+          fp = fm + TZ;
+        } else {
+          fm = (q.lx * TY + q.ly) * (TZ + 1) + q.lz;
+          fp = fm + 1;
+        }
+        const RT rinv = (RT)inv_del;
+  #pragma unroll
+        for (int k = 0; k < NC; ++k)  // only the components this pass evaluates
+          if (k < 4 ? DO_T : DO_PI) R[k] -= (double)((lds[k * F + fp] - lds[k * F + fm]) * rinv);
+      }
+      __syncthreads();
+    }
   }
   (void)N;
   return cfl;
 }
 
-// LDS elements of the face fluxes: NC components of the largest face set.
-template <int TX, int TY, int TZ, int NC = 14>
+// LDS elements of the face fluxes: NC components of the largest full-round
+// face set plus the remainders of the three axes.
+template <int TX, int TY, int TZ, int NC = 14, bool SPLIT = false>
 constexpr int lds_doubles() {
-  constexpr int N = TX * TY * TZ;
-  constexpr int fx = (TX + 1) * (N / TX), fy = (TY + 1) * (N / TY), fz = (TZ + 1) * (N / TZ);
-  constexpr int m = fx > fy ? (fx > fz ? fx : fz) : (fy > fz ? fy : fz);
-  return NC * m;
+  using L = FaceLayout<TX, TY, TZ, SPLIT>;
+  return NC * (L::MMAX + L::RSUM);
 }
 
 // Waves per SIMD asked of the stage-2 passes: 3 where the tile's LDS leaves
@@ -991,7 +1123,7 @@ template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool L1, boo
 __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__ evs,
                                                     GroupTable gt) {
   constexpr int NQ = BK ? 12 : 10;
-  __shared__ RT lds[lds_doubles<TX, TY, TZ, 4 + NQ>()];
+  __shared__ RT lds[lds_doubles<TX, TY, TZ, 4 + NQ, true>()];
   const Ctx cx = load_ctx(evs, gt, 0);
   const DFields& f = cx.f;
   const StepParams& p = cx.p;
@@ -1008,7 +1140,7 @@ __global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__
     return;
   }
   double R[4 + NQ];
-  const double cfl = tile_divergence<RT, TX, TY, TZ, true, VISC, VISC ? 1 : 0, BK>(
+  const double cfl = tile_divergence<RT, TX, TY, TZ, true, VISC, VISC ? 1 : 0, BK, true>(
       f.e, f.u, f.pi, p, eos, tf, q, R, lds);
   v[P_CFL] = cfl * p.h;
   double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0, Pi1 = 0.0;
@@ -1137,6 +1269,8 @@ template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool BK = fa
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, false>()))) void k_stage2_T(const EventDesc* __restrict__ evs,
                                                      GroupTable gt) {
+  // the unsplit face layout with DO_PI = false stores only T~'s 4 components, so
+  // the 14-component size holds them also with BK
   __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 1);
   const DFields& f = cx.f;
