@@ -8,7 +8,10 @@ stencil passes, both root solves, the diagnostics reduction) over the grid.
 Prints one JSON line.  `roofline` is measured live for the dominant kernel with
 HIP events recorded on the library's stream around every launch in the timed
 region; `cpu_baseline` times the CPU oracle on a bounded sample of the same
-workload (rank 0, N = 1 only).
+workload (rank 0, N = 1 only).  `paths` times the other paths on the same grid:
+mixed precision, quiet-tile skipping, the freeze-out surface finder, the
+Cooper-Frye spectra, the lambda_1 term, bulk pressure with baryon density, and a
+grouped batch of 64 events with the learned root-solve guess.
 """
 from __future__ import annotations
 

@@ -628,8 +628,11 @@ __device__ __forceinline__ double eval_face(const gdouble* __restrict__ e, const
 // computed once by one thread and staged in LDS (component-major).  Returns
 // max over the computed faces of c / Delta (for the CFL diagnostic).  BK: R and
 // the LDS hold 16 components (with Pi and n).  SPLIT: the face rounds of FaceLayout.
+// ALLF (T~'s components only): the faces of all three axes in one sequence of
+// rounds, F0 + F1 + F2 of them (912 for a 4x4x16 tile: 4 rounds instead of 6),
+// with one barrier; their 4 components fit lds_doubles_allf (29 KB).
 template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false,
-          bool SPLIT = false>
+          bool SPLIT = false, bool ALLF = false>
 __device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
                                                   const gdouble* const* u, const gdouble* const* pi,
                                                   const StepParams& p, const EosDev& eos,
@@ -680,7 +683,50 @@ __device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
     }
     if (!any) return vacuum_cfl<RT>(p, tauf);
   }
-  if constexpr (SPLIT) {
+  if constexpr (ALLF) {
+    static_assert(!DO_PI, "all faces at once hold T~'s components only");
+    using L = FaceLayout<TX, TY, TZ, false>;
+    constexpr int FT = L::F0 + L::F1 + L::F2;
+    // (for the 4x4x16 tile the axis is uniform over each wave in every round)
+    for (int g = tid; g < FT; g += kBlock) {
+      if (g < L::F0) {
+        if (p.nx > 1)
+          cfl = fmax(cfl, eval_face<RT, TX, TY, TZ, DO_T, DO_PI, PI_SRC, BK>(
+                              e, u, pi, p, eos, tauf, q, 0, g, lds + g, FT));
+      } else if (g < L::F0 + L::F1) {
+        if (p.ny > 1)
+          cfl = fmax(cfl, eval_face<RT, TX, TY, TZ, DO_T, DO_PI, PI_SRC, BK>(
+                              e, u, pi, p, eos, tauf, q, 1, g - L::F0, lds + g, FT));
+      } else {
+        if (p.ne > 1)
+          cfl = fmax(cfl, eval_face<RT, TX, TY, TZ, DO_T, DO_PI, PI_SRC, BK>(
+                              e, u, pi, p, eos, tauf, q, 2, g - L::F0 - L::F1, lds + g, FT));
+      }
+    }
+    __syncthreads();
+    if (q.active) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int nd = d == 0 ? p.nx : (d == 1 ? p.ny : p.ne);
+        if (nd == 1) continue;  // both faces see identical states: zero divergence
+        int fm, fp;
+        if (d == 0) {
+          fm = q.lx * (TY * TZ) + q.ly * TZ + q.lz;
+          fp = fm + TY * TZ;
+        } else if (d == 1) {
+          fm = L::F0 + q.lx * ((TY + 1) * TZ) + q.ly * TZ + q.lz;
+          fp = fm + TZ;
+        } else {
+          fm = L::F0 + L::F1 + (q.lx * TY + q.ly) * (TZ + 1) + q.lz;
+          fp = fm + 1;
+        }
+        const RT rinv = (RT)(d == 0 ? p.inv_dx : (d == 1 ? p.inv_dy : p.inv_de / tauf));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) R[k] -= (double)((lds[k * FT + fp] - lds[k * FT + fm]) * rinv);
+      }
+    }
+    __syncthreads();
+  } else if constexpr (SPLIT) {
     using L = FaceLayout<TX, TY, TZ, SPLIT>;
     RT* const rem = lds + NC * L::MMAX;  // remainder faces, axis after axis
     // Remainder round: the last R_d faces of every axis, one per thread.
@@ -816,6 +862,13 @@ template <int TX, int TY, int TZ, int NC = 14, bool SPLIT = false>
 constexpr int lds_doubles() {
   using L = FaceLayout<TX, TY, TZ, SPLIT>;
   return NC * (L::MMAX + L::RSUM);
+}
+
+// LDS elements of tile_divergence's ALLF layout: T~'s 4 components of every face.
+template <int TX, int TY, int TZ>
+constexpr int lds_doubles_allf() {
+  using L = FaceLayout<TX, TY, TZ, false>;
+  return 4 * (L::F0 + L::F1 + L::F2);
 }
 
 // Waves per SIMD asked of the stage-2 passes: 3 where the tile's LDS leaves
@@ -1269,9 +1322,7 @@ template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool BK = fa
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, false>()))) void k_stage2_T(const EventDesc* __restrict__ evs,
                                                      GroupTable gt) {
-  // the unsplit face layout with DO_PI = false stores only T~'s 4 components, so
-  // the 14-component size holds them also with BK
-  __shared__ RT lds[lds_doubles<TX, TY, TZ>()];
+  __shared__ RT lds[lds_doubles_allf<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 1);
   const DFields& f = cx.f;
   const StepParams& p = cx.p;
@@ -1295,7 +1346,7 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, false>()))) void k_s
   }
   constexpr int NT = BK ? 11 : 10;  // the components T~ uses: pi~ (and Pi)
   double R[BK ? 16 : 14];
-  const double cfl = tile_divergence<RT, TX, TY, TZ, true, false, VISC ? 2 : 0, BK>(
+  const double cfl = tile_divergence<RT, TX, TY, TZ, true, false, VISC ? 2 : 0, BK, false, true>(
       f.e1, f.u1, f.pi, p, eos, tf, q, R, lds);
   v[P_CFL] = cfl * p.h;
   double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0, PiN = 0.0;
