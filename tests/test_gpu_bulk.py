@@ -119,3 +119,38 @@ def test_bulk_full_size_201x201x105():
     wl = W.hotspots_bulk(steps=2)
     threads = min(16, os.cpu_count() or 1)
     _both(wl, 2, threads=threads)
+
+
+def test_group_with_bulk_events():
+    """A group mixing viscous events with bulk/baryon events (their own kernel
+    class) gives the single-run fields bit for bit, and the grouped bulk event
+    matches the oracle."""
+    import torch
+
+    import paper_1802_04449_amd as K
+    _say("grouped bulk events")
+    evs = [W.hotspots_bulk(nx=29, ny=29, ne=7, dx=0.45, dy=0.45, de=0.45, steps=5, seed=81),
+           W.hotspots_viscous(nx=25, ny=25, ne=5, dx=0.45, dy=0.45, de=0.45, steps=5, seed=82),
+           W.hotspots_bulk(nx=31, ny=27, ne=9, dx=0.45, dy=0.45, de=0.45, steps=5, seed=83,
+                           baryon=False)]
+
+    def make(wl, st):
+        h = K.Hydro(stream=st, **wl.params)
+        h.set_eos(wl.eos)
+        h.set_initial(wl.ic)
+        return h
+
+    st = torch.cuda.Stream()
+    solo = [make(wl, st) for wl in evs]
+    grouped = [make(wl, st) for wl in evs]
+    for h in solo:
+        h.step(5)
+    grp = K.Group(grouped)
+    assert grp.classes >= 2
+    grp.step(5)
+    for e, (x, y) in enumerate(zip(solo, grouped)):
+        fx, fy = x.fields(), y.fields()
+        for k in fx:
+            assert np.array_equal(fx[k], fy[k]), (e, k)
+    G.assert_parity(grouped[0].fields(), G.run_oracle(evs[0], 5).fields(), TOL,
+                    "grouped bulk event vs oracle")
