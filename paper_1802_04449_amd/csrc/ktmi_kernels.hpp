@@ -883,6 +883,15 @@ constexpr int pi_waves() {
   return !L1 && 163840 / (int)(lds_doubles<TX, TY, TZ, NC>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
 }
 
+// Waves per SIMD asked of stage 2T: as the other stage-2 passes, except that the
+// FP32 (mixed-precision) instance without bulk asks for 4 (128 VGPRs, 68 bytes of
+// spill a lane): 0.56 -> 0.53 ms on the 201x201x105 hotspot grid, +1.8% on the
+// grid without vacuum.  The same cap on the FP32 stage 1 or stage 2pi loses.
+template <typename RT, int TX, int TY, int TZ, bool BK>
+constexpr int s2t_waves() {
+  return sizeof(RT) == 4 && !BK ? 4 : pi_waves<RT, TX, TY, TZ, false>();
+}
+
 // u~^tau of spatial components.
 __device__ __forceinline__ double utau(double a, double b, double c) {
   return sqrt(1.0 + a * a + b * b + c * c);
@@ -1320,7 +1329,7 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, L1 || BK, BK ? 16 : 
 // BK: P + Pi^{n+1} in T~ and in the root solve.
 template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool BK = false>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, false>()))) void k_stage2_T(const EventDesc* __restrict__ evs,
+__attribute__((amdgpu_waves_per_eu(s2t_waves<RT, TX, TY, TZ, BK>()))) void k_stage2_T(const EventDesc* __restrict__ evs,
                                                      GroupTable gt) {
   __shared__ RT lds[lds_doubles_allf<TX, TY, TZ>()];
   const Ctx cx = load_ctx(evs, gt, 1);
