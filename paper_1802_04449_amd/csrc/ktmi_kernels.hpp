@@ -1181,8 +1181,9 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(const EventDesc* __re
 
 // Stage 1 at tau_n (predictor) for the ideal (VISC = false) or viscous path;
 // BK (viscous only): also Pi and n, with P + Pi in T~ and in the root solve.
+// The bulk variant (172 VGPRs uncapped: two waves per SIMD) asks for three.
 template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool L1, bool BK = false>
-__global__ __launch_bounds__(kBlock) void k_stage1(const EventDesc* __restrict__ evs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BK ? 3 : 1))) void k_stage1(const EventDesc* __restrict__ evs,
                                                     GroupTable gt) {
   constexpr int NQ = BK ? 12 : 10;
   __shared__ RT lds[lds_doubles<TX, TY, TZ, 4 + NQ, true>()];
