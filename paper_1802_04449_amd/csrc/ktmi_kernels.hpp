@@ -874,13 +874,14 @@ constexpr int lds_doubles_allf() {
 // Waves per SIMD asked of the stage-2 passes: 3 where the tile's LDS leaves
 // room for three workgroups per CU (160 KB), else no bound.  Capping their
 // registers for a third wave is a net gain (stage2_pi 10-16%, stage2_T 1-5% on
-// the 201x201x105 grids, with a few spilled registers); stage1 loses from the
-// same cap, so it has none, nor have the lambda_1 and bulk variants of stage2_pi
-// (the bulk one spills 96 bytes a lane under the cap: 1.06 ms against 0.75 ms
-// without it; its stage2_T keeps the cap, 0.67 ms against 0.79 ms).
-template <typename RT, int TX, int TY, int TZ, bool L1, int NC = 14>
+// the 201x201x105 grids, with a few spilled registers; the lambda_1 variant 8%
+// in FP64 with 60 bytes of spill, 13% in FP32); stage1 loses from the same cap,
+// so it has none, nor has the bulk variant of stage2_pi (it spills 96 bytes a
+// lane under the cap: 1.06 ms against 0.75 ms without it; its stage2_T keeps the
+// cap).  NOCAP = true asks for no bound.
+template <typename RT, int TX, int TY, int TZ, bool NOCAP, int NC = 14>
 constexpr int pi_waves() {
-  return !L1 && 163840 / (int)(lds_doubles<TX, TY, TZ, NC>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
+  return !NOCAP && 163840 / (int)(lds_doubles<TX, TY, TZ, NC>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
 }
 
 // Waves per SIMD asked of stage 2T: as the other stage-2 passes, except that the
@@ -1274,7 +1275,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BK ? 3 :
 // BK: Pi^{n+1} and n^{n+1} the same way.
 template <typename RT, int TX, int TY, int TZ, bool L1, bool BK = false>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, L1 || BK, BK ? 16 : 14>()))) void k_stage2_pi(
+__attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>()))) void k_stage2_pi(
     const EventDesc* __restrict__ evs, GroupTable gt) {
   constexpr int NQ = BK ? 12 : 10;
   __shared__ RT lds[lds_doubles<TX, TY, TZ, 4 + NQ>()];
