@@ -1182,9 +1182,13 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(const EventDesc* __re
 
 // Stage 1 at tau_n (predictor) for the ideal (VISC = false) or viscous path;
 // BK (viscous only): also Pi and n, with P + Pi in T~ and in the root solve.
-// The bulk variant (172 VGPRs uncapped: two waves per SIMD) asks for three.
+// The bulk variant (172 VGPRs uncapped: two waves per SIMD) asks for three, and so
+// do the network variants (uncapped, the matrix-core results take 32 accumulation
+// registers on top of 146 / 164 VGPRs; capped, they stay in VGPRs without spills),
+// the network variant with the lambda_1 term two (else one wave).
 template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool L1, bool BK = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BK ? 3 : 1))) void k_stage1(const EventDesc* __restrict__ evs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    BK || (NET && !L1) ? 3 : (NET ? 2 : 1)))) void k_stage1(const EventDesc* __restrict__ evs,
                                                     GroupTable gt) {
   constexpr int NQ = BK ? 12 : 10;
   __shared__ RT lds[lds_doubles<TX, TY, TZ, 4 + NQ, true>()];
