@@ -556,10 +556,12 @@ __device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const 
 // the three axes are evaluated together in one round (their own LDS area), so a
 // 4x4x16 tile takes 4 rounds of face evaluations (144 remainder faces, then 256
 // per axis) instead of 6 in which every axis' second round keeps one wave busy.
-// Measured on the 201x201x105 grids this speeds up stage 1 by 5-13% and slows the
-// stage-2 passes (up to 30%: their all-loads face evaluation is long, and the
-// remainder round adds three more inlined copies of it), so it is chosen per
-// pass: SPLIT = false puts every face in full rounds (M_d = F_d, no remainder).
+// Measured on the 201x201x105 grids this speeds up stage 1 by 5-13%; stage 2pi
+// gains on a grid without vacuum but loses up to 30% on the hotspot grid, where
+// most of its faces are vacuum faces loaded in full and rounds that mix axes cost
+// more (also with a window of x and y faces that adds no code), so the layout is
+// chosen per pass: SPLIT = false puts every face in full rounds (M_d = F_d, no
+// remainder).
 template <int TX, int TY, int TZ, bool SPLIT = true>
 struct FaceLayout {
   static constexpr int N = TX * TY * TZ;
