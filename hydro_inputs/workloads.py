@@ -98,6 +98,34 @@ def hotspots_minijets(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps=20
                     T4=ics.hotspots_with_minijets(g, 0.6, seed))
 
 
+def minijets_defects(nx=33, ny=31, ne=9, dx=0.3, dy=0.3, de=0.4, steps=4, seed=2, n_each=6,
+                     kinds=("nan", "momentum", "negative")):
+    """hotspots_minijets on a small grid with defective cells planted in T~^{tau mu}
+    (seeded positions inside the fireball, n_each of each kind in `kinds`): NaN in
+    one component ("nan"), a momentum twice the energy, |T~^{tau i}| > T~^{tau tau}
+    ("momentum"), and a negative energy T~^{tau tau} < 0 ("negative").  Input data
+    only: it exercises the root solve's guards and the diagnostics counters."""
+    wl = hotspots_minijets(nx, ny, ne, dx, dy, de, steps=steps, seed=seed)
+    T4 = wl.T4.copy()
+    rng = np.random.default_rng(seed + 31)
+    hot = np.argwhere(T4[0] > 0.5 * T4[0].max())
+    pick = hot[rng.choice(len(hot), 3 * n_each, replace=False)]
+    for n, (i, j, k) in enumerate(pick):
+        kind = n // n_each
+        if ("nan", "momentum", "negative")[kind] not in kinds:
+            continue
+        if kind == 0:
+            T4[n % 4, i, j, k] = np.nan
+        elif kind == 1:
+            T4[1 + n % 3, i, j, k] = 2.0 * T4[0, i, j, k]
+        else:
+            T4[0, i, j, k] = -0.1 * T4[0, i, j, k]
+    wl.T4 = T4
+    wl.name = f"minijets_defects_{'_'.join(kinds)}_{nx}x{ny}x{ne}"
+    wl.note = "NaN, M > E and negative-energy cells"
+    return wl
+
+
 def gubser_dense_viscous(nx=201, ny=201, ne=105, dx=0.16, dy=0.16, de=0.3, steps=200,
                          etas=0.08) -> Workload:
     """The benchmark grid and physics with a smooth ideal-Gubser profile (q = 1/fm,

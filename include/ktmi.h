@@ -97,7 +97,22 @@ typedef struct ktmi_desc {
                             S_Pi = -(Pi + zeta theta)/tau_Pi - Pi theta/3 - Pi u~^tau/tau,
                             zeta = (zeta/s)(e+P) hbarc/T, S_n = -n u~^tau/tau; Pi adds to P in
                             T^{mu nu} and in the root solve; the regulator clips Pi to [-P, P] */
+    double cfl_limit;    /* largest c h / Delta over faces and stages that raises no
+                            KTMI_ERR_CFL (default 0.5); must be > 0 */
 } ktmi_desc;
+
+/* Error bits of ktmi_diagnostics.errors, set from the counters accumulated since
+ * the initial state.  The root solve (Sec. III flow chart) takes a varying
+ * number of iterations (App. A.3) and the energy-density cutoff turns dilute
+ * cells into vacuum (Sec. V.A); these bits flag the cases that mean the run
+ * left the method's assumptions:
+ *   KTMI_ERR_NAN     a NaN reached a root solve (the cell became vacuum),
+ *   KTMI_ERR_NEG_EPS a root solve saw K^tau < 0, a negative energy density (the
+ *                    cell became vacuum),
+ *   KTMI_ERR_NONCONV a root solve stopped at newton_maxit iterations,
+ *   KTMI_ERR_CFL     a face's c h / Delta exceeded cfl_limit (the KT scheme's
+ *                    stability needs c h / Delta well below 1). */
+enum { KTMI_ERR_NAN = 1, KTMI_ERR_NEG_EPS = 2, KTMI_ERR_NONCONV = 4, KTMI_ERR_CFL = 8 };
 
 typedef struct ktmi_diagnostics {
     double tau;          /* proper time after the last step */
@@ -109,20 +124,23 @@ typedef struct ktmi_diagnostics {
     double newton_mean;  /* mean iterations per root solve (incl. the polish step) */
     long newton_max;     /* max iterations of one root solve */
     long solves, fallbacks, nonconv, nans, vacuum, clamps; /* counters */
+    long negative;       /* root solves that saw K^tau < 0 */
+    int errors;          /* KTMI_ERR_* bits */
 } ktmi_diagnostics;
 
 typedef struct ktmi_handle ktmi_handle;
 
 /* Fills d with the defaults: cutoff 1e-7, theta 1.8, tolerance 1e-12, 100
  * iterations, regulator 1.0, FP64, previous-stage guess, automatic tile,
- * taupi_coef 5, lambda1_hat 0, zetas 0, taubulk_coef 5, baryon 0.  Sizes are zero. */
+ * taupi_coef 5, lambda1_hat 0, zetas 0, taubulk_coef 5, baryon 0, cfl_limit
+ * 0.5.  Sizes are zero. */
 void ktmi_desc_default(ktmi_desc *d);
 
 /* Validates d and creates a handle (host memory only).  KTMI_EINVAL if a size
  * is < 1, a spacing, tau0 or h is not > 0, viscous with etas <= 0 or
  * taupi_coef <= 0, lambda1_hat is not finite, zetas is not finite and >= 0,
  * baryon is not 0 or 1, or bulk/baryon is asked for without viscous mode, FP64
- * and lambda1_hat = 0, or with taubulk_coef <= 0. */
+ * and lambda1_hat = 0, or with taubulk_coef <= 0, or cfl_limit is not > 0. */
 int ktmi_create(const ktmi_desc *d, ktmi_handle **out);
 
 /* Bytes of device workspace the handle needs (0 if d is invalid). */
@@ -166,8 +184,9 @@ int ktmi_set_initial_primitive_ext(ktmi_handle *h, const double *e, const double
 int ktmi_set_initial_conserved(ktmi_handle *h, const double *T4, const double *pi10);
 
 /* Enqueues n RK2 steps on the bound stream (asynchronous).  Device-side
- * failures (NaN, non-converged solves) are counted in the diagnostics, not
- * returned here. */
+ * failures (NaN, negative energy density, non-converged solves, CFL excess) are
+ * counted in the diagnostics and flagged in its error bits, not returned here
+ * (no host synchronisation). */
 int ktmi_step(ktmi_handle *h, int n);
 
 /* Copies one field (ids above) to device array dst (stream-ordered, async). */

@@ -30,7 +30,8 @@ class _Params(C.Structure):
                 ("eps_cut", C.c_double), ("theta", C.c_double), ("newton_tol", C.c_double),
                 ("newton_maxit", C.c_int), ("pi_reg", C.c_double),
                 ("taupi_coef", C.c_double), ("lambda1_hat", C.c_double),
-                ("zetas", C.c_double), ("taubulk_coef", C.c_double), ("baryon", C.c_int)]
+                ("zetas", C.c_double), ("taubulk_coef", C.c_double), ("baryon", C.c_int),
+                ("cfl_limit", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -38,20 +39,31 @@ class _Diag(C.Structure):
                 ("sum_Ttt", C.c_double), ("geo_src", C.c_double), ("max_cfl", C.c_double),
                 ("newton_mean", C.c_double), ("newton_max", C.c_long), ("solves", C.c_long),
                 ("fallbacks", C.c_long), ("nonconv", C.c_long), ("nans", C.c_long),
-                ("vacuum", C.c_long), ("clamps", C.c_long)]
+                ("vacuum", C.c_long), ("clamps", C.c_long), ("negative", C.c_long),
+                ("errors", C.c_int)]
 
+
+MUT_LIB_PATH = os.path.join(_HERE, "liboracle_mut.so")
 
 _lib = None
+_plain = None    # liboracle.so
+_mutant = None   # liboracle_mut.so, loaded by set_mutant() only
 
 
 def load():
-    global _lib
+    global _lib, _plain
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
+    _plain = _open(LIB_PATH)
+    _lib = _plain
+    return _lib
+
+
+def _open(path):
+    if not os.path.exists(path):
         from . import build as _b
         _b.build()
-    lib = C.CDLL(LIB_PATH)
+    lib = C.CDLL(path)
     P = C.POINTER(C.c_double)
     lib.orc_create.restype = C.c_void_p
     lib.orc_create.argtypes = [C.POINTER(_Params)]
@@ -71,8 +83,8 @@ def load():
                                       C.POINTER(C.c_int)]
     lib.orc_prim2K.argtypes = [C.c_void_p, C.c_int, P, P, P]
     lib.orc_local_speed.argtypes = [C.c_int, P, C.c_int, P, P]
+    lib.orc_regulate.argtypes = [C.c_void_p, C.c_double, P]
     lib.orc_shear_at.argtypes = [C.c_void_p, P, P, P, C.c_double, C.c_int, C.c_int, C.c_int, P]
-    lib.orc_set_mutant.argtypes = [C.c_int]
     lib.orc_mlp_nparam.restype = C.c_int
     lib.orc_mlp_forward.argtypes = [P, C.c_int, P, P, P]
     lib.orc_mlp_loss_grad.argtypes = [P, C.c_int, P, P, P, P, P]
@@ -86,7 +98,6 @@ def load():
                                 C.POINTER(C.c_int), P, C.c_int, P, C.c_int, P, C.c_int, P, P]
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_max_threads.restype = C.c_int
-    _lib = lib
     return lib
 
 
@@ -105,8 +116,22 @@ def set_threads(n: int):
 
 
 def set_mutant(k: int):
-    """Plant mistake k in the oracle (0 restores it); used only by the pin tests' self-check."""
-    load().orc_set_mutant(int(k))
+    """Plant mistake k (0: none).  Used only by the pins' self-check: a nonzero k
+    switches this module to the separate mutant build liboracle_mut.so, k = 0
+    switches back to liboracle.so (which has no switches).  Oracle objects keep
+    the library that was current when they were created."""
+    global _lib, _mutant
+    load()
+    if k:
+        if _mutant is None:
+            _mutant = _open(MUT_LIB_PATH)
+            _mutant.orc_set_mutant.argtypes = [C.c_int]
+        _mutant.orc_set_mutant(int(k))
+        _lib = _mutant
+    else:
+        if _mutant is not None:
+            _mutant.orc_set_mutant(0)
+        _lib = _plain
 
 
 def max_threads() -> int:
@@ -136,13 +161,14 @@ class Params:
     zetas: float = 0.0         # zeta/s of the bulk pressure (0: no bulk)
     taubulk_coef: float = 5.0  # tau_Pi = taubulk_coef (zeta/s) hbarc / T
     baryon: bool = False       # transport the net-baryon density
+    cfl_limit: float = 0.5     # c h / Delta above which the CFL error bit is raised
 
     def c(self):
         return _Params(self.nx, self.ny, self.ne, self.dx, self.dy, self.de, self.tau0, self.h,
                        self.etas, int(self.viscous), int(self.cartesian), self.eps_cut,
                        self.theta, self.newton_tol, self.newton_maxit, self.pi_reg,
                        self.taupi_coef, self.lambda1_hat, self.zetas, self.taubulk_coef,
-                       int(self.baryon))
+                       int(self.baryon), self.cfl_limit)
 
 
 class Oracle:
@@ -248,6 +274,13 @@ class Oracle:
         self.lib.orc_shear_at(self.h, *[_p(a) for a in arrs], float(tau), i, j, k, _p(out))
         return out[:10], out[10], out[11:]
 
+    def regulate(self, e, q):
+        """The shear regulator on one cell: q holds the transported components
+        (10 pi~, plus Pi and n with bulk/baryon); returns the regulated copy."""
+        q = _c(q).copy()
+        self.lib.orc_regulate(self.h, float(e), _p(q))
+        return q
+
     def prim2K(self, e, u):
         e = _c(e).reshape(-1)
         u = _c(u).reshape(-1, 3)
@@ -264,7 +297,8 @@ def local_speed(u3, axis, cs2):
     return out
 
 
-C2P_FALLBACK, C2P_NONCONV, C2P_NAN, C2P_VAC, C2P_CLAMP = 1, 2, 4, 8, 16
+C2P_FALLBACK, C2P_NONCONV, C2P_NAN, C2P_VAC, C2P_CLAMP, C2P_NEG = 1, 2, 4, 8, 16, 32
+ERR_NAN, ERR_NEG_EPS, ERR_NONCONV, ERR_CFL = 1, 2, 4, 8
 
 
 # ---- learned root-solve guess (FP64 reference) ----

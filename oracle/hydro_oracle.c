@@ -61,13 +61,14 @@
 
 #define HBARC 0.1973269804
 
-/* Planted-mistake switch for the pin tests' own check (0 = the oracle as
- * written).  A nonzero value deliberately breaks one term, so the tests can
- * show that some pin notices; it is never set outside that test. */
+/* Planted-mistake switch of the pins' self-check: only in the separate
+ * -DORC_MUTANTS build (oracle_mut.h); a nonzero value breaks one term. */
+#include "oracle_mut.h"
+#ifdef ORC_MUTANTS
 static int orc_mutant = 0;
-#define MUT(k) (orc_mutant == (k))
 void orc_set_mutant(int k) { orc_mutant = k; }
 int orc_get_mutant(void) { return orc_mutant; }
+#endif
 #define NG 2 /* ghost layers per face: the KT stencil reaches i-2 .. i+2 */
 #define NQ 12 /* transported components: 10 pi~, Pi, n */
 #define QB 10 /* index of Pi */
@@ -88,6 +89,7 @@ typedef struct orc_params {
     double zetas;        /* zeta / s of the bulk pressure Pi; 0: Pi stays 0 */
     double taubulk_coef; /* tau_Pi = taubulk_coef (zeta/s) hbarc / T */
     int baryon;          /* 1: transport the net-baryon density n */
+    double cfl_limit;    /* max c h / Delta above which the CFL error bit is raised */
 } orc_params;
 
 typedef struct orc_diag {
@@ -100,7 +102,14 @@ typedef struct orc_diag {
     double newton_mean;  /* mean iterations per root solve (incl. polish)      */
     long newton_max;
     long solves, fallbacks, nonconv, nans, vacuum, clamps;
+    long negative; /* root solves whose K^tau was negative (set to vacuum)   */
+    int errors;    /* ORC_ERR_* bits of the run so far                        */
 } orc_diag;
+
+/* Error bits of the diagnostics: a NaN reached a root solve, a negative energy
+ * density K^tau reached one, a solve hit the iteration cap, a face's c h / Delta
+ * exceeded cfl_limit. */
+enum { ORC_ERR_NAN = 1, ORC_ERR_NEG_EPS = 2, ORC_ERR_NONCONV = 4, ORC_ERR_CFL = 8 };
 
 typedef struct orc_eos {
     int kind; /* 0 conformal (P = e/3), 1 uniform table */
@@ -131,7 +140,7 @@ typedef struct orc {
     long sum_iters;
 } orc;
 
-enum { C2P_FALLBACK = 1, C2P_NONCONV = 2, C2P_NAN = 4, C2P_VAC = 8, C2P_CLAMP = 16 };
+enum { C2P_FALLBACK = 1, C2P_NONCONV = 2, C2P_NAN = 4, C2P_VAC = 8, C2P_CLAMP = 16, C2P_NEG = 32 };
 
 /* Index of padded cell (i, j, k) with i in [-NG, nx+NG). */
 static inline long IDX(const orc *S, int i, int j, int k) {
@@ -211,7 +220,7 @@ static void con2prim(const orc *S, const double Kin[4], double Pi, double guess,
         return;
     }
     if (!(E >= S->p.eps_cut)) { /* energy-density cutoff, Sec. V.A */
-        *flags |= C2P_VAC;
+        *flags |= C2P_VAC | (E < 0.0 ? C2P_NEG : 0);
         *e_out = 0.0;
         u_out[0] = u_out[1] = u_out[2] = 0.0;
         return;
@@ -689,14 +698,21 @@ static void regulate_pi(const orc *S, double e, double pi10[NQ]) {
     for (int mu = 0; mu < 4; ++mu)
         for (int nu = 0; nu < 4; ++nu) {
             double v = pi10[SYM(mu, nu)];
-            pp += GT[mu] * GT[nu] * v * v;
+            double g2 = GT[mu] * GT[nu];
+            if (MUT(35) && (mu == 0) != (nu == 0)) g2 = -g2;            /* tau-i sign */
+            if (MUT(36) && mu != nu && mu > 0 && nu > 0) g2 = -g2;     /* i-j sign */
+            pp += g2 * v * v;
         }
-    double rho = sqrt(fabs(pp)) / w;
+    double rho = (MUT(37) ? sqrt(pp) : sqrt(fabs(pp))) / w;
     if (rho > S->p.pi_reg) {
         double f = S->p.pi_reg / rho;
-        for (int m = 0; m < 10; ++m) pi10[m] *= f;
+        for (int m = 0; m < (MUT(38) ? S->nq : 10); ++m) pi10[m] *= f;
     }
 }
+
+/* Test hook: the regulator on one cell's transported components q (S's nq of
+ * them), in place, with the cell's energy density e. */
+void orc_regulate(const orc *S, double e, double *q) { regulate_pi(S, e, q); }
 
 /* Full right-hand side: R_T = S_KT + S_T (if doT), R_pi = S_KT + S_pi (if doPi).
  * Ghosts of every field read must be filled by the caller. */
@@ -749,6 +765,7 @@ static void cells_con2prim(orc *S, double *const T[4], double *const piq[NQ], do
     for (long c = 0; c < S->ncell; ++c) {
         int fl = S->flag_cell[c];
         if (fl & C2P_NAN) S->d.nans++;
+        if (fl & C2P_NEG) S->d.negative++;
         if (it_cell_zero(S->it_cell[c])) continue; /* decided before iterating */
         S->d.solves++;
         S->sum_iters += S->it_cell[c];
@@ -804,6 +821,7 @@ orc *orc_create(const orc_params *p) {
     const int ext = p->zetas > 0.0 || p->baryon;
     if (ext && !p->viscous) return NULL; /* Pi and n ride on the viscous step */
     if (p->zetas > 0.0 && !(p->taubulk_coef > 0.0)) return NULL;
+    if (!(p->cfl_limit > 0.0)) return NULL;
     orc *S = (orc *)calloc(1, sizeof(orc));
     S->p = *p;
     S->nq = ext ? NQ : 10;
@@ -928,7 +946,7 @@ static void first_step_estimate(orc *S) {
             }
     long solves = S->d.solves, it = S->sum_iters; /* do not count these solves */
     long nmax = S->d.newton_max, fb = S->d.fallbacks, nc = S->d.nonconv, na = S->d.nans,
-         cl = S->d.clamps;
+         cl = S->d.clamps, ng = S->d.negative;
     cells_con2prim(S, S->T1, NULL, tau1, S->e, S->e1, S->u1);
     S->d.solves = solves;
     S->sum_iters = it;
@@ -937,6 +955,7 @@ static void first_step_estimate(orc *S) {
     S->d.nonconv = nc;
     S->d.nans = na;
     S->d.clamps = cl;
+    S->d.negative = ng;
     for (int i = 0; i < nx; ++i)
         for (int j = 0; j < ny; ++j)
             for (int k = 0; k < ne; ++k) {
@@ -1079,7 +1098,7 @@ static void one_step(orc *S) {
                     for (int m = 0; m < nq; ++m)
                         pn[m] = (0.5 * (utn * S->pi[m][id] + uts * S->pi1[m][id]) +
                                  0.5 * h * S->Rpi2[m][id]) / ut1;
-                    if (S->p.pi_reg > 0.0) regulate_pi(S, S->e1[id], pn);
+                    if (S->p.pi_reg > 0.0) regulate_pi(S, MUT(34) ? S->e[id] : S->e1[id], pn);
                     for (int m = 0; m < nq; ++m) S->piN[m][id] = pn[m];
                 }
         for (int m = 0; m < nq; ++m) fill_ghosts(S, S->piN[m]);
@@ -1117,6 +1136,12 @@ static void one_step(orc *S) {
                 if (S->e[id] == 0.0) {
                     vac++;
                     for (int m = 0; m < nq; ++m) S->pi[m][id] = 0.0;
+                } else if (MUT(33) && visc && S->p.pi_reg > 0.0) {
+                    /* mistake: a third regulation after the root solve, with e^{n+1} */
+                    double pn[NQ];
+                    for (int m = 0; m < nq; ++m) pn[m] = S->pi[m][id];
+                    regulate_pi(S, S->e[id], pn);
+                    for (int m = 0; m < nq; ++m) S->pi[m][id] = pn[m];
                 }
                 if (S->e[id] > emax) emax = S->e[id];
                 sumT += S->T[0][id];
@@ -1170,6 +1195,9 @@ int orc_read(const orc *S, int field, double *dst) {
 
 int orc_diag_get(const orc *S, orc_diag *out) {
     *out = S->d;
+    out->errors = (S->d.nans > 0 ? ORC_ERR_NAN : 0) | (S->d.negative > 0 ? ORC_ERR_NEG_EPS : 0) |
+                  (S->d.nonconv > 0 ? ORC_ERR_NONCONV : 0) |
+                  (S->d.max_cfl > S->p.cfl_limit ? ORC_ERR_CFL : 0);
     return 0;
 }
 

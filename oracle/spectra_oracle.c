@@ -31,9 +31,7 @@
 
 #define HBARC_S 0.1973269804
 
-/* Planted-mistake switch shared with hydro_oracle.c (0 = as written). */
-int orc_get_mutant(void);
-#define PMUT(k) (orc_get_mutant() == (k))
+#include "oracle_mut.h" /* planted-mistake switches (mutant build only) */
 
 int orc_spectra(const double *el, long n, double T, double eps_plus_P, int ns, const double *mass,
                 const double *dof, const int *stat, const double *mu, int nY, const double *Y,
@@ -56,8 +54,8 @@ int orc_spectra(const double *el, long n, double T, double eps_plus_P, int ns, c
                         const double p[4] = {mT * cosh(Y[iy] - eta), pt[ip] * cos(phi[iq]),
                                              pt[ip] * sin(phi[iq]), mT * sinh(Y[iy] - eta)};
                         const double pdS = p[0] * r[5] + p[1] * r[6] + p[2] * r[7] +
-                                           (PMUT(26) ? p[3] : p[3] / tau) * r[8];
-                        const double pu = p[0] * ut - (PMUT(27) ? -p[1] : p[1]) * ux - p[2] * uy -
+                                           (MUT(26) ? p[3] : p[3] / tau) * r[8];
+                        const double pu = p[0] * ut - (MUT(27) ? -p[1] : p[1]) * ux - p[2] * uy -
                                           p[3] * ue;
                         const double f = 1.0 / (exp((pu - mu[s]) / T) + (double)stat[s]);
                         double df = 0.0;
@@ -66,7 +64,7 @@ int orc_spectra(const double *el, long n, double T, double eps_plus_P, int ns, c
                             for (int a = 0; a < 4; ++a)
                                 for (int b = 0; b < 4; ++b)
                                     ppi += gt[a] * p[a] * gt[b] * p[b] * r[12 + sym[a][b]];
-                            df = (PMUT(25) ? 1.0 + (double)stat[s] * f : 1.0 - (double)stat[s] * f) *
+                            df = (MUT(25) ? 1.0 + (double)stat[s] * f : 1.0 - (double)stat[s] * f) *
                                  ppi / (2.0 * T * T * eps_plus_P);
                         }
                         sum += pdS * f * (1.0 + df);

@@ -40,10 +40,7 @@
 
 #define SURF_REC 24
 
-/* Planted-mistake switch shared with hydro_oracle.c (0 = as written); only the
- * pin tests' self-check sets it. */
-int orc_get_mutant(void);
-#define SMUT(k) (orc_get_mutant() == (k))
+#include "oracle_mut.h" /* planted-mistake switches (mutant build only) */
 
 /* Hot volume fraction of a tetrahedron on which phi is linear with vertex
  * values v[0..3] (exact; every branch is a sum or product of positive terms). */
@@ -60,7 +57,7 @@ static double tet_hot_fraction(const double v[4]) {
     if (np == 4) return 1.0;
     if (np == 1) {
         double a = pos[0];
-        if (SMUT(24)) return (a / (a + neg[0])) * (a / (a + neg[1]));
+        if (MUT(24)) return (a / (a + neg[0])) * (a / (a + neg[1]));
         return (a / (a + neg[0])) * (a / (a + neg[1])) * (a / (a + neg[2]));
     }
     if (np == 3) {
@@ -73,7 +70,7 @@ static double tet_hot_fraction(const double v[4]) {
      * with c, d the magnitudes of the cold values */
     double a = pos[0], b = pos[1], c = neg[0], d = neg[1];
     double num = a * a * b * b + a * b * (a + b) * (c + d) +
-                 (SMUT(22) ? 0.0 : c * d * (a * a + a * b + b * b));
+                 (MUT(22) ? 0.0 : c * d * (a * a + a * b + b * b));
     double den = (a + c) * (a + d) * (b + c) * (b + d);
     return num / den;
 }
@@ -151,7 +148,7 @@ long orc_surface(int nx, int ny, int ne, double dx, double dy, double de, const 
                     double V = 1.0;
                     for (int ax = 0; ax < 4; ++ax)
                         if (ax != mu) V *= ext[ax];
-                    Sm[mu] = V * (SMUT(21) ? f[1] - f[0] : f[0] - f[1]);
+                    Sm[mu] = V * (MUT(21) ? f[1] - f[0] : f[0] - f[1]);
                 }
                 /* centre: mean of the edge crossings, in units of the extents */
                 double cen[4] = {0.0, 0.0, 0.0, 0.0};
@@ -162,7 +159,7 @@ long orc_surface(int nx, int ny, int ne, double dx, double dy, double de, const 
                         if (c & bitm) continue;
                         const int c2 = c | bitm;
                         if ((phi[c] > 0.0) == (phi[c2] > 0.0)) continue;
-                        const double s = SMUT(23) ? phi[c2] / (phi[c2] - phi[c])
+                        const double s = MUT(23) ? phi[c2] / (phi[c2] - phi[c])
                                                   : phi[c] / (phi[c] - phi[c2]);
                         for (int a2 = 0; a2 < 4; ++a2) {
                             const int bb = (c >> (3 - a2)) & 1;

@@ -36,7 +36,7 @@ class ktmi_desc(C.Structure):
                 ("newton_maxit", C.c_int), ("pi_reg", C.c_double), ("precision", C.c_int),
                 ("guess", C.c_int), ("tile", C.c_int), ("taupi_coef", C.c_double),
                 ("lambda1_hat", C.c_double), ("zetas", C.c_double),
-                ("taubulk_coef", C.c_double), ("baryon", C.c_int)]
+                ("taubulk_coef", C.c_double), ("baryon", C.c_int), ("cfl_limit", C.c_double)]
 
 
 class ktmi_diagnostics(C.Structure):
@@ -44,7 +44,8 @@ class ktmi_diagnostics(C.Structure):
                 ("sum_Ttt", C.c_double), ("geo_src", C.c_double), ("max_cfl", C.c_double),
                 ("newton_mean", C.c_double), ("newton_max", C.c_long), ("solves", C.c_long),
                 ("fallbacks", C.c_long), ("nonconv", C.c_long), ("nans", C.c_long),
-                ("vacuum", C.c_long), ("clamps", C.c_long)]
+                ("vacuum", C.c_long), ("clamps", C.c_long), ("negative", C.c_long),
+                ("errors", C.c_int)]
 
 
 def _load():

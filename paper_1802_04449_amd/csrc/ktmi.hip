@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_init_primitive(Fields f, StepParams 
 // in a fixed order (thread t takes tiles t, t + kRedBlock, ...; then the waves
 // and the workgroup in order).
 // acc: 0 geo_src, 1 max_cfl, 2 solves, 3 iter_sum, 4 iter_max, 5 fallbacks,
-//      6 nonconv, 7 nans, 8 clamps, 9 eps_max, 10 sum_Ttt, 11 vacuum.
+//      6 nonconv, 7 nans, 8 clamps, 9 eps_max, 10 sum_Ttt, 11 vacuum, 12 negative.
 constexpr int kRedBlock = 1024;
 __global__ __launch_bounds__(kRedBlock) void k_reduce(const EventDesc* __restrict__ evs) {
   __shared__ double sh[2][kRedBlock / 64];
@@ -307,6 +307,10 @@ static bool desc_ok(const ktmi_desc* d, std::string* why) {
   }
   if (d->tile < -1 || d->tile >= kNumTiles) {
     *why = "tile index out of range";
+    return false;
+  }
+  if (!(d->cfl_limit > 0.0)) {
+    *why = "cfl_limit must be > 0";
     return false;
   }
   return true;
@@ -637,6 +641,7 @@ void ktmi_desc_default(ktmi_desc* d) {
   d->zetas = 0.0;
   d->taubulk_coef = 5.0;
   d->baryon = 0;
+  d->cfl_limit = 0.5;
 }
 
 size_t ktmi_workspace_bytes(const ktmi_desc* d) {
@@ -1073,6 +1078,10 @@ int ktmi_diag(ktmi_handle* h, ktmi_diagnostics* out) {
   out->eps_max = acc[9];
   out->sum_Ttt = acc[10];
   out->vacuum = (long)acc[11];
+  out->negative = (long)acc[12];
+  out->errors = (out->nans > 0 ? KTMI_ERR_NAN : 0) | (out->negative > 0 ? KTMI_ERR_NEG_EPS : 0) |
+                (out->nonconv > 0 ? KTMI_ERR_NONCONV : 0) |
+                (out->max_cfl > h->d.cfl_limit ? KTMI_ERR_CFL : 0);
   return KTMI_OK;
 }
 

@@ -62,8 +62,8 @@ struct EosDev {
   const float* cs2f;
 };
 
-// Root-solve outcome flags (counted in the diagnostics).
-enum : int { kFallback = 1, kNonconv = 2, kNan = 4, kVac = 8, kClamp = 16 };
+// Root-solve outcome flags (counted in the diagnostics).  kNeg: K^tau < 0.
+enum : int { kFallback = 1, kNonconv = 2, kNan = 4, kVac = 8, kClamp = 16, kNeg = 32 };
 
 // ---------------------------------------------------------------------------
 // EoS lookup (Sec. III, EoS options).  The table is uniform in e; values are
@@ -190,7 +190,7 @@ __device__ inline Prim con2prim(const EosDev& q, const StepParams& p, double E, 
     return vacuum();
   }
   if (!(E >= p.eps_cut)) {
-    flags = kVac;
+    flags = kVac | (E < 0.0 ? kNeg : 0);
     return vacuum();
   }
   double B = E;

@@ -31,14 +31,14 @@
 namespace ktmi {
 
 constexpr int kBlock = 256;
-constexpr int kNP = 12;            // diagnostic partials per workgroup
+constexpr int kNP = 13;            // diagnostic partials per workgroup
 
 constexpr int kEosMaxRows = 8192;  // table capacity reserved in the workspace
 
-// Partial slots.  Sums: 0, 2, 3, 5-8, 10, 11.  Maxima: 1, 4, 9.
+// Partial slots.  Sums: 0, 2, 3, 5-8, 10-12.  Maxima: 1, 4, 9.
 enum : int {
   P_GEO = 0, P_CFL = 1, P_SOLVES = 2, P_ITSUM = 3, P_ITMAX = 4, P_FALLBACK = 5,
-  P_NONCONV = 6, P_NAN = 7, P_CLAMP = 8, P_EMAX = 9, P_TSUM = 10, P_VAC = 11
+  P_NONCONV = 6, P_NAN = 7, P_CLAMP = 8, P_EMAX = 9, P_TSUM = 10, P_VAC = 11, P_NEG = 12
 };
 __host__ __device__ constexpr bool is_max_slot(int s) {
   return s == P_CFL || s == P_ITMAX || s == P_EMAX;
@@ -1094,6 +1094,7 @@ __device__ __forceinline__ void block_partials(double v[kNP], gdouble* out, int 
 
 __device__ __forceinline__ void count_solve(double v[kNP], int it, int fl) {
   if (fl & kNan) v[P_NAN] += 1.0;
+  if (fl & kNeg) v[P_NEG] += 1.0;
   if (it == 0) return;  // decided before iterating (vacuum or NaN input)
   v[P_SOLVES] += 1.0;
   v[P_ITSUM] += (double)it;
@@ -1206,6 +1207,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   const double tf = g.cart ? 1.0 : g.tau;
   if (tile_asleep<TX, TY, TZ>(p, cx.tg, cx.qcur, cx.tile)) {
     v[P_CFL] = vacuum_cfl<RT>(p, tf) * p.h;  // what the vacuum faces would give
+    // the stage-1 root solve of a quiet cell sees K^tau = T~^{tau tau}/tau_{n+1}
+    if (q.active) v[P_NEG] = f.T[0][q.c] < 0.0 ? 1.0 : 0.0;
     block_partials(v, f.partial, cx.tg.ntiles, cx.tile);
     return;
   }
@@ -1356,6 +1359,7 @@ __attribute__((amdgpu_waves_per_eu(s2t_waves<RT, TX, TY, TZ, BK>()))) void k_sta
     if (q.active) {
       v[P_TSUM] = f.T[0][q.c];
       v[P_VAC] = 1.0;
+      v[P_NEG] = f.T[0][q.c] < 0.0 ? 1.0 : 0.0;  // as the skipped root solve would count
     }
     block_partials(v, f.partial + (size_t)kNP * cx.tg.ntiles, cx.tg.ntiles, cx.tile);
     if (threadIdx.x == 0) cx.qnext[cx.tile] = 1;

@@ -25,7 +25,8 @@ def oracle_params(p: dict, **kw) -> O.Params:
                     cartesian=bool(q["cartesian"]), **{k: q[k] for k in
                                                       ("eps_cut", "theta", "newton_tol",
                                                        "newton_maxit", "pi_reg", "taupi_coef",
-                                                       "lambda1_hat", "zetas", "taubulk_coef")
+                                                       "lambda1_hat", "zetas", "taubulk_coef",
+                                                       "cfl_limit")
                                                       if k in q},
                     baryon=bool(q.get("baryon", 0)))
 

@@ -54,11 +54,27 @@ def pin_bjorken_ideal():
     return ok, dict(heun_dev=heun_dev, ratio=ratio, errs=errs)
 
 
-def _is_reduced(eps0, phi0, tau0, h, n, etas):
+def _is_reduced(eps0, phi0, tau0, h, n, etas, cap=0.0, stats=None):
     """The paper's RK2 (pi first, then T with pi^{n+1}) applied to the 0+1D IS system
-    in the variables (Q = tau eps, Phi); u~ = (1, 0, 0, 0) so u* = u and no division."""
+    in the variables (Q = tau eps, Phi); u~ = (1, 0, 0, 0) so u* = u and no division.
+    cap > 0: the shear regulator as the reading adopted for the paper's silence
+    states it, written out for this state: sqrt(pi~:pi~) = sqrt(3/2)|Phi| is held
+    to cap (e + P), after the predictor with the rate's own e^n and after the
+    corrector with e'; the corrector is then the average of the start and the
+    (regulated) prediction plus half a step of the stage-2 rate.  stats (a dict)
+    receives how many of the regulations scaled Phi."""
     def P(e):
         return e / 3.0
+
+    def reg(phi, e):
+        if cap <= 0.0:
+            return phi
+        rho = math.sqrt(1.5) * abs(phi) / (e + P(e))
+        if rho > cap:
+            if stats is not None:
+                stats["fired"] = stats.get("fired", 0) + 1
+            return phi * (cap / rho)
+        return phi
 
     def phis(e, phi, tau):
         T = (e / E.C_SB) ** 0.25
@@ -72,10 +88,13 @@ def _is_reduced(eps0, phi0, tau0, h, n, etas):
         RT1 = -(P(e) - phi)
         Rp1 = phis(e, phi, tau)
         Q1 = Q + h * RT1
-        phi1 = phi + h * Rp1
+        phi1 = reg(phi + h * Rp1, e)
         e1 = Q1 / (tau + h)
         Rp2 = phis(e1, phi1, tau + h)
-        phiN = phi + 0.5 * h * (Rp1 + Rp2)
+        if cap > 0.0:
+            phiN = reg(0.5 * (phi + phi1) + 0.5 * h * Rp2, e1)
+        else:
+            phiN = phi + 0.5 * h * (Rp1 + Rp2)
         RT2 = -(P(e1) - phiN)
         Q = Q + 0.5 * h * (RT1 + RT2)
         phi = phiN
@@ -120,6 +139,172 @@ def pin_bjorken_viscous():
     ns_dev = abs(Tn / Tns - 1.0)
     ok = red_dev < 1e-12 and 3.5 < ratio < 4.5 and ns_dev < 0.01
     return ok, dict(red_dev=red_dev, ratio=ratio, errs=errs, ns_dev=ns_dev)
+
+
+# ---------------------------------------------------------------------------
+# Shear regulator (the paper states none; the reading adopted holds
+# sqrt(|pi~:pi~|) to pi_reg (e + P) after each stage's pi~ update).
+# ---------------------------------------------------------------------------
+_SYM = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]
+
+
+def _pack(M):
+    return np.array([M[a, b] for a, b in _SYM])
+
+
+def _boost(v):
+    """Pure Lorentz boost (contravariant) from the rest frame to velocity v."""
+    v = np.asarray(v, dtype=float)
+    b2 = float(v @ v)
+    g = 1.0 / math.sqrt(1.0 - b2)
+    L = np.eye(4)
+    L[0, 0] = g
+    L[0, 1:] = L[1:, 0] = g * v
+    if b2 > 0.0:
+        L[1:, 1:] += (g - 1.0) * np.outer(v, v) / b2
+    return L
+
+
+def pin_regulator():
+    """The regulator on single cells, against values fixed without the oracle's
+    contraction: a rest-frame shear tensor A (spatial, so pi:pi = sum A_ij^2)
+    boosted to a random velocity keeps that invariant, so when it exceeds the cap
+    the regulated tensor must be the boosted tensor times cap (e+P)/|A|, and below
+    the cap it must be unchanged; one-component tensors (not transverse) have
+    |pi:pi| = a^2 (diagonal) or 2 a^2 (off-diagonal, with pi:pi < 0 for tau-i);
+    e = 0 zeroes every transported component; with bulk pressure and baryon
+    density the shear factor leaves Pi and n alone and Pi is clipped to [-P, P]."""
+    cap, e = 0.3, 7.0
+    w = e + e / 3.0  # conformal EoS
+    o = _orc(1, 1, 1, 0.3, 0.3, 0.3, 1.0, 0.01, etas=0.1, viscous=True, pi_reg=cap)
+    rng = np.random.default_rng(17)
+    dev = 0.0
+    for trial in range(12):
+        A = rng.standard_normal((3, 3))
+        A = A + A.T
+        A -= np.trace(A) / 3.0 * np.eye(3)
+        v = rng.standard_normal(3)
+        v *= rng.uniform(0.0, 0.9) / np.linalg.norm(v)
+        for k in (3.0, 0.5):  # above / below the cap
+            Ar = A * (k * cap * w / np.linalg.norm(A))
+            R = np.zeros((4, 4))
+            R[1:, 1:] = Ar
+            L = _boost(v)
+            lab = _pack(L @ R @ L.T)
+            want = lab * (1.0 / k if k > 1.0 else 1.0)
+            got = o.regulate(e, lab)
+            dev = max(dev, float(np.max(np.abs(got - want)) / np.max(np.abs(want))))
+    for (a, b) in [(0, 0), (0, 1), (0, 3), (1, 1), (1, 2), (2, 3), (3, 3)]:
+        x = 2.0 * cap * w
+        norm = abs(x) * (1.0 if a == b else math.sqrt(2.0))
+        q = np.zeros(10)
+        q[_SYM.index((a, b))] = x
+        got = o.regulate(e, q)
+        want = q * (cap * w / norm)
+        dev = max(dev, float(np.max(np.abs(got - want)) / abs(x)))
+    vac = o.regulate(0.0, np.full(10, 0.7))
+    dev = max(dev, float(np.max(np.abs(vac))))
+    ob = _orc(1, 1, 1, 0.3, 0.3, 0.3, 1.0, 0.01, etas=0.1, viscous=True, pi_reg=cap, zetas=0.05,
+              baryon=True)
+    Pe = e / 3.0
+    for Pi_in, Pi_want in ((0.5 * Pe, 0.5 * Pe), (2.0 * Pe, Pe), (-2.0 * Pe, -Pe)):
+        q = np.zeros(12)
+        q[4], q[7], q[9] = 2.0 * cap * w, -2.0 * cap * w, 0.0
+        q[10], q[11] = Pi_in, 0.3
+        got = ob.regulate(e, q)
+        f = cap * w / (2.0 * cap * w * math.sqrt(2.0))
+        want = np.concatenate([q[:10] * f, [Pi_want, 0.3]])
+        dev = max(dev, float(np.max(np.abs(got - want)) / (2.0 * cap * w)))
+    vb = ob.regulate(0.0, np.full(12, 0.7))
+    dev = max(dev, float(np.max(np.abs(vb))))
+    return dev < 1e-14, dict(dev=dev)
+
+
+def pin_regulator_bjorken():
+    """Viscous Bjorken flow starting at eight times its Navier-Stokes shear stress,
+    with a cap below the Navier-Stokes ratio sqrt(3/2) Phi_NS/(e + P) of the early
+    steps (so the relaxation keeps pushing Phi into it): the 3D oracle must equal
+    the 0+1D scheme with the regulator written out at the two stated points
+    (predictor with e^n, corrector with e') to 1e-12; the cap must fire for many
+    steps and no longer in the last ones (the Navier-Stokes ratio falls as
+    tau^(-2/3)), and removing it must change the result."""
+    etas, tau0, T0, cap, h, n = 0.08, 0.6, 0.4, 0.07, 0.02, 60
+    eps0 = E.C_SB * T0 ** 4
+    eta0 = etas * (4.0 / 3.0 * eps0) * E.HBARC / T0
+    phi0 = 8.0 * (4.0 * eta0 / (3.0 * tau0))
+    g = ics.Grid(3, 4, 5, 0.3, 0.3, 0.3)
+    o = _orc(*g.shape, g.dx, g.dy, g.de, tau0, h, etas=etas, viscous=True, pi_reg=cap)
+    o.set_initial(ics.bjorken(g, eps0, phi0))
+    stats = {}
+    dev, fired_late = 0.0, 0
+    for step in range(n):
+        o.step(1)
+        st = {}
+        er, pr = _is_reduced(eps0, phi0, tau0, h, step + 1, etas, cap=cap, stats=st)
+        e, phi = o.read("eps"), -o.read("pi9")
+        dev = max(dev, float(np.max(np.abs(e / er - 1.0))), float(np.max(np.abs(phi / pr - 1.0))),
+                  float(np.max(np.abs(o.read("pi4") - 0.5 * phi)) / abs(pr)))
+        stats = st
+    fired = stats.get("fired", 0)
+    e_free, p_free = _is_reduced(eps0, phi0, tau0, h, n, etas)
+    effect = abs(p_free / pr - 1.0)
+    st_last = {}
+    _is_reduced(eps0, phi0, tau0, h, n, etas, cap=cap, stats=st_last)
+    st_prev = {}
+    _is_reduced(eps0, phi0, tau0, h, n - 5, etas, cap=cap, stats=st_prev)
+    fired_late = st_last.get("fired", 0) - st_prev.get("fired", 0)
+    ok = dev < 1e-12 and fired >= 4 and fired_late == 0 and effect > 1e-3
+    return ok, dict(dev=dev, fired=fired, fired_late=fired_late, effect=effect)
+
+
+def pin_regulator_consistency():
+    """The stored state after a step obeys the root solve's defining relation
+    T~^{tau mu}/tau = (e + P) u~^tau u~^mu - P g~^{tau mu} + pi~^{tau mu} (to the
+    solve's tolerance) also where the regulator fires: pi~^{n+1} is final before
+    T~^{n+1} uses it and before the root solve, as the paper's corrector orders
+    them.  Lumpy moving fluid with shear stress transverse to the flow and above
+    the cap (Milne, conformal EoS)."""
+    g = ics.Grid(17, 15, 13, 0.3, 0.3, 0.3)
+    e0 = _blob(g, eps_peak=15.0, width=0.7, seed=8)
+    e0 = np.where(e0 > 0, e0 + 0.5, 0.0)
+    X, Y, Eta = g.mesh()
+    ux = 0.4 * np.sin(1.3 * X + 0.4) * (e0 > 0)
+    uy = 0.3 * np.cos(0.9 * Y - 0.2) * (e0 > 0)
+    ue = 0.2 * np.sin(1.1 * Eta + 0.3) * (e0 > 0)
+    rng = np.random.default_rng(23)
+    A = rng.standard_normal((3, 3))
+    A = A + A.T
+    A -= np.trace(A) / 3.0 * np.eye(3)
+    A /= np.linalg.norm(A)
+    pi = np.zeros((10,) + g.shape)
+    for idx in zip(*np.nonzero(e0 > 0)):
+        u3 = np.array([ux[idx], uy[idx], ue[idx]])
+        v = u3 / math.sqrt(1.0 + u3 @ u3)
+        R = np.zeros((4, 4))
+        R[1:, 1:] = A * (0.6 * (4.0 / 3.0) * e0[idx])  # |pi:pi|^(1/2) = 0.6 (e + P)
+        L = _boost(v)
+        pi[(slice(None),) + idx] = _pack(L @ R @ L.T)
+    devs, diffs = [], []
+    for cap in (0.3, 0.0):
+        o = _orc(*g.shape, g.dx, g.dy, g.de, 0.6, 0.01, etas=0.1, viscous=True, pi_reg=cap)
+        o.set_initial(dict(eps=e0, ux=ux, uy=uy, ue=ue, pi=pi))
+        o.step(3)
+        e, u = o.read("eps"), [o.read(k) for k in ("ux", "uy", "ue")]
+        ut = np.sqrt(1.0 + u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+        P = e / 3.0
+        u4 = [ut] + u
+        tau = 0.6 + 3 * 0.01
+        mask = e > 0
+        scale = np.max(np.abs(o.read("T0")))
+        dev = 0.0
+        for nu in range(4):
+            rhs = (e + P) * ut * u4[nu] - (P if nu == 0 else 0.0) + o.read(f"pi{nu}")
+            dev = max(dev, float(np.max(np.abs(o.read(f"T{nu}")[mask] / tau - rhs[mask]))) / scale)
+        devs.append(dev)
+        diffs.append(o.read("pi4"))
+    effect = float(np.max(np.abs(diffs[0] - diffs[1])) / np.max(np.abs(diffs[1])))
+    ok = devs[0] < 1e-12 and effect > 1e-2
+    return ok, dict(dev=devs[0], dev_uncapped=devs[1], effect=effect)
 
 
 def pin_gubser():
@@ -1017,6 +1202,9 @@ ALL_PINS = {
     "first_step": pin_first_step,
     "bjorken_ideal": pin_bjorken_ideal,
     "bjorken_viscous": pin_bjorken_viscous,
+    "regulator": pin_regulator,
+    "regulator_bjorken": pin_regulator_bjorken,
+    "regulator_consistency": pin_regulator_consistency,
     "gubser": pin_gubser,
     "riemann": pin_riemann,
     "relaxing_static": lambda: pin_relaxing_fluid(0.0),

@@ -1,5 +1,7 @@
 """Self-check of the pins: plant one plausible mistake at a time in the oracle
-(on the CPU) and require that at least one pin fails.
+(on the CPU) and require that at least one pin fails.  The mistakes exist only in
+the separate mutant build liboracle_mut.so (-DORC_MUTANTS); oracle.set_mutant()
+switches to it and back.
 
 Mutants (see MUT(k) in oracle/hydro_oracle.c):
  1 S_T^tau sign, 2 sign of the pi u~^tau/tau term, 3 sign of I^{mu nu},
@@ -18,7 +20,12 @@ Mutants (see MUT(k) in oracle/hydro_oracle.c):
  instead of (1 - sigma f), 26 p^eta dSigma_eta without the 1/tau of the tilde
  component, 27 the sign of p^x u^x in p.u; bulk and baryon: 28 the sign of
  zeta theta in S_Pi, 29 S_Pi without its Pi u~^tau/tau term, 30 Pi left out of
- T's density and flux, 31 the root solve without Pi, 32 S_n dropped.
+ T's density and flux, 31 the root solve without Pi, 32 S_n dropped; shear
+ regulator: 33 a third regulation after the root solve with e^{n+1} (the
+ stored pi~ then no longer matches T~ and (e, u~)), 34 the corrector regulated
+ with e^n instead of e', 35 the sign of the tau-i terms of pi~:pi~, 36 the sign
+ of the i-j off-diagonal terms, 37 |pi~:pi~| without the absolute value, 38 the
+ shear factor applied to Pi and n too.
 Mutant 16 (u* = u^n instead of 2u^n - u^{n-1}) alters only the predicted pi'
 at O(h) and the step at O(h^2), the scheme's own order, so no pin is expected
 to separate it; the GPU-oracle parity tests cover that code path.
@@ -32,7 +39,7 @@ import oracle as O
 
 from . import pins
 
-CAUGHT = list(range(1, 16)) + list(range(17, 33))
+CAUGHT = list(range(1, 16)) + list(range(17, 39))
 
 
 @pytest.mark.parametrize("k", CAUGHT)
