@@ -299,6 +299,21 @@ size_t ktmi_mlp_grad_workspace_bytes(int n);
 int ktmi_mlp_grad(const float *params, int n, const double *E, const double *M, const double *eps,
                   double emin, int mode, float *out, void *ws, size_t bytes, void *stream);
 
+/* ktmi_mlp_grad for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight training loops, harnesses that
+ * forbid allocation).  Same arguments and result as ktmi_mlp_grad, bitwise, but
+ * the per-workgroup partial sums go to a scratch array inside the library: one
+ * 2.56 MB copy per GPU (512 records of ktmi_mlp_nparam() + 2 floats), held
+ * until the process ends.  That covers every sample count the call accepts:
+ * 1 <= n <= 2^31 - 129 (KTMI_EINVAL outside, as for a bad pointer or mode).
+ * No allocation of any kind; the first call on a GPU looks up the array's
+ * device address (KTMI_EHIP if that fails).  The array is shared by every call
+ * on one GPU and keeps the last call's contents: calls that overlap on one GPU
+ * (on different streams, or from several threads) race and must be ordered by
+ * the caller.  Async on stream. */
+int ktmi_mlp_grad_noalloc(const float *params, int n, const double *E, const double *M,
+                          const double *eps, double emin, int mode, float *out, void *stream);
+
 /* One Adam step (Kingma & Ba 2015; bias-corrected moments, t counts from 1) on
  * params with gradient grad and moment arrays m, v (device, updated).  Async. */
 int ktmi_mlp_adam(float *params, const float *grad, float *m, float *v, int t, float lr, float b1,

@@ -97,6 +97,8 @@ def _load():
         "ktmi_mlp_grad_workspace_bytes": (sz, [C.c_int]),
         "ktmi_mlp_grad": (C.c_int, [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, vp, vp, sz,
                                     vp]),
+        "ktmi_mlp_grad_noalloc": (C.c_int, [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, vp,
+                                            vp]),
         "ktmi_mlp_adam": (C.c_int, [vp, vp, vp, vp, C.c_int, f, f, f, f, vp]),
         "ktmi_step_until": (C.c_int, [vp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int)]),
         "ktmi_snapshot_doubles": (sz, [vp, C.c_int]),
@@ -374,6 +376,12 @@ def ktmi_mlp_grad(params_ptr, n, E_ptr, M_ptr, eps_ptr, emin, mode, out_ptr, ws_
                              C.c_void_p(M_ptr), C.c_void_p(eps_ptr), float(emin), int(mode),
                              C.c_void_p(out_ptr), C.c_void_p(ws_ptr), int(ws_bytes),
                              C.c_void_p(stream_ptr)))
+
+
+def ktmi_mlp_grad_noalloc(params_ptr, n, E_ptr, M_ptr, eps_ptr, emin, mode, out_ptr, stream_ptr):
+    _check(lib.ktmi_mlp_grad_noalloc(C.c_void_p(params_ptr), int(n), C.c_void_p(E_ptr),
+                                     C.c_void_p(M_ptr), C.c_void_p(eps_ptr), float(emin),
+                                     int(mode), C.c_void_p(out_ptr), C.c_void_p(stream_ptr)))
 
 
 def ktmi_mlp_adam(params_ptr, grad_ptr, m_ptr, v_ptr, t, lr, b1, b2, epsilon, stream_ptr):

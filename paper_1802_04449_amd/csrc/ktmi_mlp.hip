@@ -6,6 +6,8 @@
 // folds the workgroups in a fixed order (bitwise reproducible), then Adam.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "../../include/ktmi.h"
 #include "ktmi_mlp.hpp"
 
@@ -197,8 +199,52 @@ __global__ void k_mlp_adam(float* __restrict__ prm, const float* __restrict__ g,
 }
 
 static int mlp_grid(int n) {
-  const int nchunk = (n + kMlpBlock - 1) / kMlpBlock;
+  const int nchunk = (int)(((long)n + kMlpBlock - 1) / kMlpBlock);
   return nchunk < kMlpGrid ? nchunk : kMlpGrid;
+}
+
+// Largest sample count: the gradient kernel indexes samples with 32-bit ints
+// (chunk * kMlpBlock + thread), which stay below 2^31 up to this n.
+constexpr int kMlpMaxSamples = 0x7fffffff - kMlpBlock;
+
+// Scratch of ktmi_mlp_grad_noalloc: the partial sums of the gradient kernel's
+// workgroups (at most kMlpGrid records of kMlpSlots floats, 2.56 MB).  One copy
+// per GPU, held until the process ends.  Its name is a host-side stand-in in
+// host code: kernels get the device address from hipGetSymbolAddress.
+constexpr size_t kMlpScratchFloats = (size_t)kMlpGrid * kMlpSlots;
+static __device__ __align__(256) float scratch[kMlpScratchFloats];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[kMaxDevices];  // device address of scratch on each GPU
+
+// Device address of scratch on the current GPU, looked up once per device.
+static int scratch_on_current_device(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return KTMI_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return KTMI_EHIP;
+    g_scratch_ptr[dev] = (float*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return KTMI_OK;
+}
+
+// Gradient kernel, then the fixed-order fold of its workgroups, into out.
+static int launch_mlp_grad(const float* params, int n, const double* E, const double* M,
+                           const double* eps, double emin, int mode, float* out, float* part,
+                           hipStream_t s) {
+  const int nblk = mlp_grid(n);
+  if (mode == KTMI_MLP_BF16)
+    hipLaunchKernelGGL(k_mlp_grad<1>, dim3(nblk), dim3(kMlpBlock), 0, s, params, n, E, M, eps,
+                       emin, part);
+  else
+    hipLaunchKernelGGL(k_mlp_grad<0>, dim3(nblk), dim3(kMlpBlock), 0, s, params, n, E, M, eps,
+                       emin, part);
+  hipLaunchKernelGGL(k_mlp_fold, dim3((kMlpSlots + 255) / 256), dim3(256), 0, s, part, nblk, out);
+  return hipGetLastError() == hipSuccess ? KTMI_OK : KTMI_EHIP;
 }
 
 }  // namespace ktmi
@@ -234,18 +280,21 @@ int ktmi_mlp_grad(const float* params, int n, const double* E, const double* M, 
   if (!params || n < 1 || !E || !M || !eps || !out || !ws ||
       (mode != KTMI_MLP_FP32 && mode != KTMI_MLP_BF16))
     return KTMI_EINVAL;
-  if (bytes < ktmi_mlp_grad_workspace_bytes(n)) return KTMI_EINVAL;
-  const int nblk = mlp_grid(n);
-  hipStream_t s = (hipStream_t)stream;
-  float* part = (float*)ws;
-  if (mode == KTMI_MLP_BF16)
-    hipLaunchKernelGGL(k_mlp_grad<1>, dim3(nblk), dim3(kMlpBlock), 0, s, params, n, E, M, eps,
-                       emin, part);
-  else
-    hipLaunchKernelGGL(k_mlp_grad<0>, dim3(nblk), dim3(kMlpBlock), 0, s, params, n, E, M, eps,
-                       emin, part);
-  hipLaunchKernelGGL(k_mlp_fold, dim3((kMlpSlots + 255) / 256), dim3(256), 0, s, part, nblk, out);
-  return hipGetLastError() == hipSuccess ? KTMI_OK : KTMI_EHIP;
+  if (n > kMlpMaxSamples || bytes < ktmi_mlp_grad_workspace_bytes(n)) return KTMI_EINVAL;
+  return launch_mlp_grad(params, n, E, M, eps, emin, mode, out, (float*)ws, (hipStream_t)stream);
+}
+
+int ktmi_mlp_grad_noalloc(const float* params, int n, const double* E, const double* M,
+                          const double* eps, double emin, int mode, float* out, void* stream) {
+  if (!params || n < 1 || n > kMlpMaxSamples || !E || !M || !eps || !out ||
+      (mode != KTMI_MLP_FP32 && mode != KTMI_MLP_BF16))
+    return KTMI_EINVAL;
+  // every sample count fits: the kernel never runs more than kMlpGrid workgroups
+  if ((size_t)mlp_grid(n) * kMlpSlots > kMlpScratchFloats) return KTMI_EINVAL;
+  float* part = nullptr;
+  const int rc = scratch_on_current_device(&part);
+  if (rc != KTMI_OK) return rc;
+  return launch_mlp_grad(params, n, E, M, eps, emin, mode, out, part, (hipStream_t)stream);
 }
 
 int ktmi_mlp_adam(float* params, const float* grad, float* m, float* v, int t, float lr, float b1,

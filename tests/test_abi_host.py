@@ -143,6 +143,11 @@ def test_learned_guess_argument_checks():
     assert lib.ktmi_mlp_forward(8, 4, 8, 8, 1e-7, 8, 7, None) == K.KTMI_EINVAL        # bad mode
     assert lib.ktmi_mlp_grad(8, 0, 8, 8, 8, 1e-7, 0, 8, 8, 1 << 20, None) == K.KTMI_EINVAL
     assert lib.ktmi_mlp_grad(8, 1000, 8, 8, 8, 1e-7, 0, 8, 8, 16, None) == K.KTMI_EINVAL  # short ws
+    assert lib.ktmi_mlp_grad_noalloc(8, 0, 8, 8, 8, 1e-7, 0, 8, None) == K.KTMI_EINVAL  # empty
+    assert lib.ktmi_mlp_grad_noalloc(8, 2 ** 31 - 128, 8, 8, 8, 1e-7, 0, 8,
+                                     None) == K.KTMI_EINVAL                          # too many
+    assert lib.ktmi_mlp_grad_noalloc(8, 100, 8, 8, 8, 1e-7, 5, 8, None) == K.KTMI_EINVAL  # mode
+    assert lib.ktmi_mlp_grad_noalloc(8, 100, None, 8, 8, 1e-7, 0, 8, None) == K.KTMI_EINVAL
     assert lib.ktmi_mlp_adam(8, 8, 8, 8, 0, 1e-3, 0.9, 0.999, 1e-8, None) == K.KTMI_EINVAL  # t < 1
     assert lib.ktmi_mlp_adam(8, 8, 8, 8, 1, 1e-3, 1.0, 0.999, 1e-8, None) == K.KTMI_EINVAL  # b1 = 1
     d = _desc(guess=K.KTMI_GUESS_MLP)
