@@ -137,7 +137,8 @@ typedef struct ktmi_handle ktmi_handle;
 void ktmi_desc_default(ktmi_desc *d);
 
 /* Validates d and creates a handle (host memory only).  KTMI_EINVAL if a size
- * is < 1, a spacing, tau0 or h is not > 0, viscous with etas <= 0 or
+ * is < 1, the grid has more than 2^29 - 256 cells (the kernels address a
+ * field by 32-bit byte offsets), a spacing, tau0 or h is not > 0, viscous with etas <= 0 or
  * taupi_coef <= 0, lambda1_hat is not finite, zetas is not finite and >= 0,
  * baryon is not 0 or 1, or bulk/baryon is asked for without viscous mode, FP64
  * and lambda1_hat = 0, or with taubulk_coef <= 0, or cfl_limit is not > 0. */

@@ -219,6 +219,7 @@ struct ktmi_handle {
   // quiet-tile skipping (off by default); P of the EoS at e = 0 (must be 0 for it)
   bool quiet_on = false;
   double eos_p0 = 0.0;
+  double p_at0 = 0.0;  // P as the device lookups give it at e = 0 (first row, or 0)
   int mlp_mode = KTMI_MLP_FP32;
 };
 
@@ -251,8 +252,9 @@ static bool desc_ok(const ktmi_desc* d, std::string* why) {
     *why = "grid sizes must be >= 1";
     return false;
   }
-  if ((double)d->nx * d->ny * d->ne > 2.0e9) {
-    *why = "grid too large (more than 2e9 cells)";
+  // the kernels address a field's elements by 32-bit byte offsets
+  if ((double)d->nx * d->ny * d->ne > (double)((1u << 29) - 256)) {
+    *why = "grid too large (more than 2^29 - 256 cells)";
     return false;
   }
   if (!(d->dx > 0) || !(d->dy > 0) || !(d->de > 0) || !(d->tau0 > 0) || !(d->h > 0)) {
@@ -400,6 +402,7 @@ static StepParams step_params(const ktmi_handle* h) {
   p.newton_tol = h->d.newton_tol;
   p.pi_reg = h->d.pi_reg;
   p.newton_maxit = h->d.newton_maxit;
+  p.vac_zero = h->d.pi_reg > 0.0 && h->p_at0 == 0.0;
   // quiet tiles: neighbourhood radius in tiles covering 6 cells per axis
   const int td[3] = {kTiles[h->tile].tx, kTiles[h->tile].ty, kTiles[h->tile].tz};
   for (int a = 0; a < 3; ++a) p.quiet_r[a] = h->quiet_on ? (6 + td[a] - 1) / td[a] : 0;
@@ -699,19 +702,19 @@ int ktmi_bind(ktmi_handle* h, void* ws, size_t bytes, void* stream) {
   const size_t fs = h->fstride;
   int q = 0;
   Fields& f = h->f;
+  // pi~ and its stage-1 value are blocks of consecutive fields (the kernels
+  // address a block from its first field), Pi and n right after pi~'s 10
+  const int nq = has_ext(&h->d) ? 12 : 10;
+  f.fstride = (long)fs;
   f.e = base + fs * q++;
   for (int m = 0; m < 3; ++m) f.u[m] = base + fs * q++;
   for (int m = 0; m < 3; ++m) f.up[m] = base + fs * q++;
-  for (int m = 0; m < 10; ++m) f.pi[m] = base + fs * q++;
+  for (int m = 0; m < 12; ++m) f.pi[m] = m < nq ? base + fs * q++ : nullptr;
   for (int m = 0; m < 4; ++m) f.T[m] = base + fs * q++;
   f.e1 = base + fs * q++;
   for (int m = 0; m < 3; ++m) f.u1[m] = base + fs * q++;
-  for (int m = 0; m < 10; ++m) f.pi1[m] = base + fs * q++;
+  for (int m = 0; m < 12; ++m) f.pi1[m] = m < nq ? base + fs * q++ : nullptr;
   for (int m = 0; m < 4; ++m) f.T1[m] = base + fs * q++;
-  for (int m = 10; m < 12; ++m) {  // Pi and n, after the other fields
-    f.pi[m] = has_ext(&h->d) ? base + fs * q++ : nullptr;
-    f.pi1[m] = has_ext(&h->d) ? base + fs * q++ : nullptr;
-  }
   double* rest = base + fs * q;
   f.partial = rest;
   rest += (2 * (size_t)max_tiles(&h->d) * kNP + 31) / 32 * 32;
@@ -742,6 +745,7 @@ int ktmi_set_eos_conformal(ktmi_handle* h, double c_sb) {
   h->eos.inv_csb_f = (float)(1.0 / c_sb);
   h->cs2_vac = 1.0 / 3.0;
   h->eos_p0 = 0.0;
+  h->p_at0 = 0.0;
   h->eos_set = true;
   h->ev_dirty = true;
   return KTMI_OK;
@@ -791,6 +795,7 @@ int ktmi_set_eos_table(ktmi_handle* h, double e0, double de, int n, const double
   h->eos.inv_de = 1.0 / de;
   h->cs2_vac = cs2[0];  // lookups clamp e = 0 to the first row
   h->eos_p0 = p0;
+  h->p_at0 = P[0];
   h->eos.P = dP;
   h->eos.T = dT;
   h->eos.cs2 = dC;

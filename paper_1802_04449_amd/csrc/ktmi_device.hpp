@@ -18,6 +18,7 @@ typedef __attribute__((address_space(1))) double gdouble;
 typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) int gint;
 typedef __attribute__((address_space(1))) unsigned long long gullong;
+typedef __attribute__((address_space(1))) char gchar;
 
 template <typename T>
 __device__ __forceinline__ const __attribute__((address_space(1))) T* gl(const T* p) {
@@ -42,6 +43,10 @@ struct StepParams {
   double eps_cut, theta, newton_tol, pi_reg;
   double c_vac;  // local speed of a vacuum state, sqrt(cs2(0))
   int newton_maxit;
+  // 1 when the regulator zeroes pi~ (and Pi, n) wherever e = 0: it is on and the
+  // EoS gives P = 0 at e = 0.  Passes then skip the loads that could not change a
+  // vacuum cell's result.
+  int vac_zero;
   int quiet_r[3];          // quiet-tile skipping: neighbourhood radius in tiles (0: off)
   int guess;               // root-solve start: 0 previous stage, 1 cold (E), 2 network
   int mlp_mfma;            // network forward: 0 FP32 per lane, 1 BF16 matrix cores per wave

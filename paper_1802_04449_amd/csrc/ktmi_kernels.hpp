@@ -44,50 +44,60 @@ __host__ __device__ constexpr bool is_max_slot(int s) {
   return s == P_CFL || s == P_ITMAX || s == P_EMAX;
 }
 
-template <typename D, typename I>
-struct FieldsT {
-  D* e;       // e^n, overwritten by e^{n+1} in stage2T
-  D* u[3];    // u~^n
-  D* up[3];   // u~^{n-1}; stage2T writes u~^{n+1} here
-  D* pi[12];  // pi~^n (0..9), then Pi (10) and n (11) with bulk/baryon (else null);
-              // overwritten by their n+1 values in stage2pi
-  D* T[4];    // T~^{tau mu, n}, overwritten by T^{n+1} in stage2T
-  D* e1;      // stage-1 prediction
-  D* u1[3];
-  D* pi1[12];
-  D* T1[4];
-  D* partial;  // [2][kNP][nblk]: stage1 then stage2T, slot-major
-  D* acc;      // [16] accumulated diagnostics
-  I* quiet;    // [3][ntiles]: quiet flags by clock parity (2), stage-2pi part (1)
+// Field pointers as the host fills them.  The fields of the state live in one
+// workspace with a common stride; the pi~ block (and the stage-1 pi~ block)
+// holds NQ consecutive fields: pi~ (0..9), then Pi (10) and n (11) with
+// bulk/baryon.
+struct Fields {
+  double* e;       // e^n, overwritten by e^{n+1} in stage2T
+  double* u[3];    // u~^n
+  double* up[3];   // u~^{n-1}; stage2T writes u~^{n+1} here
+  double* pi[12];  // pi~^n (0..9), then Pi (10) and n (11) with bulk/baryon (else null);
+                   // overwritten by their n+1 values in stage2pi
+  double* T[4];    // T~^{tau mu, n}, overwritten by T^{n+1} in stage2T
+  double* e1;      // stage-1 prediction
+  double* u1[3];
+  double* pi1[12];
+  double* T1[4];
+  double* partial;  // [2][kNP][nblk]: stage1 then stage2T, slot-major
+  double* acc;      // [16] accumulated diagnostics
+  int* quiet;       // [3][ntiles]: quiet flags by clock parity (2), stage-2pi part (1)
+  long fstride;     // elements from one field to the next
 };
-using Fields = FieldsT<double, int>;     // as the host fills it
-using DFields = FieldsT<gdouble, gint>;  // the same pointers, global address space
 
-__device__ __forceinline__ DFields dfields(const Fields& f) {
-  DFields d;
-  d.e = (gdouble*)f.e;
-  d.e1 = (gdouble*)f.e1;
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    d.u[m] = (gdouble*)f.u[m];
-    d.up[m] = (gdouble*)f.up[m];
-    d.u1[m] = (gdouble*)f.u1[m];
+// One field seen through the global address space.  Element i is addressed by
+// a 32-bit byte offset from the field's base (fields hold fewer than 2^29
+// elements; the host checks the grid size).
+struct GField {
+  gdouble* p;
+  __device__ __forceinline__ double operator[](int i) const {
+    return *(const gdouble*)((const gchar*)p + (unsigned)i * 8u);
   }
-#pragma unroll
-  for (int m = 0; m < 12; ++m) {
-    d.pi[m] = (gdouble*)f.pi[m];
-    d.pi1[m] = (gdouble*)f.pi1[m];
+  __device__ __forceinline__ gdouble* operator+(int i) const {
+    return (gdouble*)((gchar*)p + (unsigned)i * 8u);
   }
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    d.T[m] = (gdouble*)f.T[m];
-    d.T1[m] = (gdouble*)f.T1[m];
-  }
-  d.partial = (gdouble*)f.partial;
-  d.acc = (gdouble*)f.acc;
-  d.quiet = (gint*)f.quiet;
-  return d;
-}
+};
+
+// Consecutive fields of one stride, seen through the global address space.
+// The kernels hold one base pointer per group of fields instead of one per
+// field: forty pointers held at once exceeded the scalar register file, and the
+// compiler kept the spilled pointers in vector-register lanes, reloading them
+// with v_readlane inside the face loops.
+struct FSet {
+  gdouble* b;  // first field of the group
+  long fs;     // elements from one field to the next
+  __device__ __forceinline__ GField operator[](int k) const { return GField{b + (long)k * fs}; }
+};
+
+struct DFields {
+  GField e;
+  FSet u, up, pi, T;
+  GField e1;
+  FSet u1, pi1, T1;
+  gdouble* partial;
+  gdouble* acc;
+  gint* quiet;
+};
 
 struct Geo {
   double tau;   // stage time in the Milne factors (1 in Cartesian mode)
@@ -203,17 +213,24 @@ __device__ __forceinline__ Ctx load_ctx(const EventDesc* __restrict__ evs, const
   while (e + 1 < gt.nev && t >= gt.start[e + 1]) ++e;
   const EventDesc& E = evs[e];
   Ctx c;
-  c.f = dfields(E.f);
+  const long fs = E.f.fstride;
+  c.f.e = GField{(gdouble*)E.f.e};
+  c.f.pi = FSet{(gdouble*)E.f.pi[0], fs};
+  c.f.T = FSet{(gdouble*)E.f.T[0], fs};
+  c.f.e1 = GField{(gdouble*)E.f.e1};
+  c.f.u1 = FSet{(gdouble*)E.f.u1[0], fs};
+  c.f.pi1 = FSet{(gdouble*)E.f.pi1[0], fs};
+  c.f.T1 = FSet{(gdouble*)E.f.T1[0], fs};
+  c.f.partial = (gdouble*)E.f.partial;
+  c.f.acc = (gdouble*)E.f.acc;
+  c.f.quiet = (gint*)E.f.quiet;
   c.p = E.p;
   c.eos = E.eos;
   c.tg = E.tg;
   const double tau = E.clock[0];
   const bool odd = E.clock[2] != 0.0;
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    c.f.u[m] = (gdouble*)(odd ? E.f.up[m] : E.f.u[m]);
-    c.f.up[m] = (gdouble*)(odd ? E.f.u[m] : E.f.up[m]);
-  }
+  c.f.u = FSet{(gdouble*)(odd ? E.f.up[0] : E.f.u[0]), fs};
+  c.f.up = FSet{(gdouble*)(odd ? E.f.u[0] : E.f.up[0]), fs};
   c.g.cart = E.cart;
   c.g.tau1 = tau + E.p.h;
   c.g.tau = stage2 ? c.g.tau1 : tau;
@@ -283,7 +300,7 @@ __device__ __forceinline__ double vacuum_cfl(const StepParams& p, double tauf) {
 
 // pi~ at a cell: PI_SRC 0 -> 0, 1 -> zero where e == 0 (vacuum), 2 -> as stored.
 template <int PI_SRC>
-__device__ __forceinline__ double ld_pi(const gdouble* const* pi, int m, int idx, double e) {
+__device__ __forceinline__ double ld_pi(const FSet& pi, int m, int idx, double e) {
   if (PI_SRC == 0) return 0.0;
   const double v = pi[m][idx];
   if (PI_SRC == 1) return e == 0.0 ? 0.0 : v;
@@ -307,8 +324,8 @@ __device__ __forceinline__ double ld_pi(const gdouble* const* pi, int m, int idx
 // and F), then T~'s flux.  The arithmetic of every component is that of
 // tau (w u u - P g + pi) and u pi as written, in that order.
 template <typename R, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false>
-__device__ __forceinline__ R face_flux_stream(const gdouble* __restrict__ e, const gdouble* const* u,
-                                       const gdouble* const* pi, int base, int a, int n,
+__device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
+                                       const FSet& pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
                                        const EosDev& eos, R* out, int F) {
   int idx[4];
@@ -439,8 +456,8 @@ __device__ __forceinline__ R face_flux_stream(const gdouble* __restrict__ e, con
 // vacuum (all primitives zero) has H = 0 and c = c_vac, so it skips the arithmetic.
 // R is the arithmetic type (double, or float on the mixed-precision path).
 template <typename R, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false>
-__device__ __forceinline__ R face_flux_all(const gdouble* __restrict__ e, const gdouble* const* u,
-                                       const gdouble* const* pi, int base, int a, int n,
+__device__ __forceinline__ R face_flux_all(const GField& e, const FSet& u,
+                                       const FSet& pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
                                        const EosDev& eos, R* out, int F) {
   int idx[4];
@@ -578,8 +595,8 @@ struct FaceLayout {
 // Face f of axis d (0 x, 1 y, 2 eta) of the thread's tile: its flux components go
 // to out[k * S] (zeros for a face outside the grid); returns c / Delta_d (0 outside).
 template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC, bool BK>
-__device__ __forceinline__ double eval_face(const gdouble* __restrict__ e, const gdouble* const* u,
-                                            const gdouble* const* pi, const StepParams& p,
+__device__ __forceinline__ double eval_face(const GField& e, const FSet& u,
+                                            const FSet& pi, const StepParams& p,
                                             const EosDev& eos, double tauf, const Pos& q, int d,
                                             int f, RT* out, int S) {
   constexpr int NC = BK ? 16 : 14;
@@ -635,8 +652,8 @@ __device__ __forceinline__ double eval_face(const gdouble* __restrict__ e, const
 // with one barrier; their 4 components fit lds_doubles_allf (29 KB).
 template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false,
           bool SPLIT = false, bool ALLF = false>
-__device__ __forceinline__ double tile_divergence(const gdouble* __restrict__ e,
-                                                  const gdouble* const* u, const gdouble* const* pi,
+__device__ __forceinline__ double tile_divergence(const GField& e,
+                                                  const FSet& u, const FSet& pi,
                                                   const StepParams& p, const EosDev& eos,
                                                   double tauf, const Pos& q, double* R,
                                                   RT* lds) {
@@ -915,8 +932,8 @@ __device__ __forceinline__ double utau(double a, double b, double c) {
 // (e + P)/c for tau_Pi = c (zeta/s) hbarc / T), S_n = -n u~^tau/tau; pc_d and
 // S_d then hold 12 components.
 template <typename R, bool L1, bool BK = false>
-__device__ __forceinline__ void pi_source(const gdouble* const* u, const gdouble* const* uE,
-                                          const gdouble* const* uL, const StepParams& p,
+__device__ __forceinline__ void pi_source(const FSet& u, const FSet& uE,
+                                          const FSet& uL, const StepParams& p,
                                           const EosDev& eos, const Geo& g, const Pos& q,
                                           double ec_d, const double* pc_d, double* S_d) {
   const R ec = (R)ec_d;
@@ -1178,9 +1195,9 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(const EventDesc* __re
   if (!q.active) return;
   int it, fl;
   const Prim s = con2prim(eos, p, K[0], K[1], K[2], K[3], x0, it, fl);
-  f.up[0][c] = 2.0 * u1 - s.u1;
-  f.up[1][c] = 2.0 * u2 - s.u2;
-  f.up[2][c] = 2.0 * u3 - s.u3;
+  st_cell(f.up[0] + c, 2.0 * u1 - s.u1);
+  st_cell(f.up[1] + c, 2.0 * u2 - s.u2);
+  st_cell(f.up[2] + c, 2.0 * u3 - s.u3);
 }
 
 // Stage 1 at tau_n (predictor) for the ideal (VISC = false) or viscous path;
@@ -1219,11 +1236,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0, Pi1 = 0.0;
   if (q.active) {
     const int c = q.c;
-    const double e = f.e[c], u1 = f.u[0][c], u2 = f.u[1][c], u3 = f.u[2][c];
-    const double ut = utau(u1, u2, u3);
-    double pc[NQ];
+    // e = 0 implies u~ = 0 (the cutoff and the root solve return zero velocity
+    // with zero energy density), and pi~ reads as zero there: no loads
+    const double e = f.e[c];
+    double u1 = 0.0, u2 = 0.0, u3 = 0.0, pc[NQ];
 #pragma unroll
-    for (int m = 0; m < NQ; ++m) pc[m] = VISC ? (e == 0.0 ? 0.0 : f.pi[m][c]) : 0.0;
+    for (int m = 0; m < NQ; ++m) pc[m] = 0.0;
+    if (e != 0.0) {
+      u1 = f.u[0][c];
+      u2 = f.u[1][c];
+      u3 = f.u[2][c];
+      if (VISC) {
+#pragma unroll
+        for (int m = 0; m < NQ; ++m) pc[m] = f.pi[m][c];
+      }
+    }
+    const double ut = utau(u1, u2, u3);
     if (!g.cart) {  // geometric source S_T = (-Tc^{ee}, 0, 0, -Tc^{te})
       double P, cs2;
       eos_p_cs2(eos, e, P, cs2);
@@ -1242,9 +1270,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int m = 0; m < NQ; ++m) R[4 + m] += S[m];
       }
-      const double s1 = 2.0 * u1 - f.up[0][c], s2 = 2.0 * u2 - f.up[1][c],
-                   s3 = 2.0 * u3 - f.up[2][c];
-      const double inv_uts = 1.0 / utau(s1, s2, s3);
+      // u* = 2u^n - u^{n-1}: not needed where pi~' is zero whatever it is
+      bool zero = e == 0.0;
+#pragma unroll
+      for (int m = 0; m < NQ; ++m) zero = zero && R[4 + m] == 0.0;
+      double inv_uts = 1.0;
+      if (!zero) {
+        const double s1 = 2.0 * u1 - f.up[0][c], s2 = 2.0 * u2 - f.up[1][c],
+                     s3 = 2.0 * u3 - f.up[2][c];
+        inv_uts = 1.0 / utau(s1, s2, s3);
+      }
 #pragma unroll
       for (int m = 0; m < NQ; ++m) p1[m] = (ut * pc[m] + p.h * R[4 + m]) * inv_uts;
       regulate<BK>(eos, p, e, p1);
@@ -1302,27 +1337,46 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>())
   if (q.active) {
     const int c = q.c;
     const double e1 = f.e1[c];
+    // where e' = 0 the regulator zeroes pi^{n+1} (vac_zero): nothing to load
+    // unless the quiet-tile test needs this cell's pi~'
+    const bool vz = e1 == 0.0 && p.vac_zero;
     double pc[NQ];
 #pragma unroll
-    for (int m = 0; m < NQ; ++m) pc[m] = f.pi1[m][c];
-    if (e1 >= p.eps_cut) {
-      double S[NQ];
-      pi_source<RT, L1, BK>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
+    for (int m = 0; m < NQ; ++m) pc[m] = 0.0;
+    if (!vz || p.quiet_r[0] > 0) {
 #pragma unroll
-      for (int m = 0; m < NQ; ++m) R[4 + m] += S[m];
+      for (int m = 0; m < NQ; ++m) pc[m] = f.pi1[m][c];
     }
-    const double en = f.e[c];
-    const double a1 = f.u[0][c], a2 = f.u[1][c], a3 = f.u[2][c];
-    const double utn = utau(a1, a2, a3);
-    const double uts = utau(2.0 * a1 - f.up[0][c], 2.0 * a2 - f.up[1][c], 2.0 * a3 - f.up[2][c]);
-    const double inv_ut1 = 1.0 / utau(f.u1[0][c], f.u1[1][c], f.u1[2][c]);
     double pn[NQ];
 #pragma unroll
-    for (int m = 0; m < NQ; ++m) {
-      const double pin = en == 0.0 ? 0.0 : f.pi[m][c];
-      pn[m] = (0.5 * (utn * pin + uts * pc[m]) + 0.5 * p.h * R[4 + m]) * inv_ut1;
+    for (int m = 0; m < NQ; ++m) pn[m] = 0.0;
+    double en = 0.0;
+    if (!vz) {
+      if (e1 >= p.eps_cut) {
+        double S[NQ];
+        pi_source<RT, L1, BK>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
+#pragma unroll
+        for (int m = 0; m < NQ; ++m) R[4 + m] += S[m];
+      }
+      en = f.e[c];
+      const double a1 = f.u[0][c], a2 = f.u[1][c], a3 = f.u[2][c];
+      const double utn = utau(a1, a2, a3);
+      const double uts = utau(2.0 * a1 - f.up[0][c], 2.0 * a2 - f.up[1][c], 2.0 * a3 - f.up[2][c]);
+      const double inv_ut1 = 1.0 / utau(f.u1[0][c], f.u1[1][c], f.u1[2][c]);
+      double pin[NQ];  // pi~^n, zero where e^n = 0
+#pragma unroll
+      for (int m = 0; m < NQ; ++m) pin[m] = 0.0;
+      if (en != 0.0) {
+#pragma unroll
+        for (int m = 0; m < NQ; ++m) pin[m] = f.pi[m][c];
+      }
+#pragma unroll
+      for (int m = 0; m < NQ; ++m)
+        pn[m] = (0.5 * (utn * pin[m] + uts * pc[m]) + 0.5 * p.h * R[4 + m]) * inv_ut1;
+      regulate<BK>(eos, p, e1, pn);
+    } else if (p.quiet_r[0] > 0) {
+      en = f.e[c];
     }
-    regulate<BK>(eos, p, e1, pn);
 #pragma unroll
     for (int m = 0; m < NQ; ++m) st_cell(f.pi[m] + c, pn[m]);
     quiet = en == 0.0 && e1 == 0.0;
@@ -1374,9 +1428,14 @@ __attribute__((amdgpu_waves_per_eu(s2t_waves<RT, TX, TY, TZ, BK>()))) void k_sta
   if (q.active) {
     const int c = q.c;
     const double e1 = f.e1[c], u1 = f.u1[0][c], u2 = f.u1[1][c], u3 = f.u1[2][c];
+    // where e' = 0 the regulator zeroed pi^{n+1} in stage 2pi (vac_zero): no loads
     double pc[NT];
 #pragma unroll
-    for (int m = 0; m < NT; ++m) pc[m] = VISC ? f.pi[m][c] : 0.0;
+    for (int m = 0; m < NT; ++m) pc[m] = 0.0;
+    if (VISC && !(e1 == 0.0 && p.vac_zero)) {
+#pragma unroll
+      for (int m = 0; m < NT; ++m) pc[m] = f.pi[m][c];
+    }
     if constexpr (BK) PiN = pc[10];
     if (!g.cart) {
       double P, cs2;
