@@ -131,7 +131,7 @@ typedef struct ktmi_diagnostics {
 typedef struct ktmi_handle ktmi_handle;
 
 /* Fills d with the defaults: cutoff 1e-7, theta 1.8, tolerance 1e-12, 100
- * iterations, regulator 1.0, FP64, previous-stage guess, automatic tile,
+ * iterations, regulator 0.3, FP64, previous-stage guess, automatic tile,
  * taupi_coef 5, lambda1_hat 0, zetas 0, taubulk_coef 5, baryon 0, cfl_limit
  * 0.5.  Sizes are zero. */
 void ktmi_desc_default(ktmi_desc *d);

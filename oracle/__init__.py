@@ -155,7 +155,7 @@ class Params:
     theta: float = 1.8
     newton_tol: float = 1e-12
     newton_maxit: int = 100
-    pi_reg: float = 1.0
+    pi_reg: float = 0.3
     taupi_coef: float = 5.0
     lambda1_hat: float = 0.0
     zetas: float = 0.0         # zeta/s of the bulk pressure (0: no bulk)

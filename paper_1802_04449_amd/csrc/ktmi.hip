@@ -635,7 +635,7 @@ void ktmi_desc_default(ktmi_desc* d) {
   d->theta = 1.8;
   d->newton_tol = 1e-12;
   d->newton_maxit = 100;
-  d->pi_reg = 1.0;
+  d->pi_reg = 0.3;
   d->precision = KTMI_FP64;
   d->guess = KTMI_GUESS_PREV;
   d->tile = -1;
