@@ -350,6 +350,20 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
     return (R)p.c_vac;
   }
   const R th = (R)p.theta;
+  // the pi~ components the face needs; the first one's loads go out with u~'s
+  auto needed = [&](int m) {
+    if (m == 10 || PI_SRC == 0) return false;  // Pi: with e and u~ below
+    bool inT = false;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) inT = inT || m == sym(0, nu) || m == sym(axis, nu);
+    return DO_PI || (DO_T && inT);
+  };
+  auto next_needed = [&](int m) {
+    int k = m + 1;
+    while (k < NQ && !needed(k)) ++k;
+    return k;
+  };
+  double pcur[4], pnext[4];
   // e and u~ face states (and Pi's, which T~'s pressure needs)
   constexpr int NV = BK ? 5 : 4;
   R fL[NV], fR[NV];
@@ -361,6 +375,13 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
     for (int m = 0; m < 3; ++m)
 #pragma unroll
       for (int t = 0; t < 4; ++t) q4[1 + m][t] = (R)u[m][idx[t]];
+    {
+      const int m0 = next_needed(-1);
+      if (m0 < NQ) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pcur[t] = pi[m0][idx[t]];
+      }
+    }
     if constexpr (BK) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) q4[4][t] = (R)ld_pi<PI_SRC>(pi, 10, idx[t], ev[t]);
@@ -400,21 +421,23 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
       out[14 * F] = R(0.5) * (FL + FR) - R(0.5) * c * (QR - QL);
     }
   }
-  // pi~ components (and n), one at a time
+  // pi~ components (and n), one at a time; the next needed component's loads
+  // are issued before the current one is used, so one round trip to the cache
+  // overlaps the arithmetic of the previous component
 #pragma unroll
   for (int m = 0; m < NQ; ++m) {
-    if (m == 10) continue;  // Pi: done above
-    bool inT = false;
-#pragma unroll
-    for (int nu = 0; nu < 4; ++nu) inT = inT || m == sym(0, nu) || m == sym(axis, nu);
-    const bool need = PI_SRC != 0 && (DO_PI || (DO_T && inT));
-    if (!need) {  // no pi~ (ideal), or a component T~'s flux does not use
-      if (DO_PI) out[(4 + m) * F] = R(0);
+    if (!needed(m)) {  // no pi~ (ideal), Pi, or a component T~'s flux does not use
+      if (DO_PI && m != 10) out[(4 + m) * F] = R(0);
       continue;
+    }
+    const int mn = next_needed(m);
+    if (mn < NQ) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) pnext[t] = pi[mn][idx[t]];
     }
     R p4[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) p4[t] = (R)ld_pi<PI_SRC>(pi, m, idx[t], ev[t]);
+    for (int t = 0; t < 4; ++t) p4[t] = (R)(PI_SRC == 1 && ev[t] == 0.0 ? 0.0 : pcur[t]);
     const R pL = p4[1] + R(0.5) * mm_slope_r<R>(th, p4[0], p4[1], p4[2]);
     const R pR = p4[2] - R(0.5) * mm_slope_r<R>(th, p4[1], p4[2], p4[3]);
     if (DO_PI) {
@@ -435,6 +458,8 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
         }
       }
     }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) pcur[t] = pnext[t];
   }
 #pragma unroll
   for (int nu = 0; nu < 4; ++nu) {
