@@ -277,22 +277,25 @@ def minijet_deposit(g: Grid, seed: int, n_jets: int = 400, mean_pt: float = 2.0,
     phi = 2.0 * math.pi * rng.random(n_jets)
     etak = rng.uniform(-eta_range, eta_range, n_jets) if g.ne > 1 else np.zeros(n_jets)
     x, y, e = g.axes()
-    out = np.zeros((4,) + g.shape)
     vol = g.dx * g.dy * g.de
-    for k in range(n_jets):
-        gx = np.exp(-(x - xy[k, 0]) ** 2 / (2.0 * sigma_r ** 2))
-        gy = np.exp(-(y - xy[k, 1]) ** 2 / (2.0 * sigma_r ** 2))
-        ge = np.exp(-(e - etak[k]) ** 2 / (2.0 * sigma_eta ** 2)) if g.ne > 1 else np.ones(1)
-        G = gx[:, None, None] * gy[None, :, None] * ge[None, None, :]
-        norm = G.sum() * vol
-        if norm <= 0.0:
-            continue
-        G /= norm
-        dy_ = etak[k] - e
-        out[0] += pt[k] * G * np.cosh(dy_)[None, None, :]
-        out[1] += pt[k] * math.cos(phi[k]) * G
-        out[2] += pt[k] * math.sin(phi[k]) * G
-        out[3] += pt[k] * G * np.sinh(dy_)[None, None, :]
+    # each parton's profile is separable, gx(x) gy(y) ge(eta): the deposits of all
+    # partons are one contraction over the parton index, (x y) x partons times
+    # partons x eta, for each component
+    gx = np.exp(-(x[None, :] - xy[:, :1]) ** 2 / (2.0 * sigma_r ** 2))      # (n_jets, nx)
+    gy = np.exp(-(y[None, :] - xy[:, 1:2]) ** 2 / (2.0 * sigma_r ** 2))     # (n_jets, ny)
+    if g.ne > 1:
+        ge = np.exp(-(e[None, :] - etak[:, None]) ** 2 / (2.0 * sigma_eta ** 2))  # (n_jets, ne)
+    else:
+        ge = np.ones((n_jets, 1))
+    norm = gx.sum(axis=1) * gy.sum(axis=1) * ge.sum(axis=1) * vol
+    w = np.where(norm > 0.0, pt / np.where(norm > 0.0, norm, 1.0), 0.0)
+    dy_ = etak[:, None] - e[None, :]                                          # (n_jets, ne)
+    B = np.stack([w[:, None] * ge * np.cosh(dy_), (w * np.cos(phi))[:, None] * ge,
+                  (w * np.sin(phi))[:, None] * ge, w[:, None] * ge * np.sinh(dy_)])
+    A = (gx[:, :, None] * gy[:, None, :]).reshape(n_jets, g.nx * g.ny)        # (n_jets, nx ny)
+    out = np.empty((4,) + g.shape)
+    for c in range(4):
+        out[c] = (A.T @ B[c]).reshape(g.shape)
     return out
 
 
