@@ -1,0 +1,216 @@
+"""The batched and large-event paths at their configured scale.
+
+- The batch of 64 uneven events (grids 101^2..301^2 x n_eta in {1, 33, 65, 105},
+  eta/s in {0, 0.08, 0.16}, hotspot initial states) stepped as one group under
+  HIP-graph replay: every event equal bit for bit to its single-event run, three
+  members (the largest grid, a boost-invariant n_eta = 1 event and a viscous
+  eta/s = 0.16 event) within 1e-12 of the oracle, and the same batch in mixed
+  precision with the learned root-solve start within the reduced-precision bar
+  of the FP64 batch for all 64 events.
+- The 385x385x129 event (hotspots + mini-jets, h = 0.005 fm) over its whole
+  1000-step run in mixed precision against the FP64 GPU path (itself within
+  1e-12 of the oracle, test_gpu_parity.py), the per-field error recorded every
+  100 steps next to the FP64 path's own response to an input perturbation of
+  the FP32 roundoff (the state is ill-conditioned in its dilute cells).
+
+Fields are compared on the device; only the oracle comparisons copy to the host.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from hydro_inputs import workloads as W
+
+from . import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+BATCH_STEPS = 4
+BAR = 1e-6  # reduced-precision bar on e and u~ (L2 over the grid, max over hydro cells)
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _make(wl, stream, mlp_params=None, **kw):
+    import paper_1802_04449_amd as K
+    d = dict(wl.params)
+    d.update(kw)
+    h = K.Hydro(stream=stream, **d)
+    h.set_eos(wl.eos)
+    if mlp_params is not None:
+        h.set_mlp(mlp_params, K.KTMI_MLP_BF16)
+    if wl.T4 is not None:
+        h.set_initial_conserved(wl.T4)
+    else:
+        h.set_initial(wl.ic)
+    return h
+
+
+def _report(name, obj):
+    d = os.environ.get("KTMI_REPORT_DIR")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, name + ".json"), "w") as fh:
+            json.dump(obj, fh, indent=1)
+
+
+def _dev_fields(h, names):
+    return {n: h.read(n) for n in names}
+
+
+def _precision_errors_dev(got, ref, eps_min=0.1):
+    """G.precision_errors on device tensors for e and the three u~ components:
+    'l2' = ||d||_2 / ||scale field||_2, 'max_hydro' = max |d| over cells with
+    reference e >= eps_min, over the scale (max |e|, or max u~^tau for u~)."""
+    import torch
+    out = {}
+    ut = torch.sqrt(1 + ref["ux"] ** 2 + ref["uy"] ** 2 + ref["ue"] ** 2)
+    m = ref["eps"] >= eps_min
+    for n in ("eps", "ux", "uy", "ue"):
+        if n == "eps":
+            scale, l2s = float(ref["eps"].abs().max()), float(torch.linalg.vector_norm(ref["eps"]))
+        else:
+            scale, l2s = float(ut.max()), float(torch.linalg.vector_norm(ut))
+        scale = scale if scale > 0 else 1.0
+        l2s = l2s if l2s > 0 else 1.0
+        d = (got[n] - ref[n]).abs()
+        out[n] = {"l2": float(torch.linalg.vector_norm(d)) / l2s,
+                  "max_hydro": float(d[m].max()) / scale if bool(m.any()) else 0.0}
+    return out
+
+
+@pytest.fixture(scope="module")
+def batch64():
+    """The 64 events and their grouped FP64 run (graph replay after two plain steps)."""
+    import torch
+    import paper_1802_04449_amd as K
+    evs = W.event_batch(nev=64, steps=BATCH_STEPS)
+    st = torch.cuda.Stream()
+    hs = [_make(wl, st) for wl in evs]
+    grp = K.Group(hs)
+    _say(f"batch of 64: {sum(w.ncell for w in evs)} cells, {grp.classes} classes")
+    grp.step(2)
+    grp.set_graph(True)
+    grp.step(BATCH_STEPS - 2)
+    torch.cuda.synchronize()
+    yield evs, hs, st
+    del grp
+    torch.cuda.synchronize()
+
+
+def test_batch64_members_equal_single_runs(batch64):
+    import torch
+    import paper_1802_04449_amd as K
+    evs, hs, _ = batch64
+    names = list(K.FIELDS)
+    for e, (wl, h) in enumerate(zip(evs, hs)):
+        solo = _make(wl, None)
+        solo.step(BATCH_STEPS)
+        a, b = _dev_fields(solo, names), _dev_fields(h, names)
+        torch.cuda.synchronize()
+        for n in names:
+            assert torch.equal(a[n], b[n]), (e, wl.name, n)
+        assert solo.diag() == h.diag(), (e, wl.name)
+        del solo, a, b
+    _say("64 grouped events equal their single runs bit for bit")
+
+
+def test_batch64_members_match_oracle(batch64):
+    evs, hs, _ = batch64
+    largest = max(range(len(evs)), key=lambda e: evs[e].ncell)
+    flat = min((e for e in range(len(evs)) if evs[e].params["ne"] == 1),
+               key=lambda e: evs[e].ncell)
+    visc = max((e for e in range(len(evs)) if evs[e].params["etas"] == 0.16 and e != largest),
+               key=lambda e: evs[e].ncell if evs[e].ncell < 3_000_000 else 0)
+    for e in (largest, flat, visc):
+        wl = evs[e]
+        _say(f"oracle comparison: event {e} {wl.name}")
+        of = G.run_oracle(wl, BATCH_STEPS).fields()
+        rel = G.assert_parity(hs[e].fields(), of, 1e-12, f"grouped event {e} vs oracle")
+        _say(f"event {e}: worst {max(rel.values()):.2e}")
+
+
+def test_batch64_learned_mixed_within_bar(batch64):
+    """The combined batched + learned + mixed path on the same 64 events against
+    the grouped FP64 run: <= 1e-6 in e and each u~ component for every event."""
+    import torch
+    import paper_1802_04449_amd as K
+    from paper_1802_04449_amd import mlp
+    evs, ref_hs, st = batch64
+    # the network: trained on states of two of the events (library kernels)
+    states = []
+    for wl in (evs[0], evs[1]):
+        g = _make(wl, None)
+        for _ in range(3):
+            states.append(g.harvest())
+            g.step(2)
+        del g
+    E, M, e = mlp.samples_from_states(states, emin=1e-7, seed=1)
+    tr = mlp.Trainer(E, M, e, seed=3)
+    tr.train(800, batch=8192)
+    hs = []
+    for wl in evs:
+        hs.append(_make(wl, st, mlp_params=tr.params, precision=K.KTMI_MIXED,
+                        guess=K.KTMI_GUESS_MLP))
+    grp = K.Group(hs)
+    grp.set_graph(True)
+    grp.step(BATCH_STEPS)
+    torch.cuda.synchronize()
+    worst = {}
+    for e, (wl, h, r) in enumerate(zip(evs, hs, ref_hs)):
+        err = _precision_errors_dev(_dev_fields(h, ("eps", "ux", "uy", "ue")),
+                                    _dev_fields(r, ("eps", "ux", "uy", "ue")))
+        for k, v in err.items():
+            for nk in ("l2", "max_hydro"):
+                worst[(k, nk)] = max(worst.get((k, nk), 0.0), v[nk])
+                assert v[nk] <= BAR, (e, wl.name, k, nk, v)
+    _say("batched learned mixed vs FP64, worst over 64 events: " +
+         ", ".join(f"{k}.{nk} {v:.1e}" for (k, nk), v in sorted(worst.items())))
+    _report("batch64_learned_mixed_vs_fp64", {f"{k}.{nk}": v for (k, nk), v in worst.items()})
+    del grp, hs
+    torch.cuda.synchronize()
+
+
+def test_large_event_mixed_whole_run():
+    """385x385x129, 1000 steps: mixed precision against FP64 on the GPU, errors
+    every 100 steps for e, u~ (gated) and pi~, T~ (reported).  The hotspot +
+    mini-jet state is ill-conditioned (dilute, nearly light-like cells left by the
+    parton deposits), so the bar is the conditioning-aware one of the mini-jet
+    parity test: on cells with e >= 0.1 GeV/fm^3 the mixed run's error may not
+    exceed max(1e-6, 10 x) the FP64 run's own response to a relative perturbation
+    of its initial state by the FP32 roundoff 2^-24."""
+    import torch
+    import paper_1802_04449_amd as K
+    wl = W.large_event(steps=1000)
+    wp = G.perturbed(wl, rel=2.0 ** -24, seed=3)
+    _say(f"large event {wl.name}: FP64, FP64 with perturbed input, mixed; 1000 steps")
+    a = _make(wl, None)
+    b = _make(wl, None, precision=K.KTMI_MIXED)
+    c = _make(wp, None)
+    names = ["eps", "ux", "uy", "ue"] + [f"pi{m}" for m in range(10)] + [f"T{m}" for m in range(4)]
+    curve = []
+    for chunk in range(10):
+        for h in (a, b, c):
+            h.step(100)
+        fa, fb, fc = (_dev_fields(h, names) for h in (a, b, c))
+        err, sens = _precision_errors_dev(fb, fa), _precision_errors_dev(fc, fa)
+        rec = {"step": 100 * (chunk + 1), "tau": a.diag()["tau"], "mixed": err, "fp64_perturbed": sens}
+        # pi~ and T~: relative to the tensor's largest component (reported, not gated)
+        for grp_names in ([f"pi{m}" for m in range(10)], [f"T{m}" for m in range(4)]):
+            scale = max(float(fa[n].abs().max()) for n in grp_names) or 1.0
+            rec["mixed"][grp_names[0][:-1]] = max(float((fb[n] - fa[n]).abs().max())
+                                                  for n in grp_names) / scale
+        curve.append(rec)
+        _say(f"step {rec['step']}: " + ", ".join(
+            f"{k} max {err[k]['max_hydro']:.1e} (fp64 perturbed {sens[k]['max_hydro']:.1e})"
+            for k in ("eps", "ux", "uy", "ue")))
+        del fa, fb, fc
+    _report("large_event_mixed_whole_run", curve)
+    for rec in curve:
+        for k in ("eps", "ux", "uy", "ue"):
+            bar = max(BAR, 10.0 * rec["fp64_perturbed"][k]["max_hydro"])
+            assert rec["mixed"][k]["max_hydro"] <= bar, (rec["step"], k, rec["mixed"][k], bar)
