@@ -1,30 +1,43 @@
 """Benchmark: cell-updates/s of the viscous KT + RK2 step on one MI355X.
 
-Workload (default): viscous hydro, eta/s = 0.08, 201 x 201 x 105 cells
+Headline workload: viscous hydro, eta/s = 0.08, 201 x 201 x 105 cells
 (dx = dy = 0.16 fm, deta = 0.3), tau0 = 0.6 fm, h = 0.01 fm, 200 seeded Gaussian
-hotspots, 1555-row synthetic EoS, FP64.  A step is one full RK2 step (all three
-stencil passes, both root solves, the diagnostics reduction) over the grid.
+hotspots, 1555-row synthetic EoS, FP64, the full 200-step run.  A step is one
+full RK2 step (all three stencil passes, both root solves, the diagnostics
+reduction) over the grid.  The timed region is `--steps` steps of ktmi_step from
+the initial state (set before the region, inputs resident on the GPU), without
+instrumentation, repeated `--reps` times; `value` is the median.  `--warmup`
+steps run once, untimed, before the first repetition.
 
-Prints one JSON line.  `roofline` is measured live for the dominant kernel with
-HIP events recorded on the library's stream around every launch in the timed
-region; `cpu_baseline` times the CPU oracle on a bounded sample of the same
-workload (rank 0, N = 1 only).  `paths` times the other paths on the same grid:
-mixed precision, quiet-tile skipping, the freeze-out surface finder, the
-Cooper-Frye spectra, the lambda_1 term, bulk pressure with baryon density, and a
-grouped batch of 64 events with the learned root-solve guess.
+Prints one JSON line.  `roofline` comes from a separate run of the same steps
+with the library's HIP events around every launch (on the library's stream):
+the dominant kernel's algorithmic bytes per launch over its average duration,
+against 8 TB/s; its VALU-issue ceiling uses the wave-VALU instruction count
+recorded by rocprofv3 (profiles/traffic.json) while the kernel sources match.
+`paths` times the other configurations the same way: the ideal Gubser grid
+33x33x17 (50 steps), the benchmark grid in mixed precision, with quiet tiles
+skipped, with the lambda_1 term, with bulk pressure and baryon density, the
+mini-jet initial state with and without the learned root-solve guess, a batch of
+64 uneven events in four forms (FP64 or mixed, with or without the network)
+under HIP-graph replay with autotuned tiles, the 385x385x129 event in FP64 and
+mixed precision, the freeze-out surface finder and the Cooper-Frye spectra.
+`cpu_baseline` times the CPU oracle on a bounded sample of the headline workload
+at one thread and at all host threads.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
+VALU_WAVE_INSTS_PER_S = 256 * 2.4e9  # one wave64 VALU instruction per CU per clock (4 SIMDs x 16 lanes)
 
 # Algorithmic HBM bytes per cell for each kernel of the FP64 viscous step: every
 # field a kernel reads or writes, counted once per cell (stencil reuse assumed
@@ -40,12 +53,16 @@ BYTES_PER_CELL_IDEAL = {"stage1": (8 + 5) * 8, "stage2_T": (8 + 4) * 8}
 # stage2_T reads Pi^{n+1} (+1).
 BYTES_PER_CELL_BULK = {"stage1": (23 + 20) * 8, "stage2_pi": (35 + 12) * 8,
                        "stage2_T": (23 + 8) * 8}
+# The step's minimum: the state read once and written once, and the stage-1
+# prediction written once and read once (21 + 18 + 18 + 18 values, u~prev rotated
+# by pointer): 600 B per cell-update in FP64.
+STEP_BYTES_PER_CELL = 600
 
 
 def source_sha256() -> str:
     """Hash of everything the step's stencil kernels are compiled from (their
     sources, the headers they include and the build flags): counter-derived
-    traffic recorded under profiles/ is used only while it matches the code
+    figures recorded under profiles/ are used only while they match the code
     being timed."""
     import hashlib
     pkg = os.path.join(ROOT, "paper_1802_04449_amd")
@@ -61,10 +78,10 @@ def source_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of `kernel` on `workload` from rocprofv3 FETCH_SIZE and
-    WRITE_SIZE (calibrated against a plain copy), or None when no record exists
-    for the current kernel sources."""
+def recorded(workload: str, kernel: str):
+    """rocprofv3 record of `kernel` on `workload` for the current kernel sources:
+    HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated against a plain
+    copy) and wave-VALU instructions per launch, or None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -73,238 +90,274 @@ def measured_traffic(workload: str, kernel: str):
         return None
     if rec.get("source_sha256") != source_sha256():
         return None
-    r = rec.get("bytes_per_launch", {}).get(workload, {}).get(kernel)
-    return None if r is None else r["fetch_bytes"] + r["write_bytes"]
+    return rec.get("per_launch", {}).get(workload, {}).get(kernel)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--workload", default="hotspots",
-                    choices=["hotspots", "gubser_dense", "large", "batch64", "bulk"],
-                    help="hotspots: the benchmark configuration; gubser_dense: the same grid and "
-                         "physics with a smooth Gubser profile that leaves no vacuum cells; large: "
-                         "385x385x129 single event; batch64: 64 uneven events in grouped launches; "
-                         "bulk: the benchmark configuration with bulk pressure and baryon density")
-    ap.add_argument("--graph", action="store_true", help="replay each step as a HIP graph")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time every tile shape first (on a discarded run) and use the fastest")
-    ap.add_argument("--tile", type=int, default=-1, help="tile shape index (-1: library default)")
-    ap.add_argument("--precision", type=int, default=0,
-                    help="0: plain FP64; 1: mixed (FP32 flux/relaxation, FP64 root solve and sources)")
-    ap.add_argument("--quiet-skip", action="store_true",
-                    help="skip tiles whose neighbourhood stayed vacuum (bitwise identical results)")
-    ap.add_argument("--guess", default="prev", choices=["prev", "mlp"],
-                    help="root-solve start: previous stage, or a network trained first on states "
-                         "harvested from the same workload (GPU training kernels)")
-    ap.add_argument("--no-paths", action="store_true",
-                    help="skip the extra measurements: the same workload in mixed precision, and "
-                         "the 64-event batch with mixed precision and the learned guess")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain device copy of 1 GiB five times (counter calibration)")
-    ap.add_argument("--only-surface", action="store_true",
-                    help="only measure the freeze-out surface finder on the workload (profiling)")
-    ap.add_argument("--only-spectra", action="store_true",
-                    help="only measure the Cooper-Frye spectra on the workload's surface (profiling)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build.", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import paper_1802_04449_amd as K
-    from hydro_inputs import workloads as W
-
-    if args.workload == "batch64":
-        print(json.dumps(bench_batch(args, learned=args.guess == "mlp")), flush=True)
-        return
-    wl = {"hotspots": W.hotspots_viscous, "gubser_dense": W.gubser_dense_viscous,
-          "large": W.large_event, "bulk": W.hotspots_bulk}[args.workload](steps=args.steps)
-    if args.only_surface:
-        print(json.dumps({"workload": wl.name, "freezeout_surface": surface_path(wl)}), flush=True)
-        return
-    if args.only_spectra:
-        print(json.dumps({"workload": wl.name, "cooper_frye_spectra": spectra_path(wl)}), flush=True)
-        return
-    p = wl.params
-    stream = torch.cuda.Stream() if args.graph else None
-    train = None
-    if args.guess == "mlp":
-        params, train = train_guess([wl])
-    g = K.Hydro(tile=args.tile, precision=args.precision, stream=stream,
-                guess=K.KTMI_GUESS_MLP if args.guess == "mlp" else K.KTMI_GUESS_PREV, **p)
-    g.set_eos(wl.eos)
-    if args.guess == "mlp":
-        g.set_mlp(params, K.KTMI_MLP_BF16)
-    if args.quiet_skip:
-        g.set_quiet_skip(True)
-
-    def initial():
-        if wl.T4 is not None:
-            g.set_initial_conserved(wl.T4)
-        else:
-            g.set_initial(wl.ic)
-
-    tile_times = None
-    if args.autotune:
-        # tune on a throwaway copy of the state, then start the measured run afresh
-        from paper_1802_04449_amd import autotune
-        initial()
-        tile, tile_times = autotune.tune(g, steps=3, use_cache=False)
-    initial()
-    if args.graph:
-        g.set_graph(True)
-    g.step(args.warmup)
-    torch.cuda.synchronize()
-
-    K.ktmi_set_timing(g.h, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    names = K.ktmi_kernel_names()
-    per_kernel = {}
-    for k, n in enumerate(names):
-        tot, cnt = K.ktmi_timing(g.h, k)
-        if cnt:
-            per_kernel[n] = dict(total_ms=tot, launches=cnt, avg_ms=tot / cnt)
-    K.ktmi_set_timing(g.h, False)
-    diag = g.diag()
-
-    dt = t1 - t0
-    ncell = wl.ncell
-    value = ncell * args.steps / dt
-    dom = max(per_kernel, key=lambda n: per_kernel[n]["total_ms"])
-    bpc = BYTES_PER_CELL if p["viscous"] else BYTES_PER_CELL_IDEAL
-    if p.get("zetas", 0) > 0 or p.get("baryon", 0):
-        bpc = dict(BYTES_PER_CELL, **BYTES_PER_CELL_BULK)
-    bytes_launch = bpc[dom] * ncell
-    achieved = bytes_launch / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
-    step_bytes = sum(bpc.get(n, 0) * ncell * per_kernel[n]["launches"] for n in per_kernel)
-    out = {
-        "metric": "cell-updates/s of viscous KT+RK2 step, plain FP64 vs batched/learned/FP32 @1e-6",
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "nx": p["nx"], "ny": p["ny"], "ne": p["ne"],
-                   "dx": p["dx"], "deta": p["de"], "tau0": p["tau0"], "h": p["h"],
-                   "eta_over_s": p["etas"], "ic": wl.note or "200 Gaussian hotspots, seed 1",
-                   "eos": "1555-row synthetic crossover table",
-                   "path": ("plain FP64" if args.precision == 0 else "mixed FP32/FP64") +
-                           (", quiet tiles skipped" if args.quiet_skip else "") +
-                           (", learned guess (BF16 forward)" if args.guess == "mlp" else "")},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic(wl.name, dom) if args.precision == 0 else None),
-                     "algorithmic_bytes": bytes_launch, "bytes_per_cell": bpc[dom],
-                     "avg_launch_ms": per_kernel[dom]["avg_ms"]},
-        "kernels": {n: round(v["avg_ms"], 4) for n, v in per_kernel.items()},
-        "tile": list(K.ktmi_tile_shape(K.ktmi_get_tile(g.h))),
-        "tile_ms_per_step": ({str(K.ktmi_tile_shape(t)): round(v, 3) for t, v in tile_times.items()}
-                             if tile_times else None),
-        "step_hbm_GBs_algorithmic": step_bytes / dt / 1e9,
-        "diag": {k: diag[k] for k in ("tau", "eps_max", "newton_mean", "newton_max", "clamps",
-                                      "nonconv", "nans", "vacuum")},
-        "context": {"paper_table_II_viscous_gpu_cell_updates_per_s": 1.69e7,
-                    "paper_hardware": "AMD FirePro S9150, 385x385x115 cells"},
-    }
-    out["graph"] = bool(args.graph)
-    if train:
-        out["training"] = train
-    if args.precision == 0 and not args.no_paths and args.guess == "prev" and not args.quiet_skip:
-        del g
-        torch.cuda.synchronize()
-        out["paths"] = {"mixed_fp32_fp64": mixed_path(wl, args)}
-        out["paths"]["fp64_quiet_skip"] = mixed_path(wl, args, precision=0, quiet=True)
-        out["paths"]["freezeout_surface"] = surface_path(wl)
-        out["paths"]["cooper_frye_spectra"] = spectra_path(wl)
-        out["paths"]["fp64_lambda1"] = mixed_path(wl, args, precision=0, lambda1_hat=-10.0)
-        out["paths"]["fp64_lambda1"]["note"] = ("second-order lambda_1 term on, lambda1_hat = -10, "
-                                                "tau_pi = 5 eta/(sT)")
-        if wl.name.startswith("hotspots_viscous"):
-            pw = wl.params
-            wb = W.hotspots_bulk(nx=pw["nx"], ny=pw["ny"], ne=pw["ne"], dx=pw["dx"], dy=pw["dy"],
-                                 de=pw["de"])
-            out["paths"]["fp64_bulk_baryon"] = mixed_path(wb, args, precision=0,
-                                                          bytes_per_cell=BYTES_PER_CELL_BULK)
-            out["paths"]["fp64_bulk_baryon"]["note"] = (
-                "bulk pressure (zeta/s = 0.04, tau_Pi = 5 (zeta/s) hbarc/T) and net-baryon "
-                "density transported (16 components per face)")
-        b = bench_batch(args, precision=1, learned=True, steps=10, warmup=2)
-        out["paths"]["batch64_mixed_learned"] = {
-            k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "newton_mean", "training")}
-        out["paths"]["batch64_mixed_learned"]["cells"] = b["config"]["cells"]
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
-    print(json.dumps(out), flush=True)
+def say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def mixed_path(wl, args, precision=1, quiet=False, bytes_per_cell=None, **extra):
-    """The same workload with FP32 reconstruction, fluxes and relaxation source
-    (FP64 root solve, geometric source and state; errors against the FP64
-    oracle are bounded by the GPU tests, <= 1e-6 in e and u~), or (precision 0,
-    quiet) in FP64 with quiet tiles skipped (fields and diagnostics identical to
-    the full computation bit for bit, tested).  `extra` overrides descriptor
-    fields (the second-order path sets lambda1_hat).  With bytes_per_cell the
-    timed steps also record each pass's average duration (HIP events on the
-    library's stream) and its algorithmic HBM rate."""
-    import torch
+# ---------------------------------------------------------------------------
+# Timing helpers
+# ---------------------------------------------------------------------------
 
+def make_hydro(wl, stream=None, **over):
     import paper_1802_04449_amd as K
     d = dict(wl.params)
-    d.update(extra)
-    g = K.Hydro(precision=precision, **d)
+    d.update(over)
+    g = K.Hydro(stream=stream, **d)
     g.set_eos(wl.eos)
-    if quiet:
-        g.set_quiet_skip(True)
+    return g
+
+
+def reset(g, wl):
     if wl.T4 is not None:
         g.set_initial_conserved(wl.T4)
     else:
         g.set_initial(wl.ic)
-    g.step(args.warmup)
-    torch.cuda.synchronize()
-    if bytes_per_cell:
-        K.ktmi_set_timing(g.h, True)
+
+
+def timed_runs(g, wl, steps, reps, warmup=0, step_fn=None, reset_fn=None):
+    """`reps` runs of `steps` steps from the initial state (reset before each,
+    outside the timed region), uninstrumented; `warmup` steps run once before.
+    Returns the wall times in seconds."""
+    import torch
+    step_fn = step_fn or g.step
+    reset_fn = reset_fn or (lambda: reset(g, wl))
+    if warmup:
+        reset_fn()
+        step_fn(warmup)
         torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g.step(args.steps)
+    ts = []
+    for _ in range(reps):
+        reset_fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step_fn(steps)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return ts
+
+
+def kernel_times(g, wl, steps):
+    """One instrumented run of `steps` steps from the initial state: per kernel
+    total, launches and average duration (HIP events on the library's stream)."""
+    import torch
+
+    import paper_1802_04449_amd as K
+    reset(g, wl)
+    K.ktmi_set_timing(g.h, True)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out = {"value": wl.ncell * args.steps / dt, "unit": "cell-updates/s",
-           "ms_per_step": dt / args.steps * 1e3, "steps": args.steps}
-    if bytes_per_cell:
-        kern = {}
-        for k, n in enumerate(K.ktmi_kernel_names()):
-            tot, cnt = K.ktmi_timing(g.h, k)
-            if cnt and n in bytes_per_cell:
-                ms = tot / cnt
-                gbs = bytes_per_cell[n] * wl.ncell / (ms * 1e-3) / 1e9
-                kern[n] = {"avg_launch_ms": round(ms, 4), "achieved_GBs": round(gbs, 1),
-                           "frac": round(gbs / HBM_PEAK_GBS, 4),
-                           "bytes_per_cell": bytes_per_cell[n]}
-        K.ktmi_set_timing(g.h, False)
-        out["kernels"] = kern
+    g.step(steps)
+    torch.cuda.synchronize()
+    out = {}
+    for k, n in enumerate(K.ktmi_kernel_names()):
+        tot, cnt = K.ktmi_timing(g.h, k)
+        if cnt:
+            out[n] = dict(total_ms=tot, launches=cnt, avg_ms=tot / cnt)
+    K.ktmi_set_timing(g.h, False)
+    return out
+
+
+def rate(ncell, steps, ts):
+    med = statistics.median(ts)
+    return {"value": ncell * steps / med, "unit": "cell-updates/s", "steps": steps,
+            "ms_per_step": med / steps * 1e3, "reps_s": [round(t, 5) for t in ts]}
+
+
+def roofline_of(wl, per_kernel, bpc):
+    """HBM roofline of the dominant kernel, the whole step's algorithmic rate, and
+    the VALU-issue ceiling (wave-VALU instructions / (256 CUs x clock)) where the
+    instruction count is on record for the current sources."""
+    ncell = wl.ncell
+    dom = max((n for n in per_kernel if n in bpc and bpc[n]),
+              key=lambda n: per_kernel[n]["total_ms"])
+    avg = per_kernel[dom]["avg_ms"]
+    bytes_launch = bpc[dom] * ncell
+    achieved = bytes_launch / (avg * 1e-3) / 1e9
+    rec = recorded(wl.name, dom)
+    out = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "traffic": None if rec is None else rec["fetch_bytes"] + rec["write_bytes"],
+           "algorithmic_bytes": bytes_launch, "bytes_per_cell": bpc[dom], "avg_launch_ms": avg}
+    if rec is not None and rec.get("valu_insts"):
+        t_issue = rec["valu_insts"] / VALU_WAVE_INSTS_PER_S
+        out["valu_issue"] = {"wave_insts": rec["valu_insts"], "ceiling_ms": t_issue * 1e3,
+                             "frac": t_issue / (avg * 1e-3)}
+    steps = max(v["launches"] for n, v in per_kernel.items() if n in bpc)
+    step_ms = sum(v["total_ms"] for v in per_kernel.values()) / steps
+    out["step"] = {"ms": step_ms,
+                   "frac_600B": STEP_BYTES_PER_CELL * ncell / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   "frac_kernels": sum(bpc.get(n, 0) * ncell * v["launches"]
+                                       for n, v in per_kernel.items()) / steps /
+                                   (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
+def kernels_summary(per_kernel, wl, bpc):
+    out = {}
+    for n, v in per_kernel.items():
+        r = {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"]}
+        if bpc.get(n):
+            gbs = bpc[n] * wl.ncell / (v["avg_ms"] * 1e-3) / 1e9
+            r["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+        out[n] = r
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Paths
+# ---------------------------------------------------------------------------
+
+def single_path(wl, steps, reps, warmup=2, bpc=None, quiet=False, graph=False, stream=None,
+                **over):
+    """`wl` stepped alone: median of `reps` uninstrumented runs of `steps` steps
+    from the initial state; per-kernel times from one instrumented run when bpc
+    is given."""
+    import torch
+    st = stream if stream is not None else (torch.cuda.Stream() if graph else None)
+    g = make_hydro(wl, stream=st, **over)
     if quiet:
+        g.set_quiet_skip(True)
+    if graph:
+        g.set_graph(True)
+    ts = timed_runs(g, wl, steps, reps, warmup)
+    out = rate(wl.ncell, steps, ts)
+    d = g.diag()
+    out["newton_mean"] = d["newton_mean"]
+    if quiet:
+        import paper_1802_04449_amd as K
         out["quiet_tiles"], out["tiles"] = K.ktmi_quiet_tiles(g.h)
+    if bpc:
+        pk = kernel_times(g, wl, steps)
+        out["kernels"] = kernels_summary(pk, wl, bpc)
+    del g
+    torch.cuda.synchronize()
+    return out
+
+
+def harvest_samples(wls, at_steps, cap=None, seed=1):
+    """(E, M, e) of every non-vacuum cell of FP64 runs of `wls` at the given steps
+    (ktmi_harvest), shuffled; at most `cap` samples."""
+    from paper_1802_04449_amd import mlp
+    states = []
+    for wl in wls:
+        g = make_hydro(wl)
+        reset(g, wl)
+        done = 0
+        for t in at_steps:
+            g.step(t - done)
+            done = t
+            states.append(g.harvest())
+        del g
+    E, M, e = mlp.samples_from_states(states, emin=1e-7, seed=seed)
+    if cap is not None and E.size > cap:
+        E, M, e = E[:cap], M[:cap], e[:cap]
+    return E, M, e
+
+
+def train_guess(E, M, e, train_steps=3000, batch=8192):
+    """The learned root-solve guess trained on the GPU (library kernels)."""
+    from paper_1802_04449_amd import mlp
+    tr = mlp.Trainer(E, M, e, seed=3)
+    loss0 = tr.loss()
+    t0 = time.perf_counter()
+    tr.train(train_steps, batch=batch)
+    dt = time.perf_counter() - t0
+    return tr.params, {"samples": int(E.size), "adam_steps": train_steps, "batch": batch,
+                       "loss_initial": loss0, "loss_final": tr.loss(), "train_s": dt}
+
+
+def minijet_path(params, train, steps, reps):
+    """The mini-jet initial state on the benchmark grid, FP64, with the previous-
+    stage start and with the learned start (BF16 matrix-core forward): the same
+    run both ways; the fields agree to the FP64 bar (tested), the iteration
+    counts and times differ."""
+    import torch
+
+    import paper_1802_04449_amd as K
+    from hydro_inputs import workloads as W
+    wl = W.hotspots_minijets(steps=steps)
+    out = {"workload": wl.name, "training": train}
+    for tag, guess in (("prev_guess", K.KTMI_GUESS_PREV), ("learned_guess", K.KTMI_GUESS_MLP)):
+        g = make_hydro(wl, guess=guess)
+        if guess == K.KTMI_GUESS_MLP:
+            g.set_mlp(params, K.KTMI_MLP_BF16)
+        ts = timed_runs(g, wl, steps, reps, warmup=2)
+        r = rate(wl.ncell, steps, ts)
+        r["newton_mean"] = g.diag()["newton_mean"]
+        out[tag] = r
+        del g
+        torch.cuda.synchronize()
+    out["learned_minus_prev_ms_per_step"] = (out["learned_guess"]["ms_per_step"] -
+                                             out["prev_guess"]["ms_per_step"])
+    return out
+
+
+def batch_path(params, steps, reps, nev=64):
+    """64 uneven events (grids 101^2..301^2 x {1, 33, 65, 105}, eta/s in {0, 0.08,
+    0.16}) stepped together (one launch per class and stage) under HIP-graph replay,
+    each event on the tile shape the autotuner found fastest for it (tuned once
+    per precision, on a throwaway run); four forms: FP64 or mixed precision, with
+    the previous-stage or the learned root-solve start."""
+    import torch
+
+    import paper_1802_04449_amd as K
+    from paper_1802_04449_amd import autotune
+    from hydro_inputs import workloads as W
+    evs = W.event_batch(nev=nev, steps=steps)
+    cells = sum(wl.ncell for wl in evs)
+    st = torch.cuda.Stream()
+    out = {"events": nev, "cells": cells, "steps": steps,
+           "grids": sorted({(w.params["nx"], w.params["ne"]) for w in evs})[:3] + ["..."]}
+    tiles = {}
+    for precision in (0, 1):
+        t0 = time.perf_counter()
+        sel = []
+        for wl in evs:
+            h = make_hydro(wl, stream=st, precision=precision)
+            reset(h, wl)
+            t, _ = autotune.tune(h, steps=2, repeats=1, use_cache=False)
+            sel.append(t)
+            del h
+        tiles[precision] = sel
+        say(f"batch: tiles tuned for precision {precision} in {time.perf_counter() - t0:.1f} s")
+    base = None
+    for precision, learned in ((0, False), (0, True), (1, False), (1, True)):
+        tag = ("fp64" if precision == 0 else "mixed") + ("_learned" if learned else "_prev")
+        hs = []
+        for wl, t in zip(evs, tiles[precision]):
+            h = make_hydro(wl, stream=st, precision=precision, tile=t,
+                           guess=K.KTMI_GUESS_MLP if learned else K.KTMI_GUESS_PREV)
+            if learned:
+                h.set_mlp(params, K.KTMI_MLP_BF16)
+            reset(h, wl)
+            hs.append(h)
+        grp = K.Group(hs)
+        grp.set_graph(True)
+
+        def reset_all():
+            for h, wl in zip(hs, evs):
+                reset(h, wl)
+
+        ts = timed_runs(None, None, steps, reps, warmup=2, step_fn=grp.step, reset_fn=reset_all)
+        r = rate(cells, steps, ts)
+        diags = [h.diag() for h in hs]
+        solves = sum(d["solves"] for d in diags)
+        r["newton_mean"] = sum(d["newton_mean"] * d["solves"] for d in diags) / max(solves, 1)
+        r["classes"] = grp.classes
+        if base is None:
+            base = r["value"]
+        r["speedup_vs_fp64_prev"] = r["value"] / base
+        out[tag] = r
+        say(f"batch {tag}: {r['ms_per_step']:.2f} ms per step")
+        del grp, hs
+        torch.cuda.synchronize()
+    shapes = {}
+    for t in tiles[0]:
+        s = "x".join(map(str, K.ktmi_tile_shape(t)))
+        shapes[s] = shapes.get(s, 0) + 1
+    out["tiles_fp64"] = shapes
     return out
 
 
@@ -321,12 +374,8 @@ def surface_path(wl, warm_steps=10, reps=20, eps_f=0.3):
     import torch
 
     import paper_1802_04449_amd as K
-    g = K.Hydro(**wl.params)
-    g.set_eos(wl.eos)
-    if wl.T4 is not None:
-        g.set_initial_conserved(wl.T4)
-    else:
-        g.set_initial(wl.ic)
+    g = make_hydro(wl)
+    reset(g, wl)
     g.step(warm_steps)
     tA = g.diag()["tau"]
     A = g.snapshot(True)
@@ -371,12 +420,8 @@ def spectra_path(wl, reps=3, eps_f=0.3, T=0.137):
     import torch
 
     import paper_1802_04449_amd as K
-    g = K.Hydro(**wl.params)
-    g.set_eos(wl.eos)
-    if wl.T4 is not None:
-        g.set_initial_conserved(wl.T4)
-    else:
-        g.set_initial(wl.ic)
+    g = make_hydro(wl)
+    reset(g, wl)
     g.step(10)
     tA = g.diag()["tau"]
     A = g.snapshot(True)
@@ -410,88 +455,6 @@ def spectra_path(wl, reps=3, eps_f=0.3, T=0.137):
                          "frac": tfl / 78.6, "flops_per_evaluation": SPECTRA_FLOPS}}
 
 
-def train_guess(wls, steps_at=(0, 5, 10), train_steps=1500):
-    """Learned root-solve guess for a set of events: harvest (E, M, e) from FP64
-    runs of the given events at a few times, train on the GPU (library kernels)."""
-    import paper_1802_04449_amd as K
-    from paper_1802_04449_amd import mlp
-    states = []
-    for wl in wls:
-        g = K.Hydro(**wl.params)
-        g.set_eos(wl.eos)
-        g.set_initial(wl.ic)
-        done = 0
-        for t in steps_at:
-            g.step(t - done)
-            done = t
-            states.append(g.harvest())
-        del g
-    E, M, e = mlp.samples_from_states(states, emin=1e-7, seed=1)
-    tr = mlp.Trainer(E, M, e, seed=3)
-    loss0 = tr.loss()
-    t0 = time.perf_counter()
-    tr.train(train_steps, batch=4096)
-    dt = time.perf_counter() - t0
-    return tr.params, {"samples": int(E.size), "adam_steps": train_steps, "loss_initial": loss0,
-                       "loss_final": tr.loss(), "train_s": dt,
-                       "harvested_from": [f"{w.name} at steps {list(steps_at)}" for w in wls]}
-
-
-def bench_batch(args, precision=None, learned=False, steps=None, warmup=None):
-    """64 uneven events (grids 101^2..301^2 x {1, 33, 65, 105}, eta/s in {0, 0.08, 0.16})
-    stepped together: per stage one launch per (mode, tile, precision, guess) class.
-    learned: root solves start from a network trained first on harvested states
-    of two of the events."""
-    import torch
-
-    import paper_1802_04449_amd as K
-    from hydro_inputs import workloads as W
-
-    precision = args.precision if precision is None else precision
-    steps = args.steps if steps is None else steps
-    warmup = args.warmup if warmup is None else warmup
-    evs = W.event_batch(nev=64, steps=steps)
-    params, train = (None, None)
-    if learned:
-        params, train = train_guess([evs[0], evs[1]])
-    st = torch.cuda.Stream()
-    hs = []
-    for wl in evs:
-        guess = K.KTMI_GUESS_MLP if learned else K.KTMI_GUESS_PREV
-        h = K.Hydro(stream=st, precision=precision, guess=guess, **wl.params)
-        h.set_eos(wl.eos)
-        if learned:
-            h.set_mlp(params, K.KTMI_MLP_BF16)
-        h.set_initial(wl.ic)
-        hs.append(h)
-    grp = K.Group(hs)
-    if args.graph:
-        grp.set_graph(True)
-    grp.step(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    grp.step(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    cells = sum(wl.ncell for wl in evs)
-    diags = [h.diag() for h in hs]
-    solves = sum(d["solves"] for d in diags)
-    iters = sum(d["newton_mean"] * d["solves"] for d in diags)
-    path = ("FP64" if precision == 0 else "mixed FP32/FP64") + (", learned guess" if learned else "")
-    out = {"metric": "cell-updates/s of viscous KT+RK2 step, plain FP64 vs batched/learned/FP32 @1e-6",
-           "value": cells * steps / dt, "unit": "cell-updates/s", "n_gpus": 1,
-           "steps": steps, "warmup": warmup, "ms_per_step": dt / steps * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if precision == 0 else "f32+f64", "data": "synthetic",
-           "config": {"workload": "batch of 64 uneven events", "cells": cells, "path": path,
-                      "classes": grp.classes, "graph": bool(args.graph)},
-           "newton_mean": iters / max(solves, 1)}
-    if train:
-        out["training"] = train
-    del grp, hs
-    return out
-
-
 def copy_calibration():
     """A plain device-to-device copy of 2^30 bytes, five times: rocprofv3's FETCH_SIZE and
     WRITE_SIZE per dispatch for it calibrate the counters against known traffic."""
@@ -505,23 +468,212 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_each_way": n * 8, "repeats": 5}), flush=True)
 
 
-def cpu_baseline(wl, steps):
-    """The CPU oracle as it stands, on the same grid and initial state, all host
-    threads, `steps` steps (the set-up and first-step estimate are not timed)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, steps_all=5, steps_one=1):
+    """The CPU oracle as it stands, on the headline grid and initial state: after
+    one untimed step (which includes the first-step estimate), `steps_one` steps at
+    one thread and `steps_all` steps at all host threads (at most 16)."""
     import oracle as O
     from tests import gpu_common as G
 
-    threads = min(16, os.cpu_count() or 1)
-    O.set_threads(threads)
-    o = O.Oracle(G.oracle_params(wl.params), eos=wl.eos)
-    o.set_initial(wl.ic)
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    return {"value": wl.ncell * steps / dt, "unit": "cell-updates/s", "cores": O.max_threads(),
-            "kind": "oracle",
-            "sample": f"full {wl.params['nx']}x{wl.params['ny']}x{wl.params['ne']} grid, first "
-                      f"{steps} steps from the same initial state ({dt:.1f} s)"}
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    res = {}
+    for tag, threads, steps in (("one_thread", 1, steps_one),
+                                ("all_threads", min(16, nproc or 1), steps_all)):
+        O.set_threads(threads)
+        used = O.max_threads()
+        o = O.Oracle(G.oracle_params(wl.params), eos=wl.eos)
+        o.set_initial(wl.ic)
+        o.step(1)
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t0
+        res[tag] = {"value": wl.ncell * steps / dt, "cores": used, "seconds": dt, "steps": steps}
+        say(f"cpu oracle {tag}: {res[tag]['value']:.3e} cell-updates/s")
+        del o
+    a = res["all_threads"]
+    return {"value": a["value"], "unit": "cell-updates/s", "cores": a["cores"], "kind": "oracle",
+            "sample": f"the full {wl.params['nx']}x{wl.params['ny']}x{wl.params['ne']} grid from "
+                      f"the same initial state: steps 2..{1 + a['steps']} at {a['cores']} threads "
+                      f"({a['seconds']:.1f} s); one thread: step 2 "
+                      f"({res['one_thread']['seconds']:.1f} s)",
+            "one_thread": res["one_thread"]["value"], "nproc": nproc, "cpu_model": cpu_model()}
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200,
+                    help="timed steps per run (200: the whole headline run)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before the first run")
+    ap.add_argument("--reps", type=int, default=5, help="timed runs; value is the median")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="hotspots",
+                    choices=["hotspots", "gubser_dense", "large", "batch64", "bulk", "minijets"],
+                    help="hotspots: the headline configuration; gubser_dense: the same grid and "
+                         "physics with a smooth Gubser profile that leaves no vacuum cells; large: "
+                         "385x385x129 single event; batch64: 64 uneven events in grouped launches; "
+                         "bulk: the headline configuration with bulk pressure and baryon density; "
+                         "minijets: the headline grid with the mini-jet initial state")
+    ap.add_argument("--graph", action="store_true", help="replay each step as a HIP graph")
+    ap.add_argument("--tile", type=int, default=-1, help="tile shape index (-1: library default)")
+    ap.add_argument("--precision", type=int, default=0,
+                    help="0: plain FP64; 1: mixed (FP32 flux/relaxation, FP64 root solve and sources)")
+    ap.add_argument("--quiet-skip", action="store_true",
+                    help="skip tiles whose neighbourhood stayed vacuum (bitwise identical results)")
+    ap.add_argument("--no-paths", action="store_true", help="only the headline line")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB five times (counter calibration)")
+    ap.add_argument("--only-surface", action="store_true",
+                    help="only measure the freeze-out surface finder on the workload (profiling)")
+    ap.add_argument("--only-spectra", action="store_true",
+                    help="only measure the Cooper-Frye spectra on the workload's surface (profiling)")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="only the 64-event batch (FP64 and mixed, with and without the network)")
+    ap.add_argument("--batch-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1802_04449_amd as K
+    from hydro_inputs import workloads as W
+
+    wl = {"hotspots": W.hotspots_viscous, "gubser_dense": W.gubser_dense_viscous,
+          "large": W.large_event, "bulk": W.hotspots_bulk, "batch64": W.hotspots_viscous,
+          "minijets": W.hotspots_minijets}[args.workload](steps=args.steps)
+    if args.only_surface:
+        print(json.dumps({"workload": wl.name, "freezeout_surface": surface_path(wl)}), flush=True)
+        return
+    if args.only_spectra:
+        print(json.dumps({"workload": wl.name, "cooper_frye_spectra": spectra_path(wl)}), flush=True)
+        return
+    if args.only_batch or args.workload == "batch64":
+        E, M, e = harvest_samples([W.hotspots_viscous()], at_steps=range(0, 201, 20), cap=10 ** 7)
+        params, train = train_guess(E, M, e)
+        b = batch_path(params, args.batch_steps, 3)
+        b["training"] = train
+        print(json.dumps({"workload": "batch of 64 uneven events", "batch64": b}), flush=True)
+        return
+
+    p = wl.params
+    bpc = BYTES_PER_CELL if p["viscous"] else BYTES_PER_CELL_IDEAL
+    if p.get("zetas", 0) > 0 or p.get("baryon", 0):
+        bpc = dict(BYTES_PER_CELL, **BYTES_PER_CELL_BULK)
+    stream = torch.cuda.Stream() if args.graph else None
+    g = make_hydro(wl, stream=stream, tile=args.tile, precision=args.precision)
+    if args.quiet_skip:
+        g.set_quiet_skip(True)
+    if args.graph:
+        g.set_graph(True)
+    say(f"headline: {wl.name}, {args.reps} runs of {args.steps} steps")
+    ts = timed_runs(g, wl, args.steps, args.reps, args.warmup)
+    head = rate(wl.ncell, args.steps, ts)
+    diag = g.diag()
+    # per-kernel durations: a separate instrumented run (graph replay off)
+    if args.graph:
+        g.set_graph(False)
+    per_kernel = kernel_times(g, wl, args.steps)
+    say(f"headline: {head['ms_per_step']:.3f} ms per step")
+    out = {
+        "metric": "cell-updates/s of viscous KT+RK2 step, plain FP64 vs batched/learned/FP32 @1e-6",
+        "value": head["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "nx": p["nx"], "ny": p["ny"], "ne": p["ne"],
+                   "dx": p["dx"], "deta": p["de"], "tau0": p["tau0"], "h": p["h"],
+                   "eta_over_s": p["etas"], "ic": wl.note or "200 Gaussian hotspots, seed 1",
+                   "eos": "1555-row synthetic crossover table",
+                   "path": ("plain FP64" if args.precision == 0 else "mixed FP32/FP64") +
+                           (", quiet tiles skipped" if args.quiet_skip else "") +
+                           (", HIP graph" if args.graph else ""),
+                   "timing": f"median of {args.reps} runs of {args.steps} steps from the "
+                             f"initial state, uninstrumented"},
+        "roofline": roofline_of(wl, per_kernel, bpc),
+        "kernels": kernels_summary(per_kernel, wl, bpc),
+        "reps_s": head["reps_s"],
+        "tile": list(K.ktmi_tile_shape(K.ktmi_get_tile(g.h))),
+        "graph": bool(args.graph),
+        "diag": {k: diag[k] for k in ("tau", "eps_max", "newton_mean", "newton_max", "clamps",
+                                      "nonconv", "nans", "vacuum", "errors")},
+        "context": {"paper_table_II_viscous_gpu_cell_updates_per_s": 1.69e7,
+                    "paper_hardware": "AMD FirePro S9150, 385x385x115 cells"},
+    }
+    del g
+    torch.cuda.synchronize()
+    headline_default = (args.workload == "hotspots" and args.precision == 0 and
+                        not args.quiet_skip and args.tile < 0)
+    if headline_default and not args.no_paths:
+        paths = {}
+        say("path: C0 ideal Gubser 33x33x17")
+        w0 = W.gubser_ideal_33()
+        paths["C0_gubser_ideal_33x33x17_fp64"] = single_path(w0, 50, 5)
+        say("path: mixed precision")
+        paths["C1_mixed_fp32_fp64"] = single_path(wl, args.steps, 3, bpc=BYTES_PER_CELL,
+                                                  precision=1)
+        say("path: quiet tiles")
+        paths["C1_fp64_quiet_skip"] = single_path(wl, args.steps, 3, quiet=True)
+        say("path: HIP graph")
+        paths["C1_fp64_graph"] = single_path(wl, args.steps, 3, graph=True)
+        say("path: lambda_1")
+        paths["C1_fp64_lambda1"] = single_path(wl, args.steps, 3, bpc=BYTES_PER_CELL,
+                                               lambda1_hat=-10.0)
+        paths["C1_fp64_lambda1"]["note"] = "second-order lambda_1 term, lambda1_hat = -10"
+        say("path: bulk and baryon")
+        wb = W.hotspots_bulk(steps=args.steps)
+        paths["C1_fp64_bulk_baryon"] = single_path(wb, args.steps, 3,
+                                                   bpc=dict(BYTES_PER_CELL, **BYTES_PER_CELL_BULK))
+        paths["C1_fp64_bulk_baryon"]["note"] = ("bulk pressure (zeta/s = 0.04) and net-baryon "
+                                                "density transported")
+        say("path: harvesting and training the root-solve guess")
+        E, M, e = harvest_samples([wl], at_steps=range(0, 201, 20), cap=10 ** 7)
+        params, train = train_guess(E, M, e)
+        train["harvested_from"] = f"{wl.name} at steps 0, 20, ..., 200 (non-vacuum cells)"
+        say(f"trained on {train['samples']} samples in {train['train_s']:.1f} s")
+        say("path: C2 mini-jets")
+        paths["C2_minijets_fp64"] = minijet_path(params, train, args.steps, 3)
+        say("path: C3 batch of 64 events")
+        paths["C3_batch64"] = batch_path(params, args.batch_steps, 3)
+        say("path: C4 large event")
+        w4 = W.large_event()
+        paths["C4_large_385x385x129_fp64"] = single_path(w4, 20, 3, bpc=BYTES_PER_CELL)
+        paths["C4_large_385x385x129_mixed"] = single_path(w4, 20, 3, bpc=BYTES_PER_CELL,
+                                                          precision=1)
+        for k in ("C4_large_385x385x129_fp64", "C4_large_385x385x129_mixed"):
+            paths[k]["note"] = "first 20 of the 1000 steps (the rate is per step)"
+        say("path: freeze-out surface and spectra")
+        paths["freezeout_surface"] = surface_path(wl)
+        paths["cooper_frye_spectra"] = spectra_path(wl)
+        out["paths"] = paths
+    if not args.no_cpu_baseline and headline_default:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
