@@ -681,7 +681,7 @@ __device__ __forceinline__ double tile_divergence(const GField& e,
                                                   const FSet& u, const FSet& pi,
                                                   const StepParams& p, const EosDev& eos,
                                                   double tauf, const Pos& q, double* R,
-                                                  RT* lds) {
+                                                  RT* lds, GField ez = GField{nullptr}) {
   constexpr int N = TX * TY * TZ;
   constexpr int NQ = BK ? 12 : 10, NC = 4 + NQ;
 #pragma unroll
@@ -714,14 +714,22 @@ __device__ __forceinline__ double tile_divergence(const GField& e,
       }
       any = __syncthreads_or(nz);
     }
-    if (PI_SRC == 2 && !any) {  // e = 0 in the whole box: as-stored pi~ decides
+    // e = 0 in the whole box: as-stored pi~ decides.  Where the regulator zeroes
+    // pi~ with zero e (vac_zero), pi~ is zero wherever the energy density it was
+    // regulated with is: the pass's own e (ez.p null: nothing more to test), or ez
+    // (one field instead of the NQ components).
+    if (PI_SRC == 2 && !any && !(p.vac_zero && ez.p == nullptr)) {
       for (int b = tid; b < NB; b += kBlock) {
         const int bx = b / (BY * BZ), by = (b / BZ) % BY, bz = b % BZ;
         const int i = clampi(q.i0 - 2 + bx, 0, p.nx - 1), j = clampi(q.j0 - 2 + by, 0, p.ny - 1);
         const int k = clampi(q.k0 - 2 + bz, 0, p.ne - 1);
         const int c = (i * p.ny + j) * p.ne + k;
+        if (p.vac_zero) {
+          nz |= ez[c] != 0.0;
+        } else {
 #pragma unroll
-        for (int m = 0; m < NQ; ++m) nz |= pi[m][c] != 0.0;
+          for (int m = 0; m < NQ; ++m) nz |= pi[m][c] != 0.0;
+        }
       }
       any = __syncthreads_or(nz);
     }
@@ -1357,7 +1365,9 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>())
   if (tile_asleep<TX, TY, TZ>(p, cx.tg, cx.qcur, cx.tile)) return;
   const double tf = g.cart ? 1.0 : g.tau;
   double R[4 + NQ];
-  tile_divergence<RT, TX, TY, TZ, false, true, 2, BK>(f.e1, f.u1, f.pi1, p, eos, tf, q, R, lds);
+  // pi~' was regulated with e^n in stage 1: zero wherever e^n is (vac_zero)
+  tile_divergence<RT, TX, TY, TZ, false, true, 2, BK>(f.e1, f.u1, f.pi1, p, eos, tf, q, R, lds,
+                                                      f.e);
   bool quiet = true;  // this cell's part of the quiet-tile test
   if (q.active) {
     const int c = q.c;
