@@ -331,11 +331,12 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
   int idx[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) idx[t] = base + clampi(a - 1 + t, 0, n - 1) * stride;
-  static_assert(PI_SRC != 2, "as-stored pi~ needs face_flux_all");
+  static_assert(PI_SRC != 2 || !DO_PI, "the pi~ flux of as-stored pi~ needs face_flux_all");
   constexpr int NQ = BK ? 12 : 10;
   // Vacuum faces: every state the kernels write has u~ = 0 where e = 0, and
-  // pi~ reads as zero there (PI_SRC 0/1), so e alone decides and a vacuum face
-  // skips the other loads.
+  // pi~ reads as zero there (PI_SRC 0/1; as stored in stage 2T, whose pi^{n+1}
+  // the regulator zeroed wherever e' is zero), so e alone decides and a vacuum
+  // face skips the other loads.
   double ev[4];
   bool vac = true;
 #pragma unroll
@@ -343,7 +344,9 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
     ev[t] = e[idx[t]];
     vac = vac && (ev[t] == 0.0);
   }
-  if (vac) {
+  // As-stored pi~ (PI_SRC 2, stage 2T) is zero where e is when the regulator
+  // zeroes it there (vac_zero); otherwise such a face is evaluated in full.
+  if (vac && (PI_SRC != 2 || p.vac_zero)) {
 #pragma unroll
     for (int k = 0; k < 4 + NQ; ++k)
       if (k < 4 ? DO_T : DO_PI) out[k * F] = R(0);
@@ -653,7 +656,7 @@ __device__ __forceinline__ double eval_face(const GField& e, const FSet& u,
     // stage 1 (pi~ masked by e): the streamed evaluation (fewer registers);
     // stage 2 (as-stored pi~): all loads at once with the per-face e/pi~ test
     RT c;
-    if constexpr (PI_SRC == 2)
+    if constexpr (PI_SRC == 2 && DO_PI)
       c = face_flux_all<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride, d + 1,
                                                      (RT)tauf, p, eos, out, S);
     else
@@ -870,7 +873,7 @@ __device__ __forceinline__ double tile_divergence(const GField& e,
           // stage 1 (pi~ masked by e): the streamed evaluation (fewer registers);
           // stage 2 (as-stored pi~): all loads at once with the per-face e/pi~ test
           RT c;
-          if constexpr (PI_SRC == 2)
+          if constexpr (PI_SRC == 2 && DO_PI)
             c = face_flux_all<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride, d + 1,
                                                            (RT)tauf, p, eos, lds + f, F);
           else
