@@ -20,6 +20,9 @@
 // Template kernels only: the stencil passes are instantiated per (pass,
 // arithmetic type) in ktmi_stencil.hip objects, the rest in ktmi.hip.
 #pragma once
+#ifndef KTMI_S2PI_STREAM
+#define KTMI_S2PI_STREAM 1
+#endif
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -327,11 +330,11 @@ template <typename R, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false>
 __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
                                        const FSet& pi, int base, int a, int n,
                                        int stride, int axis, R tauf, const StepParams& p,
-                                       const EosDev& eos, R* out, int F) {
+                                       const EosDev& eos, R* out, int F,
+                                       GField ez = GField{nullptr}) {
   int idx[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) idx[t] = base + clampi(a - 1 + t, 0, n - 1) * stride;
-  static_assert(PI_SRC != 2 || !DO_PI, "the pi~ flux of as-stored pi~ needs face_flux_all");
   constexpr int NQ = BK ? 12 : 10;
   // Vacuum faces: every state the kernels write has u~ = 0 where e = 0, and
   // pi~ reads as zero there (PI_SRC 0/1; as stored in stage 2T, whose pi^{n+1}
@@ -344,8 +347,14 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
     ev[t] = e[idx[t]];
     vac = vac && (ev[t] == 0.0);
   }
-  // As-stored pi~ (PI_SRC 2, stage 2T) is zero where e is when the regulator
-  // zeroes it there (vac_zero); otherwise such a face is evaluated in full.
+  // As-stored pi~ (PI_SRC 2) is zero wherever the energy density it was
+  // regulated with is zero when the regulator zeroes it there (vac_zero): the
+  // pass's own e (stage 2T), or ez (stage 2pi: e^n), then also tested here;
+  // without vac_zero such a face is evaluated in full.
+  if (PI_SRC == 2 && vac && ez.p != nullptr && p.vac_zero) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) vac = vac && ez[idx[t]] == 0.0;
+  }
   if (vac && (PI_SRC != 2 || p.vac_zero)) {
 #pragma unroll
     for (int k = 0; k < 4 + NQ; ++k)
@@ -626,7 +635,7 @@ template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC
 __device__ __forceinline__ double eval_face(const GField& e, const FSet& u,
                                             const FSet& pi, const StepParams& p,
                                             const EosDev& eos, double tauf, const Pos& q, int d,
-                                            int f, RT* out, int S) {
+                                            int f, RT* out, int S, GField ez = GField{nullptr}) {
   constexpr int NC = BK ? 16 : 14;
   const int nd = d == 0 ? p.nx : (d == 1 ? p.ny : p.ne);
   const double inv_del = d == 0 ? p.inv_dx : (d == 1 ? p.inv_dy : p.inv_de / tauf);
@@ -656,12 +665,12 @@ __device__ __forceinline__ double eval_face(const GField& e, const FSet& u,
     // stage 1 (pi~ masked by e): the streamed evaluation (fewer registers);
     // stage 2 (as-stored pi~): all loads at once with the per-face e/pi~ test
     RT c;
-    if constexpr (PI_SRC == 2 && DO_PI)
+    if constexpr (PI_SRC == 2 && DO_PI && !KTMI_S2PI_STREAM)
       c = face_flux_all<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride, d + 1,
                                                      (RT)tauf, p, eos, out, S);
     else
       c = face_flux_stream<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride, d + 1,
-                                                        (RT)tauf, p, eos, out, S);
+                                                        (RT)tauf, p, eos, out, S, ez);
     return (double)c * inv_del;
   }
 #pragma unroll
@@ -870,15 +879,14 @@ __device__ __forceinline__ double tile_divergence(const GField& e,
         if (inrow && ga <= nd) {
           const int base = d == 0 ? (gj * p.ne + gk)
                                   : (d == 1 ? (gi * p.ny) * p.ne + gk : (gi * p.ny + gj) * p.ne);
-          // stage 1 (pi~ masked by e): the streamed evaluation (fewer registers);
-          // stage 2 (as-stored pi~): all loads at once with the per-face e/pi~ test
           RT c;
-          if constexpr (PI_SRC == 2 && DO_PI)
+          if constexpr (PI_SRC == 2 && DO_PI && !KTMI_S2PI_STREAM)
             c = face_flux_all<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride, d + 1,
                                                            (RT)tauf, p, eos, lds + f, F);
           else
             c = face_flux_stream<RT, DO_T, DO_PI, PI_SRC, BK>(e, u, pi, base, ga - 1, nd, stride,
-                                                              d + 1, (RT)tauf, p, eos, lds + f, F);
+                                                              d + 1, (RT)tauf, p, eos, lds + f, F,
+                                                              ez);
           cfl = fmax(cfl, (double)c * inv_del);
         } else {
   #pragma unroll
