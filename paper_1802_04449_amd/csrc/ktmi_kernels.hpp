@@ -947,13 +947,15 @@ constexpr int pi_waves() {
   return !NOCAP && 163840 / (int)(lds_doubles<TX, TY, TZ, NC>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
 }
 
-// Waves per SIMD asked of stage 2T: as the other stage-2 passes, except that the
-// FP32 (mixed-precision) instance without bulk asks for 4 (128 VGPRs, 68 bytes of
-// spill a lane): 0.56 -> 0.53 ms on the 201x201x105 hotspot grid, +1.8% on the
-// grid without vacuum.  The same cap on the FP32 stage 1 or stage 2pi loses.
+// Waves per SIMD asked of stage 2T: four without bulk (its streamed faces need
+// 143 VGPRs in FP64; under the four-wave cap of 128 a few spill, and the pass
+// still runs faster: 0.46 -> 0.42 ms on the 201x201x105 hotspot grid, 0.86 ->
+// 0.84 ms on the grid without vacuum; FP32: 117 VGPRs, no spill); with bulk as
+// the other stage-2 passes.  Four waves on stage 2pi gain on the hotspot grid and
+// lose on the dense one, so it keeps three.
 template <typename RT, int TX, int TY, int TZ, bool BK>
 constexpr int s2t_waves() {
-  return sizeof(RT) == 4 && !BK ? 4 : pi_waves<RT, TX, TY, TZ, false>();
+  return !BK ? 4 : pi_waves<RT, TX, TY, TZ, false>();
 }
 
 // u~^tau of spatial components.
