@@ -688,7 +688,7 @@ __device__ __forceinline__ double eval_face(const GField& e, const FSet& u,
 // rounds, F0 + F1 + F2 of them (912 for a 4x4x16 tile: 4 rounds instead of 6),
 // with one barrier; their 4 components fit lds_doubles_allf (29 KB).
 template <typename RT, int TX, int TY, int TZ, bool DO_T, bool DO_PI, int PI_SRC, bool BK = false,
-          bool SPLIT = false, bool ALLF = false>
+          bool SPLIT = false, bool ALLF = false, bool ZERO_R = true>
 __device__ __forceinline__ double tile_divergence(const GField& e,
                                                   const FSet& u, const FSet& pi,
                                                   const StepParams& p, const EosDev& eos,
@@ -696,8 +696,10 @@ __device__ __forceinline__ double tile_divergence(const GField& e,
                                                   RT* lds, GField ez = GField{nullptr}) {
   constexpr int N = TX * TY * TZ;
   constexpr int NQ = BK ? 12 : 10, NC = 4 + NQ;
+  if constexpr (ZERO_R) {
 #pragma unroll
-  for (int k = 0; k < NC; ++k) R[k] = 0.0;
+    for (int k = 0; k < NC; ++k) R[k] = 0.0;
+  }
   double cfl = 0.0;
   const int tid = threadIdx.x;
   // Whole-tile vacuum test.  Every face stencil of the tile reads cells in the
@@ -1246,12 +1248,36 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(const EventDesc* __re
   st_cell(f.up[2] + c, 2.0 * u3 - s.u3);
 }
 
+// A cell's e, u~ and (VISC) pi~ at the current level; u~ and pi~ read as zero
+// (no loads) where e = 0.
+template <bool VISC, int NQ>
+__device__ __forceinline__ void cell_values(const DFields& f, int c, double& e, double& u1,
+                                            double& u2, double& u3, double* pc) {
+  e = f.e[c];
+  u1 = u2 = u3 = 0.0;
+#pragma unroll
+  for (int m = 0; m < NQ; ++m) pc[m] = 0.0;
+  if (e != 0.0) {
+    u1 = f.u[0][c];
+    u2 = f.u[1][c];
+    u3 = f.u[2][c];
+    if (VISC) {
+#pragma unroll
+      for (int m = 0; m < NQ; ++m) pc[m] = f.pi[m][c];
+    }
+  }
+}
+
 // Stage 1 at tau_n (predictor) for the ideal (VISC = false) or viscous path;
 // BK (viscous only): also Pi and n, with P + Pi in T~ and in the root solve.
-// The bulk variant (172 VGPRs uncapped: two waves per SIMD) asks for three, and so
-// do the network variants (uncapped, the matrix-core results take 32 accumulation
-// registers on top of 146 / 164 VGPRs; capped, they stay in VGPRs without spills),
-// the network variant with the lambda_1 term two (else one wave).
+// The cell's sources come before the face rounds, so the shear source's
+// gradients and the divergence accumulators are never live together: 137 VGPRs
+// in FP64 (three waves per SIMD, which its 45 KB of LDS also allows; 161 with the
+// sources after the rounds), 107 in FP32 (four waves; 134 before, and the pass
+// went from 0.54 to 0.49 ms on the 201x201x105 hotspot grid).  The bulk variant
+// and the network variants ask for three waves (uncapped, the matrix-core
+// results take 32 accumulation registers on top; capped, they stay in VGPRs
+// without spills), the network variant with the lambda_1 term two (else one).
 template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool L1, bool BK = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     BK || (NET && !L1) ? 3 : (NET ? 2 : 1)))) void k_stage1(const EventDesc* __restrict__ evs,
@@ -1276,46 +1302,47 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     return;
   }
   double R[4 + NQ];
-  const double cfl = tile_divergence<RT, TX, TY, TZ, true, VISC, VISC ? 1 : 0, BK, true>(
-      f.e, f.u, f.pi, p, eos, tf, q, R, lds);
-  v[P_CFL] = cfl * p.h;
-  double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0, Pi1 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4 + NQ; ++k) R[k] = 0.0;
+  // The cell's sources first (geometric, and the shear relaxation source with its
+  // velocity gradients): their registers are free again before the face rounds
+  // accumulate the flux divergence onto them.
+  // e = 0 implies u~ = 0 (the cutoff and the root solve return zero velocity
+  // with zero energy density), and pi~ reads as zero there: no loads
   if (q.active) {
     const int c = q.c;
-    // e = 0 implies u~ = 0 (the cutoff and the root solve return zero velocity
-    // with zero energy density), and pi~ reads as zero there: no loads
-    const double e = f.e[c];
-    double u1 = 0.0, u2 = 0.0, u3 = 0.0, pc[NQ];
-#pragma unroll
-    for (int m = 0; m < NQ; ++m) pc[m] = 0.0;
-    if (e != 0.0) {
-      u1 = f.u[0][c];
-      u2 = f.u[1][c];
-      u3 = f.u[2][c];
-      if (VISC) {
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) pc[m] = f.pi[m][c];
-      }
-    }
-    const double ut = utau(u1, u2, u3);
+    double e, u1, u2, u3, pc[NQ];
+    cell_values<VISC, NQ>(f, c, e, u1, u2, u3, pc);
     if (!g.cart) {  // geometric source S_T = (-Tc^{ee}, 0, 0, -Tc^{te})
+      const double ut = utau(u1, u2, u3);
       double P, cs2;
       eos_p_cs2(eos, e, P, cs2);
       if constexpr (BK) P += pc[10];
       const double w = (e > 0.0 ? e : 0.0) + P;
       const double see = -(w * u3 * u3 + P + pc[9]);
-      R[0] += see;
-      R[3] += -(w * ut * u3 + pc[3]);
+      R[0] = see;
+      R[3] = -(w * ut * u3 + pc[3]);
       v[P_GEO] = see;
     }
+    if (VISC && e >= p.eps_cut) {
+      double S[NQ];
+      pi_source<RT, L1, BK>(f.u, f.up, f.u, p, eos, g, q, e, pc, S);
+#pragma unroll
+      for (int m = 0; m < NQ; ++m) R[4 + m] = S[m];
+    }
+  }
+  const double cfl = tile_divergence<RT, TX, TY, TZ, true, VISC, VISC ? 1 : 0, BK, true, false,
+                                     false>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
+  v[P_CFL] = cfl * p.h;
+  double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0, Pi1 = 0.0;
+  if (q.active) {
+    const int c = q.c;
+    // the cell's values again (cache hits after the face rounds)
+    double e, u1, u2, u3, pc[NQ];
+    cell_values<VISC, NQ>(f, c, e, u1, u2, u3, pc);
+    const double ut = utau(u1, u2, u3);
     double p1[NQ];
     if (VISC) {
-      if (e >= p.eps_cut) {
-        double S[NQ];
-        pi_source<RT, L1, BK>(f.u, f.up, f.u, p, eos, g, q, e, pc, S);
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) R[4 + m] += S[m];
-      }
       // u* = 2u^n - u^{n-1}: not needed where pi~' is zero whatever it is
       bool zero = e == 0.0;
 #pragma unroll
