@@ -22,26 +22,27 @@
 namespace ktmi {
 
 // Initial primitive state: cutoff, then T~^{tau mu} = tau0 Tc^{tau mu}(e, u~, pi~)
-// (ext: with P + Pi, and Pi, n zero below the cutoff).
+// (ext: with P + Pi, and Pi, n zero below the cutoff).  pi~, Pi and n come
+// staged in FP64 in the stage-1 block and go to the pi~ block in its storage type.
 __global__ __launch_bounds__(kBlock) void k_init_primitive(Fields f, StepParams p, EosDev eos,
                                                             Geo g, int visc, int ext) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= p.ncell) return;
   double e = f.e[c];
   double u1 = f.u[0][c], u2 = f.u[1][c], u3 = f.u[2][c];
-  double pv[10], Pi = ext ? f.pi[10][c] : 0.0;
+  double pv[10], Pi = ext ? f.pi1[10][c] : 0.0, nb = ext ? f.pi1[11][c] : 0.0;
 #pragma unroll
-  for (int m = 0; m < 10; ++m) pv[m] = visc ? f.pi[m][c] : 0.0;
+  for (int m = 0; m < 10; ++m) pv[m] = visc ? f.pi1[m][c] : 0.0;
   if (!(e >= p.eps_cut)) {
     e = 0.0;
     u1 = u2 = u3 = 0.0;
 #pragma unroll
     for (int m = 0; m < 10; ++m) pv[m] = 0.0;
-    if (ext) {
-      Pi = 0.0;
-      f.pi[10][c] = 0.0;
-      f.pi[11][c] = 0.0;
-    }
+    Pi = nb = 0.0;
+  }
+  if (ext) {
+    stq_rt(f.pi[10], c, Pi, f.pf32);
+    stq_rt(f.pi[11], c, nb, f.pf32);
   }
   double P, cs2;
   eos_p_cs2(eos, e, P, cs2);
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_init_primitive(Fields f, StepParams 
   f.u[1][c] = u2;
   f.u[2][c] = u3;
 #pragma unroll
-  for (int m = 0; m < 10; ++m) f.pi[m][c] = pv[m];
+  for (int m = 0; m < 10; ++m) stq_rt(f.pi[m], c, pv[m], f.pf32);
 #pragma unroll
   for (int nu = 0; nu < 4; ++nu) f.T[nu][c] = tf * (w * ut * u4[nu] - (nu == 0 ? P : 0.0) + pv[nu]);
 }
@@ -128,12 +129,12 @@ __global__ void k_set_clock(double* clk, double tau) {
   }
 }
 
-// pi~ as seen by readers: zero in vacuum cells.
+// pi~ as seen by readers: zero in vacuum cells; f32: stored in FP32.
 __global__ __launch_bounds__(kBlock) void k_read_pi(const double* __restrict__ e,
                                                     const double* __restrict__ pi, double* dst,
-                                                    int n) {
+                                                    int n, int f32) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c < n) dst[c] = e[c] == 0.0 ? 0.0 : pi[c];
+  if (c < n) dst[c] = e[c] == 0.0 ? 0.0 : ldq_rt(pi, c, f32);
 }
 
 // Copies the network parameters into the handle's workspace and appends W2 as BF16.
@@ -155,10 +156,10 @@ __global__ __launch_bounds__(kBlock) void k_harvest(Fields f, const double* __re
   const double tf = cart ? 1.0 : clk[0];
   const double e = f.e[c];
   const bool pv = visc && e != 0.0;
-  const double K0 = f.T[0][c] / tf - (pv ? f.pi[0][c] : 0.0);
-  const double K1 = f.T[1][c] / tf - (pv ? f.pi[1][c] : 0.0);
-  const double K2 = f.T[2][c] / tf - (pv ? f.pi[2][c] : 0.0);
-  const double K3 = f.T[3][c] / tf - (pv ? f.pi[3][c] : 0.0);
+  const double K0 = f.T[0][c] / tf - (pv ? ldq_rt(f.pi[0], c, f.pf32) : 0.0);
+  const double K1 = f.T[1][c] / tf - (pv ? ldq_rt(f.pi[1], c, f.pf32) : 0.0);
+  const double K2 = f.T[2][c] / tf - (pv ? ldq_rt(f.pi[2], c, f.pf32) : 0.0);
+  const double K3 = f.T[3][c] / tf - (pv ? ldq_rt(f.pi[3], c, f.pf32) : 0.0);
   E[c] = K0;
   M[c] = sqrt(K1 * K1 + K2 * K2 + K3 * K3);
   eps[c] = e;
@@ -706,6 +707,7 @@ int ktmi_bind(ktmi_handle* h, void* ws, size_t bytes, void* stream) {
   // address a block from its first field), Pi and n right after pi~'s 10
   const int nq = has_ext(&h->d) ? 12 : 10;
   f.fstride = (long)fs;
+  f.pf32 = h->d.precision == KTMI_MIXED ? 1 : 0;  // pi~ blocks in FP32 (first half of each slot)
   f.e = base + fs * q++;
   for (int m = 0; m < 3; ++m) f.u[m] = base + fs * q++;
   for (int m = 0; m < 3; ++m) f.up[m] = base + fs * q++;
@@ -821,20 +823,21 @@ int ktmi_set_initial_primitive_ext(ktmi_handle* h, const double* e, const double
   HIP_TRY(h, hipMemcpyAsync(h->f.u[0], ux, nb, hipMemcpyDeviceToDevice, s));
   HIP_TRY(h, hipMemcpyAsync(h->f.u[1], uy, nb, hipMemcpyDeviceToDevice, s));
   HIP_TRY(h, hipMemcpyAsync(h->f.u[2], ue, nb, hipMemcpyDeviceToDevice, s));
+  // pi~ (Pi, n) staged in FP64 in the stage-1 block; k_init_primitive stores it
   for (int m = 0; m < 10; ++m) {
     if (pi10 && h->d.viscous)
-      HIP_TRY(h, hipMemcpyAsync(h->f.pi[m], pi10 + (size_t)m * n, nb, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(h, hipMemcpyAsync(h->f.pi1[m], pi10 + (size_t)m * n, nb, hipMemcpyDeviceToDevice, s));
     else
-      hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, h->f.pi[m], (int)n);
+      hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, h->f.pi1[m], (int)n);
   }
   const bool ext = has_ext(&h->d);
   if (ext) {
     const double* src[2] = {h->d.zetas > 0.0 ? Pi : nullptr, h->d.baryon ? nbar : nullptr};
     for (int m = 0; m < 2; ++m) {
       if (src[m])
-        HIP_TRY(h, hipMemcpyAsync(h->f.pi[10 + m], src[m], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(h->f.pi1[10 + m], src[m], n * sizeof(double), hipMemcpyDeviceToDevice, s));
       else
-        hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, h->f.pi[10 + m], (int)n);
+        hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, h->f.pi1[10 + m], (int)n);
     }
   }
   h->tau = h->d.tau0;
@@ -856,11 +859,12 @@ int ktmi_set_initial_conserved(ktmi_handle* h, const double* T4, const double* p
   hipStream_t s = h->stream;
   for (int m = 0; m < 4; ++m)
     HIP_TRY(h, hipMemcpyAsync(h->f.T[m], T4 + (size_t)m * n, nb, hipMemcpyDeviceToDevice, s));
+  // pi~ staged in FP64 in the stage-1 block; k_init_conserved stores it
   for (int m = 0; m < 10; ++m) {
     if (pi10 && h->d.viscous)
-      HIP_TRY(h, hipMemcpyAsync(h->f.pi[m], pi10 + (size_t)m * n, nb, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(h, hipMemcpyAsync(h->f.pi1[m], pi10 + (size_t)m * n, nb, hipMemcpyDeviceToDevice, s));
     else
-      hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, h->f.pi[m], (int)n);
+      hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, h->f.pi1[m], (int)n);
   }
   if (has_ext(&h->d))  // Pi = n = 0
     for (int m = 10; m < 12; ++m)
@@ -979,13 +983,13 @@ int ktmi_read(ktmi_handle* h, int field, double* dst) {
     src = cur_u(h)[field - KTMI_F_UX];
   else if (field >= KTMI_F_PI && field < KTMI_F_PI + 10) {
     hipLaunchKernelGGL(k_read_pi, dim3(h->nblk), dim3(kBlock), 0, s, h->f.e,
-                       h->f.pi[field - KTMI_F_PI], dst, n);
+                       h->f.pi[field - KTMI_F_PI], dst, n, h->f.pf32);
     HIP_TRY(h, hipGetLastError());
     return KTMI_OK;
   } else if (field == KTMI_F_BULK || field == KTMI_F_NB) {
     if (has_ext(&h->d))
       hipLaunchKernelGGL(k_read_pi, dim3(h->nblk), dim3(kBlock), 0, s, h->f.e,
-                         h->f.pi[10 + field - KTMI_F_BULK], dst, n);
+                         h->f.pi[10 + field - KTMI_F_BULK], dst, n, h->f.pf32);
     else
       hipLaunchKernelGGL(k_zero, dim3(h->nblk), dim3(kBlock), 0, s, dst, n);
     HIP_TRY(h, hipGetLastError());

@@ -66,6 +66,7 @@ struct Fields {
   double* acc;      // [16] accumulated diagnostics
   int* quiet;       // [3][ntiles]: quiet flags by clock parity (2), stage-2pi part (1)
   long fstride;     // elements from one field to the next
+  int pf32;         // the pi~ blocks (pi, pi1) hold FP32 values (mixed precision)
 };
 
 // One field seen through the global address space.  Element i is addressed by
@@ -80,6 +81,35 @@ struct GField {
     return (gdouble*)((gchar*)p + (unsigned)i * 8u);
   }
 };
+
+// The pi~ blocks (pi~, Pi, n and their stage-1 values) as stored: FP64, or FP32
+// on the mixed-precision path (RT = float), element i of field k then at
+// (float*)(base of field k) + i, in the first half of the field's slot.
+template <typename RT>
+__device__ __forceinline__ double ldq(const GField& g, int i) {
+  if constexpr (sizeof(RT) == 4)
+    return (double)*(const gfloat*)((const gchar*)g.p + (unsigned)i * 4u);
+  else
+    return g[i];
+}
+template <typename RT>
+__device__ __forceinline__ void stq(const GField& g, int i, double v) {
+  if constexpr (sizeof(RT) == 4)
+    *(gfloat*)((gchar*)g.p + (unsigned)i * 4u) = (float)v;
+  else
+    *(g + i) = v;
+}
+// The same with the storage type chosen at run time (Fields::pf32), for the
+// kernels that set up the state.
+__device__ __forceinline__ double ldq_rt(const double* b, int i, int f32) {
+  return f32 ? (double)((const float*)b)[i] : b[i];
+}
+__device__ __forceinline__ void stq_rt(double* b, int i, double v, int f32) {
+  if (f32)
+    ((float*)b)[i] = (float)v;
+  else
+    b[i] = v;
+}
 
 // Consecutive fields of one stride, seen through the global address space.
 // The kernels hold one base pointer per group of fields instead of one per
@@ -302,10 +332,10 @@ __device__ __forceinline__ double vacuum_cfl(const StepParams& p, double tauf) {
 }
 
 // pi~ at a cell: PI_SRC 0 -> 0, 1 -> zero where e == 0 (vacuum), 2 -> as stored.
-template <int PI_SRC>
+template <int PI_SRC, typename RT>
 __device__ __forceinline__ double ld_pi(const FSet& pi, int m, int idx, double e) {
   if (PI_SRC == 0) return 0.0;
-  const double v = pi[m][idx];
+  const double v = ldq<RT>(pi[m], idx);
   if (PI_SRC == 1) return e == 0.0 ? 0.0 : v;
   return v;
 }
@@ -391,12 +421,12 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
       const int m0 = next_needed(-1);
       if (m0 < NQ) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) pcur[t] = pi[m0][idx[t]];
+        for (int t = 0; t < 4; ++t) pcur[t] = ldq<R>(pi[m0], idx[t]);
       }
     }
     if constexpr (BK) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) q4[4][t] = (R)ld_pi<PI_SRC>(pi, 10, idx[t], ev[t]);
+      for (int t = 0; t < 4; ++t) q4[4][t] = (R)ld_pi<PI_SRC, R>(pi, 10, idx[t], ev[t]);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -445,7 +475,7 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
     const int mn = next_needed(m);
     if (mn < NQ) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) pnext[t] = pi[mn][idx[t]];
+      for (int t = 0; t < 4; ++t) pnext[t] = ldq<R>(pi[mn], idx[t]);
     }
     R p4[4];
 #pragma unroll
@@ -524,7 +554,7 @@ __device__ __forceinline__ R face_flux_all(const GField& e, const FSet& u,
                         m == sym(axis, 3) || m == 10;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const double x = used ? pi[m][idx[t]] : 0.0;
+        const double x = used ? ldq<R>(pi[m], idx[t]) : 0.0;
         vac = vac && (x == 0.0);
         q4[4 + m][t] = (R)x;
       }
@@ -550,7 +580,7 @@ __device__ __forceinline__ R face_flux_all(const GField& e, const FSet& u,
 #pragma unroll
     for (int m = 0; m < NQ; ++m)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) q4[4 + m][t] = (R)ld_pi<PI_SRC>(pi, m, idx[t], ev[t]);
+      for (int t = 0; t < 4; ++t) q4[4 + m][t] = (R)ld_pi<PI_SRC, R>(pi, m, idx[t], ev[t]);
   }
   R qL[NC], qR[NC];
   const R th = (R)p.theta;
@@ -742,7 +772,7 @@ __device__ __forceinline__ double tile_divergence(const GField& e,
           nz |= ez[c] != 0.0;
         } else {
 #pragma unroll
-          for (int m = 0; m < NQ; ++m) nz |= pi[m][c] != 0.0;
+          for (int m = 0; m < NQ; ++m) nz |= ldq<RT>(pi[m], c) != 0.0;
         }
       }
       any = __syncthreads_or(nz);
@@ -1183,7 +1213,7 @@ __global__ __launch_bounds__(kBlock) void k_init_conserved(Fields f, StepParams 
   double pv[10], K0 = 1.0, K1 = 0.0, K2 = 0.0, K3 = 0.0;
   if (act) {
 #pragma unroll
-    for (int m = 0; m < 10; ++m) pv[m] = visc ? f.pi[m][c] : 0.0;
+    for (int m = 0; m < 10; ++m) pv[m] = visc ? f.pi1[m][c] : 0.0;  // staged FP64 input
     K0 = f.T[0][c] / tf - pv[0];
     K1 = f.T[1][c] / tf - pv[1];
     K2 = f.T[2][c] / tf - pv[2];
@@ -1198,9 +1228,8 @@ __global__ __launch_bounds__(kBlock) void k_init_conserved(Fields f, StepParams 
   f.u[0][c] = s.u1;
   f.u[1][c] = s.u2;
   f.u[2][c] = s.u3;
-  if (s.e == 0.0 || !visc)
 #pragma unroll
-    for (int m = 0; m < 10; ++m) f.pi[m][c] = 0.0;
+  for (int m = 0; m < 10; ++m) stq_rt(f.pi[m], c, s.e == 0.0 || !visc ? 0.0 : pv[m], f.pf32);
 }
 
 // First step: u*1 from one ideal forward-Euler step; u~^{-1} = 2 u~^0 - u*1.
@@ -1250,7 +1279,7 @@ __global__ __launch_bounds__(kBlock) void k_first_estimate(const EventDesc* __re
 
 // A cell's e, u~ and (VISC) pi~ at the current level; u~ and pi~ read as zero
 // (no loads) where e = 0.
-template <bool VISC, int NQ>
+template <typename RT, bool VISC, int NQ>
 __device__ __forceinline__ void cell_values(const DFields& f, int c, double& e, double& u1,
                                             double& u2, double& u3, double* pc) {
   e = f.e[c];
@@ -1263,7 +1292,7 @@ __device__ __forceinline__ void cell_values(const DFields& f, int c, double& e, 
     u3 = f.u[2][c];
     if (VISC) {
 #pragma unroll
-      for (int m = 0; m < NQ; ++m) pc[m] = f.pi[m][c];
+      for (int m = 0; m < NQ; ++m) pc[m] = ldq<RT>(f.pi[m], c);
     }
   }
 }
@@ -1312,7 +1341,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   if (q.active) {
     const int c = q.c;
     double e, u1, u2, u3, pc[NQ];
-    cell_values<VISC, NQ>(f, c, e, u1, u2, u3, pc);
+    cell_values<RT, VISC, NQ>(f, c, e, u1, u2, u3, pc);
     if (!g.cart) {  // geometric source S_T = (-Tc^{ee}, 0, 0, -Tc^{te})
       const double ut = utau(u1, u2, u3);
       double P, cs2;
@@ -1339,7 +1368,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     const int c = q.c;
     // the cell's values again (cache hits after the face rounds)
     double e, u1, u2, u3, pc[NQ];
-    cell_values<VISC, NQ>(f, c, e, u1, u2, u3, pc);
+    cell_values<RT, VISC, NQ>(f, c, e, u1, u2, u3, pc);
     const double ut = utau(u1, u2, u3);
     double p1[NQ];
     if (VISC) {
@@ -1357,7 +1386,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
       for (int m = 0; m < NQ; ++m) p1[m] = (ut * pc[m] + p.h * R[4 + m]) * inv_uts;
       regulate<BK>(eos, p, e, p1);
 #pragma unroll
-      for (int m = 0; m < NQ; ++m) st_cell(f.pi1[m] + c, p1[m]);
+      for (int m = 0; m < NQ; ++m) stq<RT>(f.pi1[m], c, p1[m]);
       if constexpr (BK) Pi1 = p1[10];
     } else {
 #pragma unroll
@@ -1420,7 +1449,7 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>())
     for (int m = 0; m < NQ; ++m) pc[m] = 0.0;
     if (!vz || p.quiet_r[0] > 0) {
 #pragma unroll
-      for (int m = 0; m < NQ; ++m) pc[m] = f.pi1[m][c];
+      for (int m = 0; m < NQ; ++m) pc[m] = ldq<RT>(f.pi1[m], c);
     }
     double pn[NQ];
 #pragma unroll
@@ -1443,7 +1472,7 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>())
       for (int m = 0; m < NQ; ++m) pin[m] = 0.0;
       if (en != 0.0) {
 #pragma unroll
-        for (int m = 0; m < NQ; ++m) pin[m] = f.pi[m][c];
+        for (int m = 0; m < NQ; ++m) pin[m] = ldq<RT>(f.pi[m], c);
       }
 #pragma unroll
       for (int m = 0; m < NQ; ++m)
@@ -1453,7 +1482,7 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>())
       en = f.e[c];
     }
 #pragma unroll
-    for (int m = 0; m < NQ; ++m) st_cell(f.pi[m] + c, pn[m]);
+    for (int m = 0; m < NQ; ++m) stq<RT>(f.pi[m], c, pn[m]);
     quiet = en == 0.0 && e1 == 0.0;
 #pragma unroll
     for (int m = 0; m < NQ; ++m) quiet = quiet && pc[m] == 0.0 && pn[m] == 0.0;
@@ -1509,7 +1538,7 @@ __attribute__((amdgpu_waves_per_eu(s2t_waves<RT, TX, TY, TZ, BK>()))) void k_sta
     for (int m = 0; m < NT; ++m) pc[m] = 0.0;
     if (VISC && !(e1 == 0.0 && p.vac_zero)) {
 #pragma unroll
-      for (int m = 0; m < NT; ++m) pc[m] = f.pi[m][c];
+      for (int m = 0; m < NT; ++m) pc[m] = ldq<RT>(f.pi[m], c);
     }
     if constexpr (BK) PiN = pc[10];
     if (!g.cart) {

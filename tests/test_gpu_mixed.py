@@ -1,5 +1,6 @@
 """Mixed precision (FP32 reconstruction, fluxes, local speed and shear relaxation
-source; FP64 root solve, geometric source and state) against the FP64 oracle.
+source, pi~ stored in FP32; FP64 root solve, geometric source, e, u~ and T~)
+against the FP64 oracle.
 
 Bar for well-conditioned states: relative error <= 1e-6 in e and in the
 velocity components, in the L2 norm over the grid and in the max norm over the
