@@ -53,6 +53,12 @@ BYTES_PER_CELL_IDEAL = {"stage1": (8 + 5) * 8, "stage2_T": (8 + 4) * 8}
 # stage2_T reads Pi^{n+1} (+1).
 BYTES_PER_CELL_BULK = {"stage1": (23 + 20) * 8, "stage2_pi": (35 + 12) * 8,
                        "stage2_T": (23 + 8) * 8}
+# Mixed precision stores pi~ (and its stage-1 value) in FP32: 4 bytes for each of
+# their 10 values a cell reads or writes (stage1 10 + 10, stage2_pi 20 + 10,
+# stage2_T 10).
+BYTES_PER_CELL_MIXED = {"stage1": 11 * 8 + 10 * 4 + 8 * 8 + 10 * 4,
+                        "stage2_pi": 11 * 8 + 20 * 4 + 10 * 4,
+                        "stage2_T": 12 * 8 + 10 * 4 + 8 * 8}
 # The step's minimum: the state read once and written once, and the stage-1
 # prediction written once and read once (21 + 18 + 18 + 18 values, u~prev rotated
 # by pointer): 600 B per cell-update in FP64.
@@ -578,6 +584,8 @@ def main():
     bpc = BYTES_PER_CELL if p["viscous"] else BYTES_PER_CELL_IDEAL
     if p.get("zetas", 0) > 0 or p.get("baryon", 0):
         bpc = dict(BYTES_PER_CELL, **BYTES_PER_CELL_BULK)
+    if args.precision == 1 and p["viscous"] and bpc is BYTES_PER_CELL:
+        bpc = dict(BYTES_PER_CELL, **BYTES_PER_CELL_MIXED)
     stream = torch.cuda.Stream() if args.graph else None
     g = make_hydro(wl, stream=stream, tile=args.tile, precision=args.precision)
     if args.quiet_skip:
@@ -635,7 +643,8 @@ def main():
         w0 = W.gubser_ideal_33()
         paths["C0_gubser_ideal_33x33x17_fp64"] = single_path(w0, 50, 5)
         say("path: mixed precision")
-        paths["C1_mixed_fp32_fp64"] = single_path(wl, args.steps, 3, bpc=BYTES_PER_CELL,
+        paths["C1_mixed_fp32_fp64"] = single_path(wl, args.steps, 3,
+                                                  bpc=dict(BYTES_PER_CELL, **BYTES_PER_CELL_MIXED),
                                                   precision=1)
         say("path: quiet tiles")
         paths["C1_fp64_quiet_skip"] = single_path(wl, args.steps, 3, quiet=True)
@@ -663,8 +672,8 @@ def main():
         say("path: C4 large event")
         w4 = W.large_event()
         paths["C4_large_385x385x129_fp64"] = single_path(w4, 20, 3, bpc=BYTES_PER_CELL)
-        paths["C4_large_385x385x129_mixed"] = single_path(w4, 20, 3, bpc=BYTES_PER_CELL,
-                                                          precision=1)
+        paths["C4_large_385x385x129_mixed"] = single_path(
+            w4, 20, 3, bpc=dict(BYTES_PER_CELL, **BYTES_PER_CELL_MIXED), precision=1)
         for k in ("C4_large_385x385x129_fp64", "C4_large_385x385x129_mixed"):
             paths[k]["note"] = "first 20 of the 1000 steps (the rate is per step)"
         say("path: freeze-out surface and spectra")
