@@ -979,15 +979,15 @@ constexpr int pi_waves() {
   return !NOCAP && 163840 / (int)(lds_doubles<TX, TY, TZ, NC>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
 }
 
-// Waves per SIMD asked of stage 2T: four without bulk (its streamed faces need
-// 143 VGPRs in FP64; under the four-wave cap of 128 a few spill, and the pass
-// still runs faster: 0.46 -> 0.42 ms on the 201x201x105 hotspot grid, 0.86 ->
-// 0.84 ms on the grid without vacuum; FP32: 117 VGPRs, no spill); with bulk as
-// the other stage-2 passes.  Four waves on stage 2pi gain on the hotspot grid and
+// Waves per SIMD asked of stage 2T: four without bulk in FP64 (its streamed faces
+// need 143 VGPRs; under the four-wave cap of 128 a few spill, and the pass still
+// runs faster: 0.46 -> 0.42 ms on the 201x201x105 hotspot grid, 0.86 -> 0.84 ms
+// on the grid without vacuum), five in FP32 (95 VGPRs, no spill: 0.36 -> 0.33 ms
+// and 0.64 -> 0.60 ms); with bulk as the other stage-2 passes.  Four waves on stage 2pi gain on the hotspot grid and
 // lose on the dense one, so it keeps three.
 template <typename RT, int TX, int TY, int TZ, bool BK>
 constexpr int s2t_waves() {
-  return !BK ? 4 : pi_waves<RT, TX, TY, TZ, false>();
+  return !BK ? (sizeof(RT) == 4 ? 5 : 4) : pi_waves<RT, TX, TY, TZ, false>();
 }
 
 // u~^tau of spatial components.
@@ -1302,14 +1302,15 @@ __device__ __forceinline__ void cell_values(const DFields& f, int c, double& e, 
 // The cell's sources come before the face rounds, so the shear source's
 // gradients and the divergence accumulators are never live together: 137 VGPRs
 // in FP64 (three waves per SIMD, which its 45 KB of LDS also allows; 161 with the
-// sources after the rounds), 107 in FP32 (four waves; 134 before, and the pass
-// went from 0.54 to 0.49 ms on the 201x201x105 hotspot grid).  The bulk variant
+// sources after the rounds), 103 in FP32 (four waves; 134 before, and the pass
+// went from 0.54 to 0.49 ms on the 201x201x105 hotspot grid), which asks for
+// five (96 VGPRs with 14 spilled: 0.43 -> 0.41 ms there).  The bulk variant
 // and the network variants ask for three waves (uncapped, the matrix-core
 // results take 32 accumulation registers on top; capped, they stay in VGPRs
 // without spills), the network variant with the lambda_1 term two (else one).
 template <typename RT, int TX, int TY, int TZ, bool VISC, bool NET, bool L1, bool BK = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
-    BK || (NET && !L1) ? 3 : (NET ? 2 : 1)))) void k_stage1(const EventDesc* __restrict__ evs,
+    BK || (NET && !L1) ? 3 : (NET ? 2 : (sizeof(RT) == 4 ? 5 : 1))))) void k_stage1(const EventDesc* __restrict__ evs,
                                                     GroupTable gt) {
   constexpr int NQ = BK ? 12 : 10;
   __shared__ RT lds[lds_doubles<TX, TY, TZ, 4 + NQ, true>()];
