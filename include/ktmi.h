@@ -47,8 +47,10 @@ enum {
 
 enum { KTMI_FP64 = 0, KTMI_MIXED = 1 };                               /* precision */
 /* Start of the per-cell root solve: the cell's e from the previous stage, E
- * itself (cold), or the learned guess (ktmi_set_mlp).  The result does not
- * depend on the start beyond the solve tolerance (a polish step follows). */
+ * itself (cold), or the learned guess (ktmi_set_mlp; used by the initial state's
+ * and the predictor's solves, while the corrector's solve starts from the
+ * predictor's e, which is closer).  The result does not depend on the start
+ * beyond the solve tolerance (a polish step follows). */
 enum { KTMI_GUESS_PREV = 0, KTMI_GUESS_COLD = 1, KTMI_GUESS_MLP = 2 };
 enum { KTMI_MLP_FP32 = 0, KTMI_MLP_BF16 = 1 }; /* forward of the learned guess */
 

@@ -516,13 +516,14 @@ static int enqueue_class_step(ktmi_handle* h, hipStream_t s, int tile, int preci
     if (rc) return rc;
     rc = launch(h, K_STAGE2PI, [&] { launch_class(p2, s, tile, precision, false, evs, gt); });
     if (rc) return rc;
-    return launch(h, K_STAGE2T, [&] { launch_class(p3, s, tile, precision, nn, evs, gt); });
+    // stage 2T starts its root solves from the predictor's e (no network)
+    return launch(h, K_STAGE2T, [&] { launch_class(p3, s, tile, precision, false, evs, gt); });
   }
   rc = launch(h, K_STAGE1,
               [&] { launch_class(PASS_STAGE1_I, s, tile, precision, net, evs, gt); });
   if (rc) return rc;
   return launch(h, K_STAGE2T,
-                [&] { launch_class(PASS_STAGE2_T_I, s, tile, precision, net, evs, gt); });
+                [&] { launch_class(PASS_STAGE2_T_I, s, tile, precision, false, evs, gt); });
 }
 
 static bool uses_net(const ktmi_handle* h) { return h->d.guess == KTMI_GUESS_MLP; }

@@ -33,10 +33,12 @@ __host__ __device__ inline uint32_t to_bf16(float x) {
   return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
 }
 
-// tanh from its exponential form, tanh x = 1 - 2 / (e^{2x} + 1): saturates to
-// +-1 for large |x|, absolute error of a few FP32 ulps near 0.
+// tanh from its exponential form, tanh x = 1 - 2 / (e^{2x} + 1), with the
+// hardware base-2 exponential and reciprocal (about one ulp each; no division
+// sequence): saturates to +-1 for large |x|, absolute error of a few FP32 ulps.
 __device__ __forceinline__ float mlp_tanh(float x) {
-  return 1.0f - 2.0f / (__expf(2.0f * x) + 1.0f);
+  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);  // e^{2x} = 2^{2x log2 e}
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
 }
 
 // Features of (E, M^2); lo = lower end of the root bracket.
@@ -146,9 +148,12 @@ __device__ __forceinline__ float mlp_z_mfma(const float* __restrict__ prm,
   return z;
 }
 
+// guess = lo + sigmoid(z) (E - lo); the sigmoid in FP32 (hardware exponential
+// and reciprocal), clamped to [0, 1] so the guess stays inside the bracket.
 __device__ __forceinline__ double mlp_guess_from_z(float z, double E, double lo) {
-  const double s = 1.0 / (1.0 + exp(-(double)z));
-  return lo + s * (E - lo);
+  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);  // e^{-z}
+  const float s = fminf(fmaxf(__builtin_amdgcn_rcpf(1.0f + e), 0.0f), 1.0f);
+  return lo + (double)s * (E - lo);
 }
 
 // Guess of one lane (FP32 forward; divergent lanes allowed).

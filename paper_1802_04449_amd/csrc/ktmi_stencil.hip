@@ -26,9 +26,9 @@ void launch_tile(dim3 g, dim3 b, hipStream_t s, const EventDesc* evs, const Grou
 #elif KTMI_PASS == 3
   hipLaunchKernelGGL((k_stage2_pi<KTMI_RT, X, Y, Z, false>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 4
-  hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, true, N>), g, b, 0, s, evs, gt);
+  hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, true>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 5
-  hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, false, N>), g, b, 0, s, evs, gt);
+  hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, false>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 6
   hipLaunchKernelGGL((k_stage1<KTMI_RT, X, Y, Z, true, N, true>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 7
@@ -38,14 +38,15 @@ void launch_tile(dim3 g, dim3 b, hipStream_t s, const EventDesc* evs, const Grou
 #elif KTMI_PASS == 9
   hipLaunchKernelGGL((k_stage2_pi<KTMI_RT, X, Y, Z, false, true>), g, b, 0, s, evs, gt);
 #elif KTMI_PASS == 10
-  hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, true, false, true>), g, b, 0, s, evs, gt);
+  hipLaunchKernelGGL((k_stage2_T<KTMI_RT, X, Y, Z, true, true>), g, b, 0, s, evs, gt);
 #else
 #error "KTMI_PASS out of range"
 #endif
 }
 
-// passes without a root solve, and the bulk passes, have no network instances
-constexpr bool kHasNet = KTMI_PASS != 0 && KTMI_PASS != 3 && KTMI_PASS < 7;
+// only the stage-1 passes without bulk take the network's guess (stage 2T starts
+// its root solve from the predictor's e; the other passes have no root solve)
+constexpr bool kHasNet = KTMI_PASS == 1 || KTMI_PASS == 2 || KTMI_PASS == 6;
 
 }  // namespace
 

@@ -239,7 +239,9 @@ def test_learned_guess_matches_oracle(trained, mode):
 def test_learned_guess_saves_iterations(trained):
     """Held-out event: mean root-solve iterations (including the polish step)
     with the network's start vs the cold start (E) and the previous stage's e.
-    Measured on this case: prev 3.46, cold 3.62, network 3.13 (FP32 and BF16)."""
+    The network starts the predictor's solves; the corrector's start from the
+    predictor's e in every mode.  Measured on this case: prev 3.46, cold 3.62,
+    network 3.22 (FP32 and BF16)."""
     import paper_1802_04449_amd as K
     wl = W.hotspots_viscous(steps=10, seed=24, **GRID)
     _say("learned guess gain")
