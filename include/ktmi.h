@@ -78,9 +78,9 @@ typedef struct ktmi_desc {
     int newton_maxit;    /* iteration cap of the root solve */
     double pi_reg;       /* cap on sqrt(|pi~:pi~|)/(e+P); <= 0 disables */
     int precision;       /* KTMI_FP64, or KTMI_MIXED: FP32 reconstruction, fluxes, local
-                            speed and shear relaxation source, and pi~ (with Pi and n)
-                            stored in FP32; FP64 root solve, geometric source, e, u~, T~
-                            and accumulators.  ktmi_read returns every field in FP64. */
+                            speed and shear relaxation source, and pi~ stored in FP32;
+                            FP64 root solve, geometric source, e, u~, T~ and
+                            accumulators.  ktmi_read returns every field in FP64. */
     int guess;           /* KTMI_GUESS_* */
     int tile;            /* workgroup tile shape index (ktmi_tile_shape); -1 = automatic */
     double taupi_coef;   /* tau_pi = taupi_coef (eta/s) hbarc / T; 5 in Sec. II.  Must be > 0

@@ -14,6 +14,7 @@ import json
 import os
 import sys
 
+import numpy as np
 import pytest
 
 from hydro_inputs import workloads as W
@@ -88,3 +89,49 @@ def test_mixed_large_event_385x385x129():
     dense = G.precision_errors(gf, of, eps_min=1.0)
     for k in GATED:
         assert dense[k]["max_hydro"] <= BAR, (k, dense[k])
+
+
+def _is_fp32(x):
+    return np.array_equal(x, x.astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("case", ["gubser_viscous", "bulk_baryon"])
+def test_mixed_stores_pi_in_fp32(case):
+    """Storage of pi~ on the mixed path: kept in FP32 and widened by ktmi_read, so
+    every value read back is an FP32 number; the initial pi~ is the input rounded
+    to FP32 where e >= eps_cut and zero below it; the FP64 path returns the input
+    exactly.  Cases: the Sec. V.C viscous Gubser state (nonzero initial pi~), and
+    a hotspot state with the baryon density transported (nonzero initial n,
+    Pi = 0; bulk and baryon run in FP64 only, so only the FP64 staging of the
+    initial Pi and n is checked)."""
+    import paper_1802_04449_amd as K
+    if case == "gubser_viscous":
+        wl = W.gubser_viscous(n=21, ne=3, steps=2)
+        names = [f"pi{m}" for m in range(10)]
+        src = {f"pi{m}": wl.ic["pi"][m] for m in range(10)}
+    else:
+        wl = W.hotspots_bulk(nx=23, ny=19, ne=7, dx=0.35, dy=0.35, de=0.4, steps=2, seed=3)
+        names = [f"pi{m}" for m in range(10)] + ["Pi", "nb"]
+        src = {"nb": wl.ic["nb"]}
+    print(f"[gpu-case] pi~ storage {wl.name}", flush=True)
+    cut = G.oracle_params(wl.params).eps_cut
+    live = wl.ic["eps"] >= cut
+    precs = (K.KTMI_FP64, K.KTMI_MIXED) if case == "gubser_viscous" else (K.KTMI_FP64,)
+    for prec in precs:
+        d = dict(wl.params)
+        d["precision"] = prec
+        g = K.Hydro(**d)
+        g.set_eos(wl.eos)
+        g.set_initial(wl.ic)
+        got = {n: g.read_numpy(n) for n in names}
+        for n, x in src.items():
+            want = np.where(live, x, 0.0)
+            if prec == K.KTMI_MIXED:
+                want = want.astype(np.float32).astype(np.float64)
+            np.testing.assert_array_equal(got[n], want, err_msg=f"{case} {prec} {n}")
+        if prec == K.KTMI_MIXED:
+            assert all(_is_fp32(v) for v in got.values())
+            g.step(2)
+            after = {n: g.read_numpy(n) for n in names}
+            assert all(_is_fp32(v) for v in after.values())
+            assert any(np.abs(v).max() > 0 for v in after.values())
