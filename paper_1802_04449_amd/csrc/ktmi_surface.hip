@@ -160,16 +160,26 @@ constexpr int kWaves = kSurfBlock / 64;
 constexpr int kIt = 16;
 constexpr long kSpan = (long)kIt * kSurfBlock;
 
+// Workgroup b of a launch of G runs on XCD b % 8; the span it takes is
+// xcd_span(b, G): the spans [k G/8, (k+1) G/8) (remainder spread over the first
+// XCDs) go to XCD k in order, so the planes a workgroup shares with the next
+// span stay in one XCD's L2.  A bijection on [0, G).
+__device__ __forceinline__ long xcd_span(long b, long G) {
+  const long per = G / 8, rem = G % 8, k = b % 8;
+  return k * per + (k < rem ? k : rem) + b / 8;
+}
+
 // Pass 1: straddle masks and straddling hypercubes per workgroup.
 __global__ __launch_bounds__(kSurfBlock) void k_surface_count(SurfaceArgs a, int nblk) {
   __shared__ int wc[kWaves];
   const long ncube = cube_count(a.nx, a.ny, a.ne);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   gullong* blk = (gullong*)a.blocks;
-  gullong* masks = blk + nblk + (long)blockIdx.x * kIt * kWaves;
+  const long sb = xcd_span(blockIdx.x, nblk);
+  gullong* masks = blk + nblk + sb * kIt * kWaves;
   int nw = 0;
   for (int it = 0; it < kIt; ++it) {
-    const long id = (long)blockIdx.x * kSpan + (long)it * kSurfBlock + threadIdx.x;
+    const long id = sb * kSpan + (long)it * kSurfBlock + threadIdx.x;
     const bool cross = id < ncube && straddles(a, (int)id);
     const unsigned long long mask = __ballot(cross);
     if (lane == 0) masks[it * kWaves + wave] = mask;
@@ -181,7 +191,7 @@ __global__ __launch_bounds__(kSurfBlock) void k_surface_count(SurfaceArgs a, int
     int n = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) n += wc[w];
-    blk[blockIdx.x] = (unsigned long long)n;
+    blk[sb] = (unsigned long long)n;
   }
 }
 
@@ -230,7 +240,8 @@ __global__ __launch_bounds__(1024) void k_surface_offsets(SurfaceArgs a, int nbl
 __global__ __launch_bounds__(kSurfBlock) void k_surface_compact(SurfaceArgs a, int nblk) {
   __shared__ long long moff[kIt * kWaves];
   const gullong* blk = (const gullong*)a.blocks;
-  const gullong* masks = blk + nblk + (long)blockIdx.x * kIt * kWaves;
+  const long sb = xcd_span(blockIdx.x, nblk);
+  const gullong* masks = blk + nblk + sb * kIt * kWaves;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (wave == 0) {  // exclusive offsets of the kIt * kWaves masks (one wave, 64 masks)
     static_assert(kIt * kWaves == 64, "one mask per lane");
@@ -241,14 +252,14 @@ __global__ __launch_bounds__(kSurfBlock) void k_surface_compact(SurfaceArgs a, i
       const long long y = __shfl_up(x, o);
       if (lane >= o) x += y;
     }
-    moff[lane] = (long long)blk[blockIdx.x] + x - c;
+    moff[lane] = (long long)blk[sb] + x - c;
   }
   __syncthreads();
   for (int it = 0; it < kIt; ++it) {
     const unsigned long long mask = masks[it * kWaves + wave];
     if (!((mask >> lane) & 1ull)) continue;
     const long long slot = moff[it * kWaves + wave] + __popcll(mask & ((1ull << lane) - 1ull));
-    const long id = (long)blockIdx.x * kSpan + (long)it * kSurfBlock + threadIdx.x;
+    const long id = sb * kSpan + (long)it * kSurfBlock + threadIdx.x;
     if (slot < (long long)a.capacity) ((gdouble*)a.out)[slot * kSurfRec] = (double)id;
   }
 }
@@ -275,8 +286,15 @@ __global__ __launch_bounds__(kSurfBlock) void k_surface_elem(SurfaceArgs a) {
   const int mu = t >> 1, side = t & 1;
   const double ext[4] = {a.tauB - a.tauA, a.dx, a.dy, a.de};
   const long ncell = (long)a.nx * a.ny * a.ne;
-  for (long base = (long)blockIdx.x * kElemPerBlock; base < n;
-       base += (long)gridDim.x * kElemPerBlock) {
+  // contiguous runs of element groups per workgroup, the runs of one XCD adjacent
+  // (neighbouring elements share corner cells); the first min(grid, groups)
+  // workgroups share the groups, so every XCD gets work
+  const long ngrp = (n + kElemPerBlock - 1) / kElemPerBlock;
+  const long G = (long)gridDim.x < ngrp ? (long)gridDim.x : ngrp;
+  if ((long)blockIdx.x >= G) return;  // whole workgroup: before any barrier
+  const long per = (ngrp + G - 1) / G, g0 = xcd_span(blockIdx.x, G) * per;
+  const long g1 = g0 + per < ngrp ? g0 + per : ngrp;
+  for (long base = g0 * kElemPerBlock; base < g1 * kElemPerBlock; base += kElemPerBlock) {
     const long slot = base + g;
     const bool act = slot < n;
     gdouble* r = outp + (act ? slot : 0) * kSurfRec;
