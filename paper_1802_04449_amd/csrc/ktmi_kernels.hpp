@@ -1419,7 +1419,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 }
 
 // Stage 2, part 1 (tau_{n+1}): pi^{n+1} = [ (u^n pi^n + u* pi')/2 + h/2 R_pi(e', u', pi') ] / u'^tau.
-// BK: Pi^{n+1} and n^{n+1} the same way.
+// BK: Pi^{n+1} and n^{n+1} the same way.  The relaxation source comes before the
+// face rounds: 123 VGPRs in FP64 (four waves per SIMD; 139 and three with the
+// source after them: 0.45 -> 0.40 ms on the 201x201x105 hotspot grid, 1.04 ->
+// 0.96 ms without vacuum), 91 in FP32 (five waves: 0.32 -> 0.30 ms).
 template <typename RT, int TX, int TY, int TZ, bool L1, bool BK = false>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>()))) void k_stage2_pi(
@@ -1435,9 +1438,26 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>())
   if (tile_asleep<TX, TY, TZ>(p, cx.tg, cx.qcur, cx.tile)) return;
   const double tf = g.cart ? 1.0 : g.tau;
   double R[4 + NQ];
+#pragma unroll
+  for (int k = 0; k < 4 + NQ; ++k) R[k] = 0.0;
+  // The cell's relaxation source first (as in stage 1: its gradients' registers
+  // are free again before the face rounds accumulate the divergence onto it).
+  // Where e' = 0 the regulator zeroes pi^{n+1} (vac_zero): no source needed.
+  if (q.active) {
+    const int c = q.c;
+    const double e1 = f.e1[c];
+    if (!(e1 == 0.0 && p.vac_zero) && e1 >= p.eps_cut) {
+      double pc[NQ], S[NQ];
+#pragma unroll
+      for (int m = 0; m < NQ; ++m) pc[m] = ldq<RT>(f.pi1[m], c);
+      pi_source<RT, L1, BK>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
+#pragma unroll
+      for (int m = 0; m < NQ; ++m) R[4 + m] = S[m];
+    }
+  }
   // pi~' was regulated with e^n in stage 1: zero wherever e^n is (vac_zero)
-  tile_divergence<RT, TX, TY, TZ, false, true, 2, BK>(f.e1, f.u1, f.pi1, p, eos, tf, q, R, lds,
-                                                      f.e);
+  tile_divergence<RT, TX, TY, TZ, false, true, 2, BK, false, false, false>(
+      f.e1, f.u1, f.pi1, p, eos, tf, q, R, lds, f.e);
   bool quiet = true;  // this cell's part of the quiet-tile test
   if (q.active) {
     const int c = q.c;
@@ -1457,12 +1477,6 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>())
     for (int m = 0; m < NQ; ++m) pn[m] = 0.0;
     double en = 0.0;
     if (!vz) {
-      if (e1 >= p.eps_cut) {
-        double S[NQ];
-        pi_source<RT, L1, BK>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) R[4 + m] += S[m];
-      }
       en = f.e[c];
       const double a1 = f.u[0][c], a2 = f.u[1][c], a3 = f.u[2][c];
       const double utn = utau(a1, a2, a3);
