@@ -170,7 +170,8 @@ int ktmi_set_eos_table(ktmi_handle *h, double e0, double de, int n, const double
  * pi~ blocks (pi10 may be NULL for pi~ = 0; ignored in ideal mode).  Applies the
  * cutoff, forms T~^{tau mu}, and estimates u~^{-1} by one ideal forward-Euler
  * step (Sec. III: ideal hydrodynamics estimates u*1 on the first step).
- * Resets the diagnostics. */
+ * Resets the diagnostics.  With KTMI_MIXED the stored pi~ is the input rounded
+ * to FP32 (T~ is formed from the FP64 input). */
 int ktmi_set_initial_primitive(ktmi_handle *h, const double *e, const double *ux,
                                const double *uy, const double *ue, const double *pi10);
 
