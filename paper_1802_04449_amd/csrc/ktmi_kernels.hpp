@@ -966,14 +966,15 @@ constexpr int lds_doubles_allf() {
   return 4 * (L::F0 + L::F1 + L::F2);
 }
 
-// Waves per SIMD asked of the stage-2 passes: 3 where the tile's LDS leaves
-// room for three workgroups per CU (160 KB), else no bound.  Capping their
-// registers for a third wave is a net gain (stage2_pi 10-16%, stage2_T 1-5% on
-// the 201x201x105 grids, with a few spilled registers; the lambda_1 variant 8%
-// in FP64 with 60 bytes of spill, 13% in FP32); stage1 loses from the same cap,
-// so it has none, nor has the bulk variant of stage2_pi (it spills 96 bytes a
-// lane under the cap: 1.06 ms against 0.75 ms without it; its stage2_T keeps the
-// cap).  NOCAP = true asks for no bound.
+// Waves per SIMD asked of the stage-2 passes: at least 3 where the tile's LDS
+// leaves room for three workgroups per CU (160 KB), else no bound.  The cap was
+// a net gain when these passes needed more registers (stage2_pi 10-16%,
+// stage2_T 1-5% on the 201x201x105 grids, with a few spilled registers; the
+// lambda_1 variant 8% in FP64 with 60 bytes of spill, 13% in FP32); the plain
+// stage2_pi now fits 123 VGPRs (FP64, four waves) and 91 (FP32, five) without
+// it.  Stage1 loses from the cap, so it has none, nor has the bulk variant of
+// stage2_pi (it spilled 96 bytes a lane under the cap: 1.06 ms against 0.75 ms
+// without it; its stage2_T keeps the cap).  NOCAP = true asks for no bound.
 template <typename RT, int TX, int TY, int TZ, bool NOCAP, int NC = 14>
 constexpr int pi_waves() {
   return !NOCAP && 163840 / (int)(lds_doubles<TX, TY, TZ, NC>() * sizeof(RT) + 512) >= 3 ? 3 : 1;
@@ -983,8 +984,7 @@ constexpr int pi_waves() {
 // need 143 VGPRs; under the four-wave cap of 128 a few spill, and the pass still
 // runs faster: 0.46 -> 0.42 ms on the 201x201x105 hotspot grid, 0.86 -> 0.84 ms
 // on the grid without vacuum), five in FP32 (95 VGPRs, no spill: 0.36 -> 0.33 ms
-// and 0.64 -> 0.60 ms); with bulk as the other stage-2 passes.  Four waves on stage 2pi gain on the hotspot grid and
-// lose on the dense one, so it keeps three.
+// and 0.64 -> 0.60 ms); with bulk as the other stage-2 passes.
 template <typename RT, int TX, int TY, int TZ, bool BK>
 constexpr int s2t_waves() {
   return !BK ? (sizeof(RT) == 4 ? 5 : 4) : pi_waves<RT, TX, TY, TZ, false>();
