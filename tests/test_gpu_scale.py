@@ -12,6 +12,9 @@
   1e-12 of the oracle, test_gpu_parity.py), the per-field error recorded every
   100 steps next to the FP64 path's own response to an input perturbation of
   the FP32 roundoff (the state is ill-conditioned in its dilute cells).
+- The benchmark configuration (201x201x105 hotspots) over its whole 200-step run
+  in mixed precision against the FP64 GPU path: within 1e-6 in e and u~ on hydro
+  cells at every checkpoint; the grid-wide L2 norm under the conditioning-aware bar.
 
 Fields are compared on the device; only the oracle comparisons copy to the host.
 """
@@ -214,3 +217,43 @@ def test_large_event_mixed_whole_run():
         for k in ("eps", "ux", "uy", "ue"):
             bar = max(BAR, 10.0 * rec["fp64_perturbed"][k]["max_hydro"])
             assert rec["mixed"][k]["max_hydro"] <= bar, (rec["step"], k, rec["mixed"][k], bar)
+
+
+def test_benchmark_config_mixed_whole_run():
+    """The benchmark configuration (201x201x105 hotspots, eta/s = 0.08) over its
+    whole 200-step run: mixed precision against the FP64 GPU path (itself within
+    1e-12 of the oracle), errors at steps 50, 100, 150, 200 for e and u~ next to
+    the FP64 path's own response to an input perturbation of the FP32 roundoff
+    2^-24.  On the cells where hydrodynamics applies (e >= 0.1 GeV/fm^3) the
+    reduced-precision bar holds as it stands, <= 1e-6 at every checkpoint
+    (measured: at most 1.7e-7 in e and 7.3e-8 in u~).  The L2 norm over the whole
+    grid is dominated after ~150 steps by the dilute, nearly light-like cells at
+    the fireball's edge, which the FP64 path itself moves by as much under the
+    2^-24 perturbation (u~ 8.6e-2 at step 200, mixed 9.6e-2), so it is gated at
+    max(1e-6, 10 x) that response."""
+    import paper_1802_04449_amd as K
+    wl = W.hotspots_viscous(steps=200)
+    wp = G.perturbed(wl, rel=2.0 ** -24, seed=5)
+    _say(f"benchmark configuration {wl.name}: FP64, FP64 with perturbed input, mixed; 200 steps")
+    a = _make(wl, None)
+    b = _make(wl, None, precision=K.KTMI_MIXED)
+    c = _make(wp, None)
+    names = ["eps", "ux", "uy", "ue"]
+    curve = []
+    for chunk in range(4):
+        for h in (a, b, c):
+            h.step(50)
+        fa, fb, fc = (_dev_fields(h, names) for h in (a, b, c))
+        err, sens = _precision_errors_dev(fb, fa), _precision_errors_dev(fc, fa)
+        curve.append({"step": 50 * (chunk + 1), "tau": a.diag()["tau"], "mixed": err,
+                      "fp64_perturbed": sens})
+        _say(f"step {50 * (chunk + 1)}: " + ", ".join(
+            f"{k} max {err[k]['max_hydro']:.1e} (fp64 perturbed {sens[k]['max_hydro']:.1e})"
+            for k in names))
+        del fa, fb, fc
+    _report("benchmark_config_mixed_whole_run", curve)
+    for rec in curve:
+        for k in names:
+            assert rec["mixed"][k]["max_hydro"] <= BAR, (rec["step"], k, rec["mixed"][k])
+            bar = max(BAR, 10.0 * rec["fp64_perturbed"][k]["l2"])
+            assert rec["mixed"][k]["l2"] <= bar, (rec["step"], k, rec["mixed"][k], bar)
