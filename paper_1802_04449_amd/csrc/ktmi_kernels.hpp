@@ -1573,7 +1573,10 @@ __attribute__((amdgpu_waves_per_eu(s2t_waves<RT, TX, TY, TZ, BK>()))) void k_sta
     for (int nu = 0; nu < 4; ++nu) {
       const double t0 = f.T[nu][c];
       Tn[nu] = t0 + 0.5 * ((f.T1[nu][c] - t0) + p.h * R[nu]);
-      st_cell(f.T[nu] + c, Tn[nu]);
+      // T~^{n+1} goes over T~^n: a value that is bitwise unchanged (a vacuum
+      // tile's cells, where no flux or source acts) is already in memory
+      if (__builtin_bit_cast(long long, Tn[nu]) != __builtin_bit_cast(long long, t0))
+        st_cell(f.T[nu] + c, Tn[nu]);
     }
     const double inv_tf1 = 1.0 / (g.cart ? 1.0 : g.tau1);
 #pragma unroll
