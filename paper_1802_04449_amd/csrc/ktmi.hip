@@ -76,6 +76,8 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(const EventDesc* __restric
   const gdouble* part = (const gdouble*)E.f.partial;
   const bool mx = is_max_slot(s);
   double x = 0.0, y = 0.0;  // stage1, stage2T
+  // unrolled so that several rounds' loads are in flight; the folds keep their order
+#pragma unroll 8
   for (int b = threadIdx.x; b < nblk; b += kRedBlock) {
     const double a = part[(size_t)s * nblk + b];
     const double c = part[(size_t)(kNP + s) * nblk + b];
