@@ -354,9 +354,10 @@ static int max_tiles(const ktmi_desc* d) {
   return m;
 }
 
-// Doubles reserved for the quiet-tile flags: 3 ints per tile of the largest grid.
+// Doubles reserved for the per-tile flags: 4 ints per tile of the largest grid
+// (quiet flags by clock parity, the stage-2pi part, and stage 1's T~' = T~^n).
 static size_t quiet_doubles(const ktmi_desc* d) {
-  return ((size_t)3 * max_tiles(d) + 63) / 64 * 32;
+  return ((size_t)4 * max_tiles(d) + 63) / 64 * 32;
 }
 
 static const int kNumFields = 39;  // e, u(3), up(3), pi(10), T(4), e1, u1(3), pi1(10), T1(4)
@@ -725,7 +726,7 @@ int ktmi_bind(ktmi_handle* h, void* ws, size_t bytes, void* stream) {
   rest += (2 * (size_t)max_tiles(&h->d) * kNP + 31) / 32 * 32;
   f.acc = rest;
   rest += 32;
-  f.quiet = (int*)rest;  // 3 x max tiles flags
+  f.quiet = (int*)rest;  // 4 x max tiles flags
   rest += quiet_doubles(&h->d);
   h->eos_store = rest;
   rest += 3 * (size_t)kEosMaxRows;                       // FP64 table

@@ -64,7 +64,8 @@ struct Fields {
   double* T1[4];
   double* partial;  // [2][kNP][nblk]: stage1 then stage2T, slot-major
   double* acc;      // [16] accumulated diagnostics
-  int* quiet;       // [3][ntiles]: quiet flags by clock parity (2), stage-2pi part (1)
+  int* quiet;       // [4][ntiles]: quiet flags by clock parity (2), stage-2pi part (1),
+                    // stage 1 T~' = T~^n (1)
   long fstride;     // elements from one field to the next
   int pf32;         // the pi~ blocks (pi, pi1) hold FP32 values (mixed precision)
 };
@@ -176,6 +177,7 @@ struct Ctx {
   const gint* qcur;  // quiet flags after the previous step
   gint* qnext;       // quiet flags after this step
   gint* qpi;         // this step's stage-2pi part of the flags
+  gint* t1same;      // this step's stage-1 flags: the tile's T~' equals T~^n (not stored)
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -272,6 +274,7 @@ __device__ __forceinline__ Ctx load_ctx(const EventDesc* __restrict__ evs, const
   c.qcur = c.f.quiet + (odd ? nt : 0);
   c.qnext = c.f.quiet + (odd ? 0 : nt);
   c.qpi = c.f.quiet + 2 * nt;
+  c.t1same = c.f.quiet + 3 * nt;
   return c;
 }
 
@@ -1365,6 +1368,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
                                      false>(f.e, f.u, f.pi, p, eos, tf, q, R, lds);
   v[P_CFL] = cfl * p.h;
   double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0, Pi1 = 0.0;
+  double T1[4];
+  bool t1same = true;  // T~' = T~^n bitwise in this cell (no flux or source)
   if (q.active) {
     const int c = q.c;
     // the cell's values again (cache hits after the face rounds)
@@ -1393,17 +1398,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int m = 0; m < NQ; ++m) p1[m] = 0.0;
     }
-    double T1[4];
 #pragma unroll
     for (int nu = 0; nu < 4; ++nu) {
-      T1[nu] = f.T[nu][c] + p.h * R[nu];
-      st_cell(f.T1[nu] + c, T1[nu]);
+      const double t0 = f.T[nu][c];
+      T1[nu] = t0 + p.h * R[nu];
+      t1same = t1same && __builtin_bit_cast(long long, T1[nu]) == __builtin_bit_cast(long long, t0);
     }
     const double inv_tf1 = 1.0 / (g.cart ? 1.0 : g.tau1);
 #pragma unroll
     for (int nu = 0; nu < 4; ++nu) K[nu] = T1[nu] * inv_tf1 - p1[nu];
     prev = e;
   }
+  // A tile whose T~' equals T~^n in every cell (a vacuum tile: no flux, no
+  // source) does not store it; stage 2T reads T~^n for it instead (the flag is
+  // written every step, so no state carries over between steps).
+  const int all_same = __syncthreads_and(t1same);
+  if (!all_same && q.active) {
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) st_cell(f.T1[nu] + q.c, T1[nu]);
+  }
+  if (threadIdx.x == 0) cx.t1same[cx.tile] = all_same;
   const double x0 = root_guess<NET>(p, q.active, K[0], K[1], K[2], K[3], prev);
   if (q.active) {
     const int c = q.c;
@@ -1545,6 +1559,7 @@ __attribute__((amdgpu_waves_per_eu(s2t_waves<RT, TX, TY, TZ, BK>()))) void k_sta
       f.e1, f.u1, f.pi, p, eos, tf, q, R, lds);
   v[P_CFL] = cfl * p.h;
   double K[4] = {1.0, 0.0, 0.0, 0.0}, prev = 0.0, PiN = 0.0;
+  const bool t1s = cx.t1same[cx.tile] != 0;
   if (q.active) {
     const int c = q.c;
     const double e1 = f.e1[c], u1 = f.u1[0][c], u2 = f.u1[1][c], u3 = f.u1[2][c];
@@ -1572,7 +1587,11 @@ __attribute__((amdgpu_waves_per_eu(s2t_waves<RT, TX, TY, TZ, BK>()))) void k_sta
 #pragma unroll
     for (int nu = 0; nu < 4; ++nu) {
       const double t0 = f.T[nu][c];
-      Tn[nu] = t0 + 0.5 * ((f.T1[nu][c] - t0) + p.h * R[nu]);
+      // stage 1 left T~' = T~^n unstored in such a tile: the loaded value is
+      // stale there and replaced (loading it anyway keeps the loads together)
+      const double t1l = f.T1[nu][c];
+      const double t1 = t1s ? t0 : t1l;
+      Tn[nu] = t0 + 0.5 * ((t1 - t0) + p.h * R[nu]);
       // T~^{n+1} goes over T~^n: a value that is bitwise unchanged (a vacuum
       // tile's cells, where no flux or source acts) is already in memory
       if (__builtin_bit_cast(long long, Tn[nu]) != __builtin_bit_cast(long long, t0))
