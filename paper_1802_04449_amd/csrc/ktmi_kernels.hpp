@@ -20,6 +20,9 @@
 // Template kernels only: the stencil passes are instantiated per (pass,
 // arithmetic type) in ktmi_stencil.hip objects, the rest in ktmi.hip.
 #pragma once
+#ifndef KTMI_PI1_SPARSE
+#define KTMI_PI1_SPARSE 1
+#endif
 #ifndef KTMI_S2PI_STREAM
 #define KTMI_S2PI_STREAM 1
 #endif
@@ -384,9 +387,18 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
   // regulated with is zero when the regulator zeroes it there (vac_zero): the
   // pass's own e (stage 2T), or ez (stage 2pi: e^n), then also tested here;
   // without vac_zero such a face is evaluated in full.
+  // SPARSE: stage 1 leaves pi~' unstored where e^n = 0 (vac_zero), so stage 2pi
+  // reads it masked by e^n (ez), as stage 1 masks pi~^n by e^n
+  constexpr bool SPARSE = KTMI_PI1_SPARSE && PI_SRC == 2 && !BK;
+  const bool zmask = SPARSE && ez.p != nullptr && p.vac_zero;
+  double ezv[4] = {1.0, 1.0, 1.0, 1.0};
+  if (zmask) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ezv[t] = ez[idx[t]];
+  }
   if (PI_SRC == 2 && vac && ez.p != nullptr && p.vac_zero) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) vac = vac && ez[idx[t]] == 0.0;
+    for (int t = 0; t < 4; ++t) vac = vac && (zmask ? ezv[t] : ez[idx[t]]) == 0.0;
   }
   if (vac && (PI_SRC != 2 || p.vac_zero)) {
 #pragma unroll
@@ -482,7 +494,8 @@ __device__ __forceinline__ R face_flux_stream(const GField& e, const FSet& u,
     }
     R p4[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) p4[t] = (R)(PI_SRC == 1 && ev[t] == 0.0 ? 0.0 : pcur[t]);
+    for (int t = 0; t < 4; ++t)
+      p4[t] = (R)((PI_SRC == 1 && ev[t] == 0.0) || (zmask && ezv[t] == 0.0) ? 0.0 : pcur[t]);
     const R pL = p4[1] + R(0.5) * mm_slope_r<R>(th, p4[0], p4[1], p4[2]);
     const R pR = p4[2] - R(0.5) * mm_slope_r<R>(th, p4[1], p4[2], p4[3]);
     if (DO_PI) {
@@ -1391,8 +1404,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int m = 0; m < NQ; ++m) p1[m] = (ut * pc[m] + p.h * R[4 + m]) * inv_uts;
       regulate<BK>(eos, p, e, p1);
+      // with vac_zero, pi~' is zero where e^n is: stage 2pi reads it masked there
+      if (!(KTMI_PI1_SPARSE && !BK && p.vac_zero && e == 0.0)) {
 #pragma unroll
-      for (int m = 0; m < NQ; ++m) stq<RT>(f.pi1[m], c, p1[m]);
+        for (int m = 0; m < NQ; ++m) stq<RT>(f.pi1[m], c, p1[m]);
+      }
       if constexpr (BK) Pi1 = p1[10];
     } else {
 #pragma unroll
@@ -1462,8 +1478,9 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>())
     const double e1 = f.e1[c];
     if (!(e1 == 0.0 && p.vac_zero) && e1 >= p.eps_cut) {
       double pc[NQ], S[NQ];
+      const bool zm = KTMI_PI1_SPARSE && !BK && p.vac_zero && f.e[c] == 0.0;  // pi~' unstored
 #pragma unroll
-      for (int m = 0; m < NQ; ++m) pc[m] = ldq<RT>(f.pi1[m], c);
+      for (int m = 0; m < NQ; ++m) pc[m] = zm ? 0.0 : ldq<RT>(f.pi1[m], c);
       pi_source<RT, L1, BK>(f.u1, f.u, f.u1, p, eos, g, q, e1, pc, S);
 #pragma unroll
       for (int m = 0; m < NQ; ++m) R[4 + m] = S[m];
@@ -1482,7 +1499,8 @@ __attribute__((amdgpu_waves_per_eu(pi_waves<RT, TX, TY, TZ, BK, BK ? 16 : 14>())
     double pc[NQ];
 #pragma unroll
     for (int m = 0; m < NQ; ++m) pc[m] = 0.0;
-    if (!vz || p.quiet_r[0] > 0) {
+    if ((!vz || p.quiet_r[0] > 0) &&
+        !(KTMI_PI1_SPARSE && !BK && p.vac_zero && f.e[c] == 0.0)) {  // else unstored, zero
 #pragma unroll
       for (int m = 0; m < NQ; ++m) pc[m] = ldq<RT>(f.pi1[m], c);
     }
